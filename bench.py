@@ -1,0 +1,221 @@
+#!/usr/bin/env python
+"""Benchmark of the fused filter -> PK-FK hash join -> hash group-by pipeline on
+one MI355X.
+
+Workload (default): 60,000,000 fact rows x 15,000,000 dim rows, fk drawn
+Zipf(0.8) over the dim keys, predicate day < 1200 (about 47% of rows), group by
+fk (about 8.4M groups), SUM(price_cents), SUM(qty), COUNT(*). Inputs are
+synthetic, seeded, and resident in device memory before timing starts.
+
+A step is one whole pipeline call: join-table init + build, the streaming
+filter/probe/aggregate kernel, and group finalization. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "input rows/s + % of HBM and VALU roofline, filter-join-groupby, 60M rows"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# Algorithmic bytes per fact row read by the streaming kernel, by grouping:
+# day 4 + fk 4 + price_cents 8 + qty 4 (+ flag 1 when flag is part of the key).
+FACT_BYTES = {"fk": 20, "dim_grp": 20, "prio_flag": 21}
+# Dim bytes per row read by the build: pk 4 (+ payload column).
+DIM_BYTES = {"fk": 4, "dim_grp": 8, "prio_flag": 5}
+OUT_BYTES_PER_GROUP = 32  # key, SUM(price), SUM(qty), COUNT as int64
+
+
+def workload(name: str):
+    import datagen
+
+    if name == "large":
+        return datagen.large(), "fact 60,000,000 x dim 15,000,000, fk ~ Zipf(0.8), day < 1200, group by fk"
+    if name == "medium":
+        return datagen.medium(), "fact 6,000,000 x dim 1,500,000, fk uniform, day < 1800, group by (prio, flag)"
+    return datagen.small(), "fact 60,000 x dim 15,000, fk uniform, day < 1800, group by (prio, flag)"
+
+
+def kernel_times(ctx) -> dict:
+    from paper_2608_13696_amd import rel
+
+    L = rel.lib()
+    names = (ctypes.c_char_p * 32)()
+    tot = (ctypes.c_double * 32)()
+    cnt = (ctypes.c_int64 * 32)()
+    n = ctypes.c_int(0)
+    ctx.check(L.rel_ctx_kernel_times(ctx.h, names, tot, cnt, 32, ctypes.byref(n)))
+    return {names[i].decode(): (tot[i], cnt[i]) for i in range(min(n.value, 32))}
+
+
+def traffic_for(kernel: str, workload_name: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if the
+    kernel source is unchanged since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload_name}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        if rec.get("src_sha") != source_sha():
+            return None
+        return rec.get("traffic_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2608_13696_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(sample_rows: int, wl: str) -> dict:
+    """The oracle, single-threaded, on a scaled-down draw of the same workload."""
+    import datagen
+    import oracle
+
+    if wl == "large":
+        m = max(sample_rows // 4, 1)
+        T = datagen.large(seed=3, n=sample_rows, m=m)
+        desc = f"same generator and query at {sample_rows:,} fact x {m:,} dim rows (1/{60_000_000 // sample_rows} scale)"
+    else:
+        T = workload(wl)[0]
+        desc = "the full workload"
+    times = []
+    t_end = time.perf_counter() + 10.0
+    while True:
+        t0 = time.perf_counter()
+        oracle.run_tables(T)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() > t_end or len(times) >= 5:
+            break
+    times.sort()
+    med = times[len(times) // 2]
+    return {"value": T.n / med, "unit": "rows/s", "cores": 1, "kind": "oracle",
+            "sample": f"{desc}; median of {len(times)} runs, {med:.2f} s each, generation excluded"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large", choices=["large", "medium", "small"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-rows", type=int, default=6_000_000)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md on sharding); "
+              "run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2608_13696_amd import rel
+
+    t0 = time.perf_counter()
+    T, desc = workload(args.workload)
+    log(f"generated {args.workload} workload in {time.perf_counter() - t0:.1f} s: {desc}")
+    dev = torch.device("cuda:0")
+
+    def d(a):
+        return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    fact = {"fk": d(T.fk), "price_cents": d(T.price_cents), "qty": d(T.qty), "day": d(T.day), "flag": d(T.flag)}
+    dim = {"pk": d(T.pk), "prio": d(T.prio), "grp": d(T.grp)}
+    torch.cuda.synchronize()
+    log("inputs resident on the device")
+
+    ctx = rel.Context(0)
+    # one synchronising call for the statistics (not timed)
+    out, st = ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, stats=True)
+    log(f"stats: {st}")
+    for _ in range(args.warmup):
+        ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, stats=False)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} done")
+
+    ctx.check(rel.lib().rel_ctx_enable_timing(ctx.h, 1))
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, stats=False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    kt = kernel_times(ctx)
+    ctx.check(rel.lib().rel_ctx_enable_timing(ctx.h, 0))
+    log(f"timed {args.steps} steps: {ms:.3f} ms/step")
+    for k, (tot, c) in sorted(kt.items(), key=lambda kv: -kv[1][0]):
+        log(f"  kernel {k:18s} {tot / max(c, 1):9.3f} ms avg over {c} launches")
+
+    n, m = T.n, T.m
+    rows_per_s = n / (ms / 1e3)
+    dom = max(kt.items(), key=lambda kv: kv[1][0])
+    dom_name, (dom_tot, dom_cnt) = dom
+    dom_ms = dom_tot / max(dom_cnt, 1)
+    per_row = FACT_BYTES[T.group_by]
+    if dom_name == "probe_agg":
+        alg_bytes = per_row * n
+        unit_desc = f"{per_row} B per fact row x {n:,} rows"
+    else:
+        alg_bytes = None
+        unit_desc = None
+    achieved = alg_bytes / (dom_ms / 1e3) / 1e9 if alg_bytes else None
+    pipe_bytes = per_row * n + DIM_BYTES[T.group_by] * m + OUT_BYTES_PER_GROUP * st["groups"]
+    pipe_gbs = pipe_bytes / (ms / 1e3) / 1e9
+
+    result = {
+        "metric": METRIC,
+        "value": rows_per_s,
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": desc, "fact_rows": n, "dim_rows": m, "day_lt": T.day_lt, "group_by": T.group_by,
+                   "rows_passed": st["rows_passed"], "join_matches": st["join_matches"], "groups": st["groups"],
+                   "join_placement": st["join_placement"], "group_placement": st["group_placement"]},
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": traffic_for(dom_name, args.workload), "algorithmic_bytes_per_launch": alg_bytes,
+                     "per_unit": unit_desc, "avg_launch_ms": dom_ms},
+        "pipeline": {"compulsory_bytes": pipe_bytes, "achieved_gbs": pipe_gbs, "hbm_frac": pipe_gbs / HBM_PEAK_GBS,
+                     "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in kt.items()}},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline(args.cpu_sample_rows, args.workload)
+    print(json.dumps(result), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

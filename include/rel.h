@@ -1,0 +1,215 @@
+/*
+ * rel.h -- C ABI of librel, an MI355X (gfx950) library for the relational hot
+ * path the paper profiles: a selection predicate, a primary-key/foreign-key
+ * hash join and a hash group-by aggregation over columnar, device-resident
+ * tables (the cuDF filter, join build/count/retrieve and shared-memory
+ * group-by kernels of Section 7 and Table 9).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Columns are plain device arrays, one per column (the Arrow-compatible
+ *   columnar layout of Section 2.3), non-nullable. Column pointers must be
+ *   16-byte aligned (a fresh torch/hipMalloc allocation always is); a
+ *   misaligned column is rejected with REL_INVALID_ARG.
+ * - All column and output buffers are owned by the caller; librel never frees
+ *   them. librel owns contexts, join tables, batches and planners and frees
+ *   them in the matching *_destroy call. A context keeps its scratch device
+ *   memory (hash tables, counters) between calls and frees it on destroy.
+ * - Every call is stream-ordered on the context's HIP stream (borrowed, e.g.
+ *   torch.cuda.current_stream().cuda_stream) and returns once the work is
+ *   enqueued, unless it says it synchronises. Counts are written to device
+ *   int64 words. Calls on one context must come from one host thread at a
+ *   time, and work enqueued on one context must not overlap in time with
+ *   other work that uses the same context's scratch memory.
+ * - Errors: the return value. Argument errors are found on the host before
+ *   any work is enqueued; out-parameters are written only on REL_OK.
+ *   Conditions found on the device (a full table, a duplicate build key) set
+ *   sticky bits in the context's device status word; rel_ctx_sync returns and
+ *   clears them.
+ * - Integer sums and counts are 64-bit and wrap modulo 2^64, so results do not
+ *   depend on the order in which atomic updates land.
+ */
+#ifndef REL_H_
+#define REL_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rel_status {
+  REL_OK = 0,
+  REL_INVALID_ARG = 1,   /* null pointer, negative size, misaligned column, bad enum */
+  REL_CAPACITY = 2,      /* an output buffer is smaller than a bound the host can prove */
+  REL_DUPLICATE_KEY = 3, /* a build key occurs twice (reported by synchronising calls) */
+  REL_HIP = 4,           /* HIP runtime error; rel_last_error has the message */
+  REL_OOM = 5,           /* device allocation failed */
+  REL_UNSUPPORTED = 6,   /* valid request this library does not implement */
+  REL_OVERFLOW = 7       /* a table sized from a plan overflowed and no fallback was allowed */
+} rel_status;
+
+/* Device status bits (rel_ctx_sync). */
+#define REL_DEV_OVERFLOW 0x1u  /* a hash table or output ran out of room; results incomplete */
+#define REL_DEV_DUPKEY 0x2u    /* a join build met an equal key twice */
+#define REL_DEV_BADARG 0x4u    /* a device-side argument check failed (e.g. negative payload) */
+
+typedef struct rel_ctx rel_ctx;
+
+/* Create a context on HIP device `device` whose work goes to `hip_stream`
+ * (a hipStream_t, borrowed; NULL means the null stream). */
+rel_status rel_ctx_create(int device, void* hip_stream, rel_ctx** out);
+rel_status rel_ctx_destroy(rel_ctx* ctx);
+/* Point the context at another borrowed stream. */
+rel_status rel_ctx_set_stream(rel_ctx* ctx, void* hip_stream);
+/* Synchronise the stream, then return and clear the device status bits
+ * (status_bits nullable). */
+rel_status rel_ctx_sync(rel_ctx* ctx, uint32_t* status_bits);
+const char* rel_status_string(rel_status s);
+/* Message of the last failing call on this context (empty if none). */
+const char* rel_last_error(const rel_ctx* ctx);
+
+/* Per-kernel timing (the measurement side of the paper's method: kernel time
+ * is the unit of analysis, Section 3.2). When enabled, every kernel librel
+ * launches on this context is bracketed by HIP events on the context's
+ * stream. Enabling (or disabling) synchronises and clears past records. */
+rel_status rel_ctx_enable_timing(rel_ctx* ctx, int enable);
+/* Synchronise, resolve the recorded events and report up to `max` kernels:
+ * names[i] (owned by the context, valid until timing is enabled again),
+ * total_ms[i] summed over launches[i] launches. *count = kernels recorded. */
+rel_status rel_ctx_kernel_times(rel_ctx* ctx, const char** names, double* total_ms, int64_t* launches, int max,
+                                int* count);
+
+/* ------------------------------------------------------------------------------------------------------------------
+ * Selection (the filter step: cuDF's compute_column_kernel + DeviceScanKernel
+ * pair of Table 9, whose interpreted expression evaluation Section 7 singles
+ * out; here the comparison is compiled, not interpreted).
+ */
+typedef enum rel_cmp { REL_LT = 0, REL_LE = 1, REL_GT = 2, REL_GE = 3, REL_EQ = 4, REL_NE = 5 } rel_cmp;
+
+/* out_idx[0..count) = the row ids i in [0, n) with col[i] <op> literal, in
+ * ascending order (a stable selection vector); *d_out_count (device) = count.
+ * col: int32[n]; out_idx: int32[out_cap], out_cap >= n (else REL_CAPACITY);
+ * n < 2^31. */
+rel_status rel_filter_compact(rel_ctx* ctx, const int32_t* col, int64_t n, rel_cmp op, int32_t literal,
+                              int32_t* out_idx, int64_t out_cap, int64_t* d_out_count);
+
+/* ------------------------------------------------------------------------------------------------------------------
+ * Hash join (cuDF's insert_if_n build and count/retrieve probe kernels of
+ * Section 7). Open addressing with linear probing over a power-of-two table of
+ * packed 64-bit slots {key, payload}.
+ */
+typedef enum rel_placement {
+  REL_PLACE_AUTO = 0,        /* library decides from sizes */
+  REL_PLACE_LDS = 1,         /* per-workgroup table in LDS (small tables only) */
+  REL_PLACE_GLOBAL = 2,      /* one table in device memory updated with device-scope atomics */
+  REL_PLACE_PARTITIONED = 3  /* radix-partitioned: per-partition tables in LDS */
+} rel_placement;
+
+typedef struct rel_table_opts {
+  int64_t capacity_hint; /* slots or expected distinct keys; 0 = size from the input (plain sizing) */
+  int32_t placement;     /* rel_placement */
+  float max_load;        /* target load factor in (0, 0.9]; 0 = 0.5 */
+} rel_table_opts;
+
+typedef struct rel_join_table rel_join_table;
+
+/* Build a join table over dim keys pk[0..m) with payload[j] (any int32) or,
+ * when payload is NULL, the dim row id j. A repeated key sets REL_DEV_DUPKEY.
+ * opts nullable (plain sizing: capacity = next power of two >= 2m). The table
+ * is owned by the caller through *out and must outlive probes that use it. */
+rel_status rel_join_build(rel_ctx* ctx, const int32_t* pk, const int32_t* payload, int64_t m,
+                          const rel_table_opts* opts, rel_join_table** out);
+rel_status rel_join_table_destroy(rel_join_table* table);
+
+/* Probe: for each position k in [0, n) with row = sel ? sel[k] : k, if
+ * fk[row] matches a build key, emit (row, payload). Pairs come out in no
+ * particular order; *d_out_count (device) = number of pairs (<= n, since pk is
+ * unique). out_cap >= n (else REL_CAPACITY). */
+rel_status rel_join_probe(rel_ctx* ctx, const rel_join_table* table, const int32_t* fk, const int32_t* sel, int64_t n,
+                          int32_t* out_fact_idx, int32_t* out_payload, int64_t out_cap, int64_t* d_out_count);
+
+/* ------------------------------------------------------------------------------------------------------------------
+ * Group-by (cuDF's single_pass_shmem_aggs_kernel of Section 7: per-workgroup
+ * aggregation in LDS, one device-memory update per group and workgroup).
+ */
+typedef struct rel_groups_out {
+  int64_t* key;       /* device int64[cap] */
+  int64_t* sum_price; /* device int64[cap] */
+  int64_t* sum_qty;   /* device int64[cap] */
+  int64_t* count;     /* device int64[cap] */
+  int64_t cap;
+  int64_t* d_n_groups; /* device int64: number of groups (may exceed cap: then REL_DEV_OVERFLOW) */
+} rel_groups_out;
+
+/* Groups of the rows row = sel ? sel[k] : k, k in [0, n): key[row],
+ * SUM(price[row]), SUM(qty[row]), COUNT(*). Output order unspecified. opts
+ * nullable (plain sizing: capacity for min(n, 2^30) distinct keys). Every int64
+ * key is allowed. */
+rel_status rel_groupby_agg(rel_ctx* ctx, const int64_t* key, const int64_t* price, const int32_t* qty,
+                           const int32_t* sel, int64_t n, const rel_table_opts* opts, rel_groups_out* out);
+
+/* ------------------------------------------------------------------------------------------------------------------
+ * The fused pipeline:
+ *   SELECT g, SUM(price_cents), SUM(qty), COUNT(*) FROM fact JOIN dim ON fk = pk
+ *   WHERE day < day_lt GROUP BY g
+ * with g = (dim.prio, fact.flag) packed as prio * 256 + (uint8)flag, or
+ * fact.fk, or dim.grp.
+ */
+typedef struct rel_fact {
+  const int32_t* fk;
+  const int64_t* price_cents;
+  const int32_t* qty;
+  const int32_t* day;
+  const int8_t* flag; /* needed for REL_GROUP_PRIO_FLAG only */
+  int64_t n;
+} rel_fact;
+
+typedef struct rel_dim {
+  const int32_t* pk; /* unique */
+  const int8_t* prio; /* needed for REL_GROUP_PRIO_FLAG only */
+  const int32_t* grp; /* needed for REL_GROUP_DIM_GRP only */
+  int64_t m;
+} rel_dim;
+
+typedef enum rel_group_by { REL_GROUP_PRIO_FLAG = 0, REL_GROUP_FK = 1, REL_GROUP_DIM_GRP = 2 } rel_group_by;
+
+typedef struct rel_query {
+  int32_t day_lt;   /* strict predicate day < day_lt */
+  int32_t group_by; /* rel_group_by */
+} rel_query;
+
+/* Sizing and placement decided before the build (by the caller or by the
+ * learned planner). Zero fields mean "plain sizing". */
+typedef struct rel_plan {
+  int64_t group_capacity;  /* expected distinct groups (0 = upper bound from the input) */
+  int32_t group_placement; /* rel_placement */
+  int32_t join_placement;  /* rel_placement */
+  int32_t allow_fallback;  /* on overflow: 1 = rerun with plain sizing (synchronises), 0 = REL_OVERFLOW */
+  int32_t reserved;
+} rel_plan;
+
+typedef struct rel_stats {
+  int64_t rows_in;
+  int64_t rows_passed;
+  int64_t join_matches;
+  int64_t groups;
+  int64_t join_capacity;
+  int64_t group_capacity;
+  int32_t join_placement;
+  int32_t group_placement;
+  int32_t overflowed; /* the planned tables overflowed */
+  int32_t fell_back;  /* the plain pipeline was rerun */
+} rel_stats;
+
+/* Run the fused pipeline. plan nullable (plain). stats nullable; when given,
+ * the call synchronises and fills it. Returns REL_DUPLICATE_KEY / REL_OVERFLOW
+ * only when it synchronises (stats given or fallback allowed). */
+rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, const rel_query* q,
+                               const rel_plan* plan, rel_groups_out* out, rel_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REL_H_ */

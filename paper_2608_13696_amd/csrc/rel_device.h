@@ -1,0 +1,203 @@
+// Device-side building blocks shared by librel's kernels: hashing, wave64
+// ballot/prefix helpers, the packed join-table slot and the group-table slot.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rel {
+
+constexpr int kWave = 64;
+constexpr uint64_t kJoinEmpty = ~0ull;                // packed join slot: key in bits 0..31, payload in 32..63
+constexpr int64_t kGroupEmpty = (int64_t)0x8000000000000000ull;  // group-table key sentinel (INT64_MIN)
+
+constexpr uint32_t kDevOverflow = 0x1u;
+constexpr uint32_t kDevDupKey = 0x2u;
+constexpr uint32_t kDevBadArg = 0x4u;
+
+// Multiplicative (Fibonacci) hash of a 32-bit key: the top `bits` bits of
+// key * floor(2^32 / golden ratio). Only the high product bits are used, so
+// the lower bits of the key reach every output bit.
+__device__ __forceinline__ uint32_t hash32(int32_t key, uint32_t shift) {
+  return ((uint32_t)key * 2654435769u) >> shift;
+}
+
+// 64-bit keys: fold the high word in, then the 32-bit hash.
+__device__ __forceinline__ uint32_t hash64(int64_t key, uint32_t shift) {
+  const uint64_t k = (uint64_t)key;
+  const uint32_t x = (uint32_t)k ^ ((uint32_t)(k >> 32) * 0x85EBCA6Bu);
+  return (x * 2654435769u) >> shift;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// Number of set bits of a wave mask below this lane.
+__device__ __forceinline__ uint32_t mask_rank(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ void set_status(uint32_t* status, uint32_t bits) {
+  __hip_atomic_fetch_or(status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+__device__ __forceinline__ void dev_add(T* p, T v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+__device__ __forceinline__ T dev_add_ret(T* p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+__device__ __forceinline__ T dev_cas(T* p, T expected, T desired) {
+  __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return expected;  // the value found
+}
+
+// ---- join table -------------------------------------------------------------------------------------------------------
+
+// Slots [0, capacity) hold packed {key, payload}; an in-table key is never
+// 0xFFFFFFFF, so the all-ones word is free to mean "empty". The key -1 lives in
+// the extra slot [capacity], stored as the zero-extended payload.
+struct JoinView {
+  const uint64_t* slots;  // capacity + 1 words
+  uint32_t mask;          // capacity - 1
+  uint32_t shift;         // 32 - log2(capacity)
+};
+
+// Linear-probing lookup. The table always keeps at least one empty slot, so the
+// walk ends; the step bound only guards a corrupted table.
+__device__ __forceinline__ bool join_lookup(const JoinView& t, int32_t key, int32_t* payload) {
+  if (key == -1) {
+    const uint64_t s = t.slots[(size_t)t.mask + 1];
+    *payload = (int32_t)(uint32_t)s;
+    return s != kJoinEmpty;
+  }
+  uint32_t h = hash32(key, t.shift);
+  for (uint32_t step = 0; step <= t.mask; ++step) {
+    const uint64_t s = t.slots[h];
+    if (s == kJoinEmpty) return false;
+    if ((uint32_t)s == (uint32_t)key) {
+      *payload = (int32_t)(s >> 32);
+      return true;
+    }
+    h = (h + 1) & t.mask;
+  }
+  return false;
+}
+
+// ---- group table ------------------------------------------------------------------------------------------------------
+
+// One group: key and the three running aggregates. A slot is occupied exactly
+// when count != 0 (whoever claims a key adds its count right away). The slot at
+// index `capacity` is reserved for the key INT64_MIN, the empty sentinel.
+struct alignas(32) GroupSlot {
+  int64_t key;
+  uint64_t sum_price;
+  uint64_t sum_qty;
+  uint64_t count;
+};
+
+struct GroupView {
+  GroupSlot* slots;  // capacity + 1 slots
+  uint32_t mask;
+  uint32_t shift;
+  uint32_t* status;
+  uint32_t max_probe;  // longest probe walk before the table counts as overflowed
+};
+
+// Find or claim the slot of `key` in a device-memory table; -1 when full.
+__device__ __forceinline__ int64_t group_slot(const GroupView& t, int64_t key) {
+  if (key == kGroupEmpty) return (int64_t)t.mask + 1;
+  uint32_t h = hash64(key, t.shift);
+  for (uint32_t step = 0; step < t.max_probe; ++step) {
+    const int64_t k = t.slots[h].key;  // hint; the CAS below decides
+    if (k == key) return h;
+    if (k == kGroupEmpty) {
+      const int64_t old = dev_cas<int64_t>(&t.slots[h].key, kGroupEmpty, key);
+      if (old == kGroupEmpty || old == key) return h;
+    }
+    h = (h + 1) & t.mask;
+  }
+  return -1;
+}
+
+__device__ __forceinline__ void group_add(const GroupView& t, int64_t key, uint64_t sp, uint64_t sq, uint64_t cnt) {
+  const int64_t s = group_slot(t, key);
+  if (s < 0) {
+    set_status(t.status, kDevOverflow);
+    return;
+  }
+  GroupSlot* g = &t.slots[s];
+  dev_add<uint64_t>(&g->sum_price, sp);
+  dev_add<uint64_t>(&g->sum_qty, sq);
+  dev_add<uint64_t>(&g->count, cnt);
+}
+
+// Per-dim-row aggregates of the groupjoin (group key == join key).
+struct alignas(8) RowAgg {
+  uint64_t sum_price;
+  uint64_t sum_qty;
+  uint64_t count;
+};
+
+// ---- LDS group table ------------------------------------------------------------------------------------------------
+
+template <int SLOTS>
+struct LdsGroups {
+  int64_t key[SLOTS];
+  uint64_t sum_price[SLOTS];
+  uint64_t sum_qty[SLOTS];
+  uint64_t count[SLOTS];
+
+  __device__ void init(int tid, int nthreads) {
+    for (int s = tid; s < SLOTS; s += nthreads) {
+      key[s] = kGroupEmpty;
+      sum_price[s] = 0;
+      sum_qty[s] = 0;
+      count[s] = 0;
+    }
+  }
+
+  // Slot of key, or -1 when the probe budget is spent (caller goes to device memory).
+  __device__ __forceinline__ int find(int64_t k, int max_probe) {
+    uint32_t h = hash64(k, 32 - __builtin_ctz(SLOTS)) & (SLOTS - 1);
+    for (int step = 0; step < max_probe; ++step) {
+      const int64_t cur = key[h];
+      if (cur == k) return (int)h;
+      if (cur == kGroupEmpty) {
+        const int64_t old = atomicCAS((unsigned long long*)&key[h], (unsigned long long)kGroupEmpty,
+                                      (unsigned long long)k);
+        if ((int64_t)old == kGroupEmpty || (int64_t)old == k) return (int)h;
+      }
+      h = (h + 1) & (SLOTS - 1);
+    }
+    return -1;
+  }
+
+  __device__ __forceinline__ void add(int s, uint64_t sp, uint64_t sq, uint64_t cnt) {
+    atomicAdd((unsigned long long*)&sum_price[s], (unsigned long long)sp);
+    atomicAdd((unsigned long long*)&sum_qty[s], (unsigned long long)sq);
+    atomicAdd((unsigned long long*)&count[s], (unsigned long long)cnt);
+  }
+
+  // Push every occupied LDS slot into the device-memory table.
+  __device__ void flush(const GroupView& g, int tid, int nthreads) {
+    for (int s = tid; s < SLOTS; s += nthreads)
+      if (count[s] != 0) group_add(g, key[s], sum_price[s], sum_qty[s], count[s]);
+  }
+};
+
+}  // namespace rel

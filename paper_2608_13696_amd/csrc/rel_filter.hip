@@ -1,0 +1,150 @@
+// Stable stream compaction (the filter + prefix-sum pair of Table 9) in one
+// pass: single-pass prefix scan with decoupled look-back (Merrill and
+// Garland, 2016).
+//
+// Tiles are handed out by an atomic ticket, not by blockIdx, so every tile a
+// workgroup waits on belongs to a workgroup that is already running and that
+// publishes its own count before it looks back: the wait always ends.
+#include "rel_device.h"
+#include "rel_host.h"
+
+namespace {
+
+using namespace rel;
+
+constexpr int kBlock = 256;
+constexpr int kIPT = 16;  // rows per thread: four 16-byte loads
+constexpr int64_t kTile = (int64_t)kBlock * kIPT;
+constexpr uint64_t kFlagAgg = 1ull << 62;   // tile's own count is published
+constexpr uint64_t kFlagIncl = 2ull << 62;  // tile's inclusive prefix is published
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+
+template <int OP>
+__device__ __forceinline__ bool pred(int32_t v, int32_t lit) {
+  if (OP == REL_LT) return v < lit;
+  if (OP == REL_LE) return v <= lit;
+  if (OP == REL_GT) return v > lit;
+  if (OP == REL_GE) return v >= lit;
+  if (OP == REL_EQ) return v == lit;
+  return v != lit;
+}
+
+template <int OP>
+__global__ __launch_bounds__(kBlock) void k_filter_compact(const int32_t* __restrict__ col, int64_t n, int32_t lit,
+                                                           int32_t* __restrict__ out, uint64_t* __restrict__ state,
+                                                           int64_t* __restrict__ ticket, int64_t* __restrict__ d_count,
+                                                           int64_t ntiles) {
+  __shared__ int64_t s_tile;
+  __shared__ int64_t s_excl;
+  __shared__ uint32_t s_wave[kBlock / kWave];
+  if (threadIdx.x == 0) s_tile = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)ticket, 1ull);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t r0 = tile * kTile + (int64_t)threadIdx.x * kIPT;
+
+  uint32_t bits = 0;
+  if (r0 + kIPT <= n) {
+#pragma unroll
+    for (int v = 0; v < kIPT / 4; ++v) {
+      const int4 x = *reinterpret_cast<const int4*>(col + r0 + 4 * v);
+      bits |= (uint32_t)pred<OP>(x.x, lit) << (4 * v);
+      bits |= (uint32_t)pred<OP>(x.y, lit) << (4 * v + 1);
+      bits |= (uint32_t)pred<OP>(x.z, lit) << (4 * v + 2);
+      bits |= (uint32_t)pred<OP>(x.w, lit) << (4 * v + 3);
+    }
+  } else {
+    for (int k = 0; k < kIPT; ++k)
+      if (r0 + k < n) bits |= (uint32_t)pred<OP>(col[r0 + k], lit) << k;
+  }
+  const uint32_t c = __popc(bits);
+
+  // Exclusive scan of c over the workgroup: wave scan, then wave totals.
+  const uint32_t lane = lane_id();
+  const uint32_t wave = threadIdx.x / kWave;
+  uint32_t incl = c;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o, kWave);
+    if (lane >= (uint32_t)o) incl += t;
+  }
+  if (lane == kWave - 1) s_wave[wave] = incl;
+  __syncthreads();
+  uint32_t wave_off = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / kWave; ++w) {
+    const uint32_t t = s_wave[w];
+    wave_off += (uint32_t)w < wave ? t : 0u;
+    total += t;
+  }
+  const uint32_t my_off = wave_off + incl - c;
+
+  // Publish, then look back.
+  if (threadIdx.x == 0) {
+    if (tile == 0) {
+      __hip_atomic_store(&state[0], kFlagIncl | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_excl = 0;
+    } else {
+      __hip_atomic_store(&state[tile], kFlagAgg | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      uint64_t acc = 0;
+      int64_t p = tile - 1;
+      for (;;) {
+        const uint64_t st = __hip_atomic_load(&state[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t flag = st & ~kValMask;
+        if (flag == 0) {
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        acc += st & kValMask;
+        if (flag == kFlagIncl) break;
+        --p;  // p > 0 here: tile 0 only ever publishes an inclusive prefix
+      }
+      __hip_atomic_store(&state[tile], kFlagIncl | (acc + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_excl = (int64_t)acc;
+    }
+    if (tile == ntiles - 1) *d_count = s_excl + total;
+  }
+  __syncthreads();
+  int64_t o = s_excl + my_off;
+  for (int k = 0; k < kIPT; ++k)
+    if (bits & (1u << k)) out[o++] = (int32_t)(r0 + k);
+}
+
+template <int OP>
+void launch(rel_ctx* ctx, const int32_t* col, int64_t n, int32_t lit, int32_t* out, uint64_t* state, int64_t* ticket,
+            int64_t* d_count, int64_t ntiles) {
+  hipLaunchKernelGGL(k_filter_compact<OP>, dim3((unsigned)ntiles), dim3(kBlock), 0, ctx->stream, col, n, lit, out, state,
+                     ticket, d_count, ntiles);
+}
+
+}  // namespace
+
+extern "C" rel_status rel_filter_compact(rel_ctx* ctx, const int32_t* col, int64_t n, rel_cmp op, int32_t literal,
+                                         int32_t* out_idx, int64_t out_cap, int64_t* d_out_count) {
+  if (!ctx || n < 0 || !d_out_count || (n > 0 && (!col || !out_idx)) || op < REL_LT || op > REL_NE)
+    return relh::fail(ctx, REL_INVALID_ARG, "rel_filter_compact: bad argument");
+  if (col && !relh::aligned16(col)) return relh::fail(ctx, REL_INVALID_ARG, "rel_filter_compact: column not 16-byte aligned");
+  if (n >= (1ll << 31)) return relh::fail(ctx, REL_UNSUPPORTED, "rel_filter_compact: n >= 2^31");
+  if (out_cap < n) return relh::fail(ctx, REL_CAPACITY, "rel_filter_compact: out_cap < n");
+  rel_status s = relh::ensure_counters(ctx);
+  if (s != REL_OK) return s;
+  if (n == 0) return relh::fill_u64(ctx, d_out_count, 1, 0);
+  const int64_t ntiles = (n + kTile - 1) / kTile;
+  void* st;
+  s = relh::scratch(ctx, SCR_SCAN_STATE, (size_t)ntiles * 8, &st);
+  if (s != REL_OK) return s;
+  int64_t* ticket = relh::counters(ctx) + CNT_TICKET;
+  if ((s = relh::fill_u64(ctx, st, (size_t)ntiles, 0)) != REL_OK) return s;
+  if ((s = relh::fill_u64(ctx, ticket, 1, 0)) != REL_OK) return s;
+  uint64_t* state = (uint64_t*)st;
+  relh::KernelTimer kt(ctx, "filter_compact");
+  switch (op) {
+    case REL_LT: launch<REL_LT>(ctx, col, n, literal, out_idx, state, ticket, d_out_count, ntiles); break;
+    case REL_LE: launch<REL_LE>(ctx, col, n, literal, out_idx, state, ticket, d_out_count, ntiles); break;
+    case REL_GT: launch<REL_GT>(ctx, col, n, literal, out_idx, state, ticket, d_out_count, ntiles); break;
+    case REL_GE: launch<REL_GE>(ctx, col, n, literal, out_idx, state, ticket, d_out_count, ntiles); break;
+    case REL_EQ: launch<REL_EQ>(ctx, col, n, literal, out_idx, state, ticket, d_out_count, ntiles); break;
+    case REL_NE: launch<REL_NE>(ctx, col, n, literal, out_idx, state, ticket, d_out_count, ntiles); break;
+  }
+  REL_LAUNCH_CHECK(ctx, "filter_compact");
+  return REL_OK;
+}

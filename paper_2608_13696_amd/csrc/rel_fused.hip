@@ -1,0 +1,455 @@
+// The fused filter -> probe -> aggregate pipeline (build, one streaming
+// kernel, finalize) and the standalone hash group-by.
+//
+// The streaming kernel reads the fact columns once with 16-byte vector loads,
+// several rows per thread (the paper's Recommendation 1: overlap latency with
+// instruction-level parallelism), evaluates the compiled predicate, probes the
+// join table and updates the group state:
+//   * few groups: a per-workgroup LDS table (the shared-memory aggregation of
+//     Section 7), flushed to device memory once per workgroup;
+//   * many groups: a device-memory table updated with device-scope atomics;
+//   * group key == join key (GROUP BY fk): a groupjoin, aggregating straight
+//     into per-dim-row accumulators so no second hash table exists.
+#include "rel_device.h"
+#include "rel_host.h"
+#include "rel_ops.h"
+
+namespace {
+
+using namespace rel;
+
+enum Mode : int { M_PRIO_FLAG = REL_GROUP_PRIO_FLAG, M_FK = REL_GROUP_FK, M_DIM_GRP = REL_GROUP_DIM_GRP };
+enum GPlace : int { G_LDS = 0, G_GLOBAL = 1, G_ROWAGG = 2 };
+
+constexpr int kBlock = 256;
+constexpr int kIPT = 4;  // rows per thread per tile: one 16-byte load per int32 column
+constexpr int kLdsSlots = 1024;
+constexpr int kLdsProbe = 32;
+// A table sized from a prediction gives up after this many probe steps (at a
+// load of 0.5 linear probing practically never walks that far), so that an
+// undersized table reports overflow instead of degrading to a linear scan.
+constexpr uint32_t kPlannedProbe = 256;
+
+struct FusedArgs {
+  const int32_t* fk;
+  const int64_t* price;
+  const int32_t* qty;
+  const int32_t* day;
+  const int8_t* flag;
+  int64_t n;
+  int32_t day_lt;
+  JoinView join;
+  GroupView groups;
+  RowAgg* row_agg;
+  int64_t* counters;  // [0] rows passed, [1] join matches
+};
+
+template <int MODE>
+__device__ __forceinline__ int64_t group_key(int32_t payload, int32_t fk, int8_t flag) {
+  if (MODE == M_PRIO_FLAG) return (int64_t)payload * 256 + (int64_t)(uint8_t)flag;
+  if (MODE == M_DIM_GRP) return (int64_t)payload;
+  return (int64_t)fk;
+}
+
+template <int MODE, int GP>
+__global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a) {
+  __shared__ LdsGroups<GP == G_LDS ? kLdsSlots : 1> lds;
+  if (GP == G_LDS) {
+    lds.init(threadIdx.x, kBlock);
+    __syncthreads();
+  }
+  uint64_t passed = 0, matched = 0;
+  constexpr int64_t tile_rows = (int64_t)kBlock * kIPT;
+  const int64_t ntiles = (a.n + tile_rows - 1) / tile_rows;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t r0 = tile * tile_rows + (int64_t)threadIdx.x * kIPT;
+    int32_t d[kIPT], f[kIPT], q[kIPT];
+    int64_t p[kIPT];
+    int8_t fl[kIPT];
+    int nv;
+    if (r0 + kIPT <= a.n) {
+      nv = kIPT;
+      const int4 dv = *reinterpret_cast<const int4*>(a.day + r0);
+      const int4 fv = *reinterpret_cast<const int4*>(a.fk + r0);
+      const int4 qv = *reinterpret_cast<const int4*>(a.qty + r0);
+      const longlong2 p01 = *reinterpret_cast<const longlong2*>(a.price + r0);
+      const longlong2 p23 = *reinterpret_cast<const longlong2*>(a.price + r0 + 2);
+      d[0] = dv.x; d[1] = dv.y; d[2] = dv.z; d[3] = dv.w;
+      f[0] = fv.x; f[1] = fv.y; f[2] = fv.z; f[3] = fv.w;
+      q[0] = qv.x; q[1] = qv.y; q[2] = qv.z; q[3] = qv.w;
+      p[0] = p01.x; p[1] = p01.y; p[2] = p23.x; p[3] = p23.y;
+      if (MODE == M_PRIO_FLAG) {
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(a.flag + r0);
+#pragma unroll
+        for (int k = 0; k < kIPT; ++k) fl[k] = (int8_t)(w >> (8 * k));
+      } else {
+#pragma unroll
+        for (int k = 0; k < kIPT; ++k) fl[k] = 0;
+      }
+    } else {
+      nv = r0 < a.n ? (int)(a.n - r0) : 0;
+#pragma unroll
+      for (int k = 0; k < kIPT; ++k) {
+        const bool ok = k < nv;
+        d[k] = ok ? a.day[r0 + k] : 0;
+        f[k] = ok ? a.fk[r0 + k] : 0;
+        q[k] = ok ? a.qty[r0 + k] : 0;
+        p[k] = ok ? a.price[r0 + k] : 0;
+        fl[k] = (ok && MODE == M_PRIO_FLAG) ? a.flag[r0 + k] : 0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kIPT; ++k) {
+      if (k >= nv || !(d[k] < a.day_lt)) continue;
+      ++passed;
+      int32_t pl;
+      if (!join_lookup(a.join, f[k], &pl)) continue;
+      ++matched;
+      const uint64_t sp = (uint64_t)p[k], sq = (uint64_t)(int64_t)q[k];
+      if (GP == G_ROWAGG) {
+        RowAgg* r = &a.row_agg[pl];
+        dev_add<uint64_t>(&r->sum_price, sp);
+        dev_add<uint64_t>(&r->sum_qty, sq);
+        dev_add<uint64_t>(&r->count, 1ull);
+      } else {
+        const int64_t key = group_key<MODE>(pl, f[k], fl[k]);
+        int s = -1;
+        if (GP == G_LDS) s = lds.find(key, kLdsProbe);
+        if (s >= 0) lds.add(s, sp, sq, 1ull);
+        else group_add(a.groups, key, sp, sq, 1ull);
+      }
+    }
+  }
+  if (GP == G_LDS) {
+    __syncthreads();
+    lds.flush(a.groups, threadIdx.x, kBlock);
+  }
+  passed = wave_sum(passed);
+  matched = wave_sum(matched);
+  if (lane_id() == 0) {
+    if (passed) dev_add<unsigned long long>((unsigned long long*)&a.counters[0], passed);
+    if (matched) dev_add<unsigned long long>((unsigned long long*)&a.counters[1], matched);
+  }
+}
+
+// Standalone group-by over key[row], row = sel ? sel[k] : k.
+template <int GP>
+__global__ __launch_bounds__(kBlock) void k_groupby(const int64_t* __restrict__ key, const int64_t* __restrict__ price,
+                                                    const int32_t* __restrict__ qty, const int32_t* __restrict__ sel,
+                                                    int64_t n, GroupView g) {
+  __shared__ LdsGroups<GP == G_LDS ? kLdsSlots : 1> lds;
+  if (GP == G_LDS) {
+    lds.init(threadIdx.x, kBlock);
+    __syncthreads();
+  }
+  int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (; k < n; k += stride) {
+    const int64_t row = sel ? (int64_t)sel[k] : k;
+    const int64_t kv = key[row];
+    const uint64_t sp = (uint64_t)price[row], sq = (uint64_t)(int64_t)qty[row];
+    int s = -1;
+    if (GP == G_LDS && kv != kGroupEmpty) s = lds.find(kv, kLdsProbe);
+    if (s >= 0) lds.add(s, sp, sq, 1ull);
+    else group_add(g, kv, sp, sq, 1ull);
+  }
+  if (GP == G_LDS) {
+    __syncthreads();
+    lds.flush(g, threadIdx.x, kBlock);
+  }
+}
+
+__global__ void k_init_groups(GroupSlot* __restrict__ slots, int64_t nslots) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < nslots; i += stride) {
+    GroupSlot s;
+    s.key = kGroupEmpty;
+    s.sum_price = 0;
+    s.sum_qty = 0;
+    s.count = 0;
+    slots[i] = s;
+  }
+}
+
+struct OutArgs {
+  int64_t* key;
+  int64_t* sum_price;
+  int64_t* sum_qty;
+  int64_t* count;
+  int64_t cap;
+  int64_t* d_n;
+  uint32_t* status;
+};
+
+// Wave-cooperative output append: one atomic per wave reserves room for the
+// wave's occupied slots; ranks come from the ballot.
+__device__ __forceinline__ void emit(const OutArgs& o, bool occ, int64_t key, uint64_t sp, uint64_t sq, uint64_t cnt) {
+  const uint64_t b = wave_ballot(occ);
+  if (b == 0) return;
+  int64_t base = 0;
+  if (lane_id() == 0) base = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)o.d_n, (unsigned long long)__popcll(b));
+  base = __shfl(base, 0, kWave);
+  if (!occ) return;
+  const int64_t i = base + mask_rank(b);
+  if (i < o.cap) {
+    o.key[i] = key;
+    o.sum_price[i] = (int64_t)sp;
+    o.sum_qty[i] = (int64_t)sq;
+    o.count[i] = (int64_t)cnt;
+  } else {
+    set_status(o.status, kDevOverflow);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize_groups(const GroupSlot* __restrict__ slots, int64_t nslots, int64_t side,
+                                                            OutArgs o) {
+  const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+  const int64_t n_waves = ((int64_t)gridDim.x * kBlock) / kWave;
+  for (int64_t base = wave * kWave; base < nslots; base += n_waves * kWave) {
+    const int64_t s = base + lane_id();
+    bool occ = false;
+    GroupSlot g{};
+    if (s < nslots) {
+      g = slots[s];
+      occ = g.count != 0;
+      if (s == side) g.key = kGroupEmpty;
+    }
+    emit(o, occ, g.key, g.sum_price, g.sum_qty, g.count);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize_rowagg(const RowAgg* __restrict__ agg, const int32_t* __restrict__ pk,
+                                                            int64_t m, OutArgs o) {
+  const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+  const int64_t n_waves = ((int64_t)gridDim.x * kBlock) / kWave;
+  for (int64_t base = wave * kWave; base < m; base += n_waves * kWave) {
+    const int64_t j = base + lane_id();
+    bool occ = false;
+    RowAgg r{};
+    int64_t key = 0;
+    if (j < m) {
+      r = agg[j];
+      occ = r.count != 0;
+      if (occ) key = pk[j];
+    }
+    emit(o, occ, key, r.sum_price, r.sum_qty, r.count);
+  }
+}
+
+rel_status init_groups(rel_ctx* ctx, GroupSlot* slots, int64_t nslots) {
+  const unsigned grid = relh::grid_for(ctx, nslots, 256 * 4, 4);
+  relh::KernelTimer kt(ctx, "group_table_init");
+  hipLaunchKernelGGL(k_init_groups, dim3(grid), dim3(256), 0, ctx->stream, slots, nslots);
+  REL_LAUNCH_CHECK(ctx, "init_groups");
+  return REL_OK;
+}
+
+bool out_ok(const rel_groups_out* out) {
+  return out && out->key && out->sum_price && out->sum_qty && out->count && out->d_n_groups && out->cap >= 0;
+}
+
+OutArgs out_args(rel_ctx* ctx, const rel_groups_out* out) {
+  return OutArgs{out->key, out->sum_price, out->sum_qty, out->count, out->cap, out->d_n_groups, ctx->d_status};
+}
+
+// Group-table capacity (power of two) for `expected` distinct keys at load `load`.
+uint32_t group_log2cap(int64_t expected, double load) {
+  if (expected < 1) expected = 1;
+  uint32_t l = relh::log2_ceil((uint64_t)((double)expected / load) + 1);
+  return l < 4 ? 4 : l;
+}
+
+template <int MODE>
+rel_status launch_fused(rel_ctx* ctx, int gp, const FusedArgs& a, unsigned grid) {
+  relh::KernelTimer kt(ctx, "probe_agg");
+  if (gp == G_LDS)
+    hipLaunchKernelGGL((k_fused<MODE, G_LDS>), dim3(grid), dim3(kBlock), 0, ctx->stream, a);
+  else if (gp == G_GLOBAL)
+    hipLaunchKernelGGL((k_fused<MODE, G_GLOBAL>), dim3(grid), dim3(kBlock), 0, ctx->stream, a);
+  else
+    hipLaunchKernelGGL((k_fused<MODE, G_ROWAGG>), dim3(grid), dim3(kBlock), 0, ctx->stream, a);
+  REL_LAUNCH_CHECK(ctx, "fused");
+  return REL_OK;
+}
+
+#define TRY(x)                      \
+  do {                              \
+    rel_status s_ = (x);            \
+    if (s_ != REL_OK) return s_;    \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+rel_status rel_groupby_agg(rel_ctx* ctx, const int64_t* key, const int64_t* price, const int32_t* qty,
+                           const int32_t* sel, int64_t n, const rel_table_opts* opts, rel_groups_out* out) {
+  if (!ctx || n < 0 || !out_ok(out) || (n > 0 && (!key || !price || !qty)))
+    return relh::fail(ctx, REL_INVALID_ARG, "rel_groupby_agg: bad argument");
+  if (n >= (1ll << 31)) return relh::fail(ctx, REL_UNSUPPORTED, "rel_groupby_agg: n >= 2^31");
+  const double load = (opts && opts->max_load > 0.f) ? (opts->max_load > 0.9f ? 0.9 : opts->max_load) : 0.5;
+  int64_t expected = (opts && opts->capacity_hint > 0) ? opts->capacity_hint : (n < (1ll << 30) ? n : (1ll << 30));
+  int placement = opts ? opts->placement : REL_PLACE_AUTO;
+  if (placement == REL_PLACE_PARTITIONED) return relh::fail(ctx, REL_UNSUPPORTED, "rel_groupby_agg: partitioned placement");
+  if (placement == REL_PLACE_AUTO) placement = expected <= kLdsSlots / 2 ? REL_PLACE_LDS : REL_PLACE_GLOBAL;
+  const uint32_t l = group_log2cap(expected, load);
+  if (l > 31) return relh::fail(ctx, REL_UNSUPPORTED, "rel_groupby_agg: capacity above 2^31");
+  const int64_t nslots = (1ll << l) + 1;
+  void* tbl;
+  TRY(relh::scratch(ctx, SCR_GROUP_TABLE, (size_t)nslots * sizeof(GroupSlot), &tbl));
+  TRY(init_groups(ctx, (GroupSlot*)tbl, nslots));
+  const uint32_t probe = (opts && opts->capacity_hint > 0) ? kPlannedProbe : (uint32_t)(1ull << l);
+  GroupView g{(GroupSlot*)tbl, (uint32_t)((1ull << l) - 1), 32u - l, ctx->d_status, probe};
+  if (n > 0) {
+    const unsigned grid = relh::grid_for(ctx, n, kBlock * 4, placement == REL_PLACE_LDS ? 2 : 8);
+    relh::KernelTimer kt(ctx, "groupby");
+    if (placement == REL_PLACE_LDS)
+      hipLaunchKernelGGL(k_groupby<G_LDS>, dim3(grid), dim3(kBlock), 0, ctx->stream, key, price, qty, sel, n, g);
+    else
+      hipLaunchKernelGGL(k_groupby<G_GLOBAL>, dim3(grid), dim3(kBlock), 0, ctx->stream, key, price, qty, sel, n, g);
+    REL_LAUNCH_CHECK(ctx, "groupby");
+  }
+  TRY(relh::fill_u64(ctx, out->d_n_groups, 1, 0));
+  const unsigned fgrid = relh::grid_for(ctx, nslots, kBlock, 8);
+  relh::KernelTimer kt(ctx, "finalize");
+  hipLaunchKernelGGL(k_finalize_groups, dim3(fgrid), dim3(kBlock), 0, ctx->stream, (const GroupSlot*)tbl, nslots,
+                     nslots - 1, out_args(ctx, out));
+  REL_LAUNCH_CHECK(ctx, "finalize_groups");
+  return REL_OK;
+}
+
+rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, const rel_query* q,
+                               const rel_plan* plan, rel_groups_out* out, rel_stats* stats) {
+  if (!ctx || !fact || !dim || !q || !out_ok(out)) return relh::fail(ctx, REL_INVALID_ARG, "rel_filter_join_agg: null argument");
+  const int64_t n = fact->n, m = dim->m;
+  const int gb = q->group_by;
+  if (n < 0 || m < 0 || gb < REL_GROUP_PRIO_FLAG || gb > REL_GROUP_DIM_GRP)
+    return relh::fail(ctx, REL_INVALID_ARG, "rel_filter_join_agg: bad size or group_by");
+  if (n > 0 && (!fact->fk || !fact->price_cents || !fact->qty || !fact->day || (gb == REL_GROUP_PRIO_FLAG && !fact->flag)))
+    return relh::fail(ctx, REL_INVALID_ARG, "rel_filter_join_agg: missing fact column");
+  if (m > 0 && (!dim->pk || (gb == REL_GROUP_PRIO_FLAG && !dim->prio) || (gb == REL_GROUP_DIM_GRP && !dim->grp)))
+    return relh::fail(ctx, REL_INVALID_ARG, "rel_filter_join_agg: missing dim column");
+  const void* cols[] = {fact->fk, fact->price_cents, fact->qty, fact->day, fact->flag, dim->pk, dim->prio, dim->grp};
+  for (const void* c : cols)
+    if (c && !relh::aligned16(c)) return relh::fail(ctx, REL_INVALID_ARG, "rel_filter_join_agg: column not 16-byte aligned");
+  if (n >= (1ll << 31) || m >= (1ll << 30)) return relh::fail(ctx, REL_UNSUPPORTED, "rel_filter_join_agg: table too large");
+  if (plan && plan->join_placement == REL_PLACE_PARTITIONED)
+    return relh::fail(ctx, REL_UNSUPPORTED, "rel_filter_join_agg: partitioned join is not built here");
+  TRY(relh::ensure_counters(ctx));
+  int64_t* cnt = relh::counters(ctx);
+
+  // Join table: plain sizing (2m rounded up to a power of two), in device memory.
+  const uint32_t jl = relh::join_log2cap(m, nullptr);
+  void* jt;
+  TRY(relh::scratch(ctx, SCR_JOIN_TABLE, ((size_t)8 << jl) + 8, &jt));
+  const void* payload = gb == REL_GROUP_PRIO_FLAG ? (const void*)dim->prio : gb == REL_GROUP_DIM_GRP ? (const void*)dim->grp : nullptr;
+  const int pkind = gb == REL_GROUP_PRIO_FLAG ? relh::PAY_I8 : gb == REL_GROUP_DIM_GRP ? relh::PAY_I32 : relh::PAY_ROW_ID;
+  TRY(relh::join_build_into(ctx, dim->pk, payload, pkind, m, (uint64_t*)jt, jl));
+  TRY(relh::fill_u64(ctx, cnt, 2, 0));
+
+  FusedArgs a{};
+  a.fk = fact->fk;
+  a.price = fact->price_cents;
+  a.qty = fact->qty;
+  a.day = fact->day;
+  a.flag = fact->flag;
+  a.n = n;
+  a.day_lt = q->day_lt;
+  a.join = JoinView{(const uint64_t*)jt, (uint32_t)((1ull << jl) - 1), 32u - jl};
+  a.counters = cnt;
+
+  int gp;
+  int64_t group_cap = 0;
+  void* gt = nullptr;
+  const bool planned = plan && plan->group_capacity > 0;
+  if (gb == REL_GROUP_FK) {
+    gp = G_ROWAGG;  // group key == join key: per-dim-row accumulators
+    group_cap = m;
+    TRY(relh::scratch(ctx, SCR_GROUP_TABLE, (size_t)(m > 0 ? m : 1) * sizeof(RowAgg), &gt));
+    {
+      relh::KernelTimer kt(ctx, "group_table_init");
+      TRY(relh::fill_u64(ctx, gt, (size_t)m * 3, 0));
+    }
+    a.row_agg = (RowAgg*)gt;
+  } else {
+    const int64_t ub = gb == REL_GROUP_PRIO_FLAG ? (n < 65536 ? n : 65536) : (n < m ? n : m);
+    const int64_t expected = planned ? plan->group_capacity : ub;
+    int placement = plan ? plan->group_placement : REL_PLACE_AUTO;
+    if (placement == REL_PLACE_PARTITIONED) return relh::fail(ctx, REL_UNSUPPORTED, "rel_filter_join_agg: partitioned group-by");
+    if (placement == REL_PLACE_AUTO) placement = (gb == REL_GROUP_PRIO_FLAG || expected <= kLdsSlots / 2) ? REL_PLACE_LDS : REL_PLACE_GLOBAL;
+    gp = placement == REL_PLACE_LDS ? G_LDS : G_GLOBAL;
+    const uint32_t gl = group_log2cap(expected, 0.5);
+    if (gl > 31) return relh::fail(ctx, REL_UNSUPPORTED, "rel_filter_join_agg: group table above 2^31 slots");
+    group_cap = 1ll << gl;
+    TRY(relh::scratch(ctx, SCR_GROUP_TABLE, (size_t)(group_cap + 1) * sizeof(GroupSlot), &gt));
+    TRY(init_groups(ctx, (GroupSlot*)gt, group_cap + 1));
+    a.groups = GroupView{(GroupSlot*)gt, (uint32_t)(group_cap - 1), 32u - gl, ctx->d_status,
+                         planned ? kPlannedProbe : (uint32_t)group_cap};
+  }
+
+  if (n > 0) {
+    const unsigned grid = relh::grid_for(ctx, n, kBlock * kIPT, gp == G_LDS ? 4 : 8);
+    if (gb == REL_GROUP_PRIO_FLAG) TRY(launch_fused<M_PRIO_FLAG>(ctx, gp, a, grid));
+    else if (gb == REL_GROUP_FK) TRY(launch_fused<M_FK>(ctx, gp, a, grid));
+    else TRY(launch_fused<M_DIM_GRP>(ctx, gp, a, grid));
+  }
+
+  TRY(relh::fill_u64(ctx, out->d_n_groups, 1, 0));
+  const OutArgs oa = out_args(ctx, out);
+  {
+  relh::KernelTimer kt(ctx, "finalize");
+  if (gp == G_ROWAGG) {
+    if (m > 0) {
+      const unsigned fgrid = relh::grid_for(ctx, m, kBlock, 8);
+      hipLaunchKernelGGL(k_finalize_rowagg, dim3(fgrid), dim3(kBlock), 0, ctx->stream, (const RowAgg*)gt, dim->pk, m, oa);
+    }
+  } else {
+    const unsigned fgrid = relh::grid_for(ctx, group_cap + 1, kBlock, 8);
+    hipLaunchKernelGGL(k_finalize_groups, dim3(fgrid), dim3(kBlock), 0, ctx->stream, (const GroupSlot*)gt, group_cap + 1,
+                       group_cap, oa);
+  }
+  }
+  REL_LAUNCH_CHECK(ctx, "finalize");
+
+  const bool want_sync = stats != nullptr || (planned && plan->allow_fallback);
+  if (!want_sync) return REL_OK;
+  REL_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  int64_t hc[2] = {0, 0}, ng = 0;
+  uint32_t bits = 0;
+  REL_HIP_CHECK(ctx, hipMemcpy(hc, cnt, sizeof hc, hipMemcpyDeviceToHost));
+  REL_HIP_CHECK(ctx, hipMemcpy(&ng, out->d_n_groups, sizeof ng, hipMemcpyDeviceToHost));
+  REL_HIP_CHECK(ctx, hipMemcpy(&bits, ctx->d_status, sizeof bits, hipMemcpyDeviceToHost));
+  if (bits) {
+    TRY(relh::fill_u32(ctx, ctx->d_status, 1, 0));
+    REL_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  if (bits & kDevDupKey) return relh::fail(ctx, REL_DUPLICATE_KEY, "rel_filter_join_agg: duplicate pk");
+  const bool overflow = (bits & kDevOverflow) != 0;
+  if (overflow && ng > out->cap) return relh::fail(ctx, REL_CAPACITY, "rel_filter_join_agg: %lld groups > cap", (long long)ng);
+  if (overflow && planned) {
+    if (!plan->allow_fallback) return relh::fail(ctx, REL_OVERFLOW, "rel_filter_join_agg: planned table overflowed");
+    rel_status s = rel_filter_join_agg(ctx, fact, dim, q, nullptr, out, stats);
+    if (s == REL_OK && stats) {
+      stats->overflowed = 1;
+      stats->fell_back = 1;
+    }
+    return s;
+  }
+  if (overflow) return relh::fail(ctx, REL_OVERFLOW, "rel_filter_join_agg: table overflow");
+  if (stats) {
+    stats->rows_in = n;
+    stats->rows_passed = hc[0];
+    stats->join_matches = hc[1];
+    stats->groups = ng;
+    stats->join_capacity = 1ll << jl;
+    stats->group_capacity = group_cap;
+    stats->join_placement = REL_PLACE_GLOBAL;
+    stats->group_placement = gp == G_LDS ? REL_PLACE_LDS : REL_PLACE_GLOBAL;
+    stats->overflowed = 0;
+    stats->fell_back = 0;
+  }
+  return REL_OK;
+}
+
+}  // extern "C"

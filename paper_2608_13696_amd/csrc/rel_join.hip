@@ -1,0 +1,180 @@
+// Hash join: build (insert_if_n analogue) and probe (count + retrieve
+// analogue, fused into one pass because a PK-FK probe emits at most one pair
+// per probe row, so no counting pass is needed to size the output).
+#include "rel_device.h"
+#include "rel_host.h"
+#include "rel_ops.h"
+
+namespace {
+
+using namespace rel;
+using relh::PAY_I32;
+using relh::PAY_I8;
+using relh::PAY_ROW_ID;
+
+// Insert (pk[j], payload) with one 64-bit CAS per attempted slot. Consecutive
+// threads take consecutive rows, so the key and payload reads are coalesced
+// and each thread keeps its CAS independent of the others.
+template <int PK>
+__global__ __launch_bounds__(256) void k_join_build(const int32_t* __restrict__ pk, const void* __restrict__ payload,
+                                                    int64_t m, uint64_t* __restrict__ slots, uint32_t mask,
+                                                    uint32_t shift, uint32_t* __restrict__ status) {
+  int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; j < m; j += stride) {
+    const int32_t key = pk[j];
+    const int32_t pl = PK == PAY_ROW_ID ? (int32_t)j
+                       : PK == PAY_I32  ? ((const int32_t*)payload)[j]
+                                        : (int32_t)((const int8_t*)payload)[j];
+    if (key == -1) {
+      const uint64_t old = dev_cas<uint64_t>(&slots[(size_t)mask + 1], kJoinEmpty, (uint64_t)(uint32_t)pl);
+      if (old != kJoinEmpty) set_status(status, kDevDupKey);
+      continue;
+    }
+    const uint64_t want = (uint64_t)(uint32_t)key | ((uint64_t)(uint32_t)pl << 32);
+    uint32_t h = hash32(key, shift);
+    for (uint32_t step = 0;; ++step) {
+      if (step > mask) {
+        set_status(status, kDevOverflow);
+        break;
+      }
+      const uint64_t old = dev_cas<uint64_t>(&slots[h], kJoinEmpty, want);
+      if (old == kJoinEmpty) break;
+      if ((uint32_t)old == (uint32_t)key) {
+        set_status(status, kDevDupKey);
+        break;
+      }
+      h = (h + 1) & mask;
+    }
+  }
+}
+
+// Probe: each wave compacts its matches with a ballot and reserves output
+// space with one atomic per wave. Output order is therefore unspecified.
+__global__ __launch_bounds__(256) void k_join_probe(JoinView t, const int32_t* __restrict__ fk,
+                                                    const int32_t* __restrict__ sel, int64_t n,
+                                                    int32_t* __restrict__ out_fact, int32_t* __restrict__ out_payload,
+                                                    int64_t* __restrict__ d_count) {
+  const int64_t wave_global = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const uint32_t lane = lane_id();
+  for (int64_t base = wave_global * kWave; base < n; base += n_waves * kWave) {
+    const int64_t k = base + lane;
+    bool hit = false;
+    int32_t row = 0, pl = 0;
+    if (k < n) {
+      row = sel ? sel[k] : (int32_t)k;
+      hit = join_lookup(t, fk[row], &pl);
+    }
+    const uint64_t ballot = wave_ballot(hit);
+    if (ballot == 0) continue;
+    int64_t off = 0;
+    if (lane == 0) off = dev_add_ret<unsigned long long>((unsigned long long*)d_count, (unsigned long long)__popcll(ballot));
+    off = __shfl(off, 0, kWave);
+    if (hit) {
+      const int64_t o = off + mask_rank(ballot);
+      out_fact[o] = row;
+      out_payload[o] = pl;
+    }
+  }
+}
+
+}  // namespace
+
+namespace relh {
+
+rel_status join_build_into(rel_ctx* ctx, const int32_t* pk, const void* payload, int payload_kind, int64_t m,
+                           uint64_t* slots, uint32_t log2cap) {
+  const uint64_t cap = 1ull << log2cap;
+  rel_status s;
+  {
+    KernelTimer kt(ctx, "join_table_init");
+    s = fill_u64(ctx, slots, cap + 1, rel::kJoinEmpty);
+  }
+  if (s != REL_OK) return s;
+  if (m == 0) return REL_OK;
+  const unsigned grid = grid_for(ctx, m, 256 * 4, 8);
+  const uint32_t mask = (uint32_t)(cap - 1), shift = 32u - log2cap;
+  KernelTimer kt(ctx, "join_build");
+  if (payload_kind == PAY_I32)
+    hipLaunchKernelGGL(k_join_build<PAY_I32>, dim3(grid), dim3(256), 0, ctx->stream, pk, payload, m, slots, mask, shift,
+                       ctx->d_status);
+  else if (payload_kind == PAY_I8)
+    hipLaunchKernelGGL(k_join_build<PAY_I8>, dim3(grid), dim3(256), 0, ctx->stream, pk, payload, m, slots, mask, shift,
+                       ctx->d_status);
+  else
+    hipLaunchKernelGGL(k_join_build<PAY_ROW_ID>, dim3(grid), dim3(256), 0, ctx->stream, pk, payload, m, slots, mask,
+                       shift, ctx->d_status);
+  REL_LAUNCH_CHECK(ctx, "join_build");
+  return REL_OK;
+}
+
+uint32_t join_log2cap(int64_t m, const rel_table_opts* opts) {
+  double load = (opts && opts->max_load > 0.f) ? (double)opts->max_load : 0.5;
+  if (load > 0.9) load = 0.9;
+  int64_t want = (int64_t)((double)(m > 0 ? m : 1) / load) + 1;
+  if (opts && opts->capacity_hint > want) want = opts->capacity_hint;
+  uint32_t l = log2_ceil((uint64_t)want);
+  if (l < 4) l = 4;
+  return l;
+}
+
+}  // namespace relh
+
+extern "C" {
+
+rel_status rel_join_build(rel_ctx* ctx, const int32_t* pk, const int32_t* payload, int64_t m,
+                          const rel_table_opts* opts, rel_join_table** out) {
+  if (!ctx || !out || m < 0 || (m > 0 && !pk)) return relh::fail(ctx, REL_INVALID_ARG, "rel_join_build: bad argument");
+  if (m >= (1ll << 30)) return relh::fail(ctx, REL_UNSUPPORTED, "rel_join_build: m >= 2^30");
+  if (opts && opts->placement != REL_PLACE_AUTO && opts->placement != REL_PLACE_GLOBAL)
+    return relh::fail(ctx, REL_UNSUPPORTED, "rel_join_build: standalone tables live in device memory");
+  const uint32_t l = relh::join_log2cap(m, opts);
+  if (l > 31) return relh::fail(ctx, REL_UNSUPPORTED, "rel_join_build: capacity above 2^31");
+  rel_join_table* t = new rel_join_table();
+  t->ctx = ctx;
+  t->log2cap = l;
+  t->m = m;
+  hipError_t e = hipMalloc(&t->slots, (sizeof(uint64_t) << l) + sizeof(uint64_t));
+  if (e != hipSuccess) {
+    delete t;
+    (void)hipGetLastError();
+    return relh::fail(ctx, REL_OOM, "rel_join_build: table allocation failed");
+  }
+  rel_status s = relh::join_build_into(ctx, pk, payload, payload ? relh::PAY_I32 : relh::PAY_ROW_ID, m, t->slots, l);
+  if (s != REL_OK) {
+    (void)hipFree(t->slots);
+    delete t;
+    return s;
+  }
+  *out = t;
+  return REL_OK;
+}
+
+rel_status rel_join_table_destroy(rel_join_table* t) {
+  if (!t) return REL_INVALID_ARG;
+  if (t->ctx) (void)hipStreamSynchronize(t->ctx->stream);
+  if (t->slots) (void)hipFree(t->slots);
+  delete t;
+  return REL_OK;
+}
+
+rel_status rel_join_probe(rel_ctx* ctx, const rel_join_table* t, const int32_t* fk, const int32_t* sel, int64_t n,
+                          int32_t* out_fact_idx, int32_t* out_payload, int64_t out_cap, int64_t* d_out_count) {
+  if (!ctx || !t || n < 0 || !d_out_count || (n > 0 && (!fk || !out_fact_idx || !out_payload)))
+    return relh::fail(ctx, REL_INVALID_ARG, "rel_join_probe: bad argument");
+  if (t->ctx != ctx) return relh::fail(ctx, REL_INVALID_ARG, "rel_join_probe: table belongs to another context");
+  if (n >= (1ll << 31)) return relh::fail(ctx, REL_UNSUPPORTED, "rel_join_probe: n >= 2^31");
+  if (out_cap < n) return relh::fail(ctx, REL_CAPACITY, "rel_join_probe: out_cap %lld < n %lld", (long long)out_cap, (long long)n);
+  rel_status s = relh::fill_u64(ctx, d_out_count, 1, 0);
+  if (s != REL_OK || n == 0) return s;
+  rel::JoinView v{t->slots, (uint32_t)((1ull << t->log2cap) - 1), 32u - t->log2cap};
+  const unsigned grid = relh::grid_for(ctx, n, 256, 8);
+  relh::KernelTimer kt(ctx, "join_probe");
+  hipLaunchKernelGGL(k_join_probe, dim3(grid), dim3(256), 0, ctx->stream, v, fk, sel, n, out_fact_idx, out_payload,
+                     d_out_count);
+  REL_LAUNCH_CHECK(ctx, "join_probe");
+  return REL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,17 @@
+// Internal entry points shared between librel's translation units.
+#pragma once
+
+#include "rel_host.h"
+
+namespace relh {
+
+// Source of a join-table payload.
+enum PayloadKind : int { PAY_ROW_ID = 0, PAY_I32 = 1, PAY_I8 = 2 };
+
+// Fill `slots` (capacity 2^log2cap, plus the side slot) and insert pk[0..m).
+rel_status join_build_into(rel_ctx* ctx, const int32_t* pk, const void* payload, int payload_kind, int64_t m,
+                           uint64_t* slots, uint32_t log2cap);
+// log2 of the join-table capacity for m keys under opts (plain: 2m rounded up).
+uint32_t join_log2cap(int64_t m, const rel_table_opts* opts);
+
+}  // namespace relh

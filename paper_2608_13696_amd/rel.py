@@ -1,0 +1,281 @@
+"""Thin ctypes binding over librel's C ABI (include/rel.h).
+
+Argument marshalling only: tensors in, device pointers out, on the current
+torch stream. Every step of the computation runs in librel's HIP kernels; if
+librel.so is missing this module raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librel.so")
+
+# enums mirrored from rel.h
+OK, INVALID_ARG, CAPACITY, DUPLICATE_KEY, HIP, OOM, UNSUPPORTED, OVERFLOW = range(8)
+DEV_OVERFLOW, DEV_DUPKEY, DEV_BADARG = 0x1, 0x2, 0x4
+CMP = {"lt": 0, "le": 1, "gt": 2, "ge": 3, "eq": 4, "ne": 5}
+PLACE = {"auto": 0, "lds": 1, "global": 2, "partitioned": 3}
+PLACE_NAME = {v: k for k, v in PLACE.items()}
+GROUP_BY = {"prio_flag": 0, "fk": 1, "dim_grp": 2}
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+
+
+class RelError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"librel status {status}: {msg}")
+        self.status = status
+
+
+class TableOpts(ctypes.Structure):
+    _fields_ = [("capacity_hint", _i64), ("placement", _i32), ("max_load", ctypes.c_float)]
+
+
+class GroupsOut(ctypes.Structure):
+    _fields_ = [("key", _vp), ("sum_price", _vp), ("sum_qty", _vp), ("count", _vp), ("cap", _i64), ("d_n_groups", _vp)]
+
+
+class Fact(ctypes.Structure):
+    _fields_ = [("fk", _vp), ("price_cents", _vp), ("qty", _vp), ("day", _vp), ("flag", _vp), ("n", _i64)]
+
+
+class Dim(ctypes.Structure):
+    _fields_ = [("pk", _vp), ("prio", _vp), ("grp", _vp), ("m", _i64)]
+
+
+class Query(ctypes.Structure):
+    _fields_ = [("day_lt", _i32), ("group_by", _i32)]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("group_capacity", _i64), ("group_placement", _i32), ("join_placement", _i32),
+                ("allow_fallback", _i32), ("reserved", _i32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rows_in", _i64), ("rows_passed", _i64), ("join_matches", _i64), ("groups", _i64),
+                ("join_capacity", _i64), ("group_capacity", _i64), ("join_placement", _i32),
+                ("group_placement", _i32), ("overflowed", _i32), ("fell_back", _i32)]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["join_placement"] = PLACE_NAME.get(d["join_placement"], d["join_placement"])
+        d["group_placement"] = PLACE_NAME.get(d["group_placement"], d["group_placement"])
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """Load librel.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2608_13696_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.rel_ctx_create.argtypes = [ctypes.c_int, _vp, P(_vp)]
+        L.rel_ctx_destroy.argtypes = [_vp]
+        L.rel_ctx_set_stream.argtypes = [_vp, _vp]
+        L.rel_ctx_sync.argtypes = [_vp, P(ctypes.c_uint32)]
+        L.rel_status_string.argtypes = [ctypes.c_int]
+        L.rel_status_string.restype = ctypes.c_char_p
+        L.rel_last_error.argtypes = [_vp]
+        L.rel_last_error.restype = ctypes.c_char_p
+        L.rel_filter_compact.argtypes = [_vp, _vp, _i64, ctypes.c_int, _i32, _vp, _i64, _vp]
+        L.rel_join_build.argtypes = [_vp, _vp, _vp, _i64, P(TableOpts), P(_vp)]
+        L.rel_join_table_destroy.argtypes = [_vp]
+        L.rel_join_probe.argtypes = [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp]
+        L.rel_groupby_agg.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, P(TableOpts), P(GroupsOut)]
+        L.rel_filter_join_agg.argtypes = [_vp, P(Fact), P(Dim), P(Query), P(Plan), P(GroupsOut), P(Stats)]
+        for name in ("rel_ctx_create", "rel_ctx_destroy", "rel_ctx_set_stream", "rel_ctx_sync", "rel_filter_compact",
+                     "rel_join_build", "rel_join_table_destroy", "rel_join_probe", "rel_groupby_agg",
+                     "rel_filter_join_agg"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_check(t, dtype, name):
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Context:
+    """A librel context bound to a device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self.device = device
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self._stream = s
+        h = ctypes.c_void_p()
+        st = lib().rel_ctx_create(device, ctypes.c_void_p(s.cuda_stream), ctypes.byref(h))
+        if st != OK:
+            raise RelError(st, "rel_ctx_create failed")
+        self.h = h
+
+    def check(self, st: int):
+        if st != OK:
+            msg = lib().rel_last_error(self.h).decode()
+            raise RelError(st, msg or lib().rel_status_string(st).decode())
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self._stream = stream
+        self.check(lib().rel_ctx_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def sync(self) -> int:
+        bits = ctypes.c_uint32(0)
+        self.check(lib().rel_ctx_sync(self.h, ctypes.byref(bits)))
+        return bits.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rel_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- operators ------------------------------------------------------------------------------------------------
+
+    def filter_compact(self, col: torch.Tensor, op: str, literal: int):
+        """Stable selection vector of rows with col <op> literal. Returns (idx[:count] view, count)."""
+        _dev_check(col, torch.int32, "col")
+        n = col.numel()
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=col.device)
+        cnt = torch.empty(1, dtype=torch.int64, device=col.device)
+        self.check(lib().rel_filter_compact(self.h, _ptr(col), n, CMP[op], int(literal), _ptr(out), out.numel(), _ptr(cnt)))
+        c = int(cnt.item())
+        return out[:c], c
+
+    def join_build(self, pk: torch.Tensor, payload: torch.Tensor | None = None, capacity_hint: int = 0,
+                   max_load: float = 0.0) -> "JoinTable":
+        _dev_check(pk, torch.int32, "pk")
+        _dev_check(payload, torch.int32, "payload")
+        opts = TableOpts(capacity_hint, PLACE["auto"], max_load)
+        h = ctypes.c_void_p()
+        self.check(lib().rel_join_build(self.h, _ptr(pk), _ptr(payload), pk.numel(), ctypes.byref(opts), ctypes.byref(h)))
+        return JoinTable(self, h, pk, payload)
+
+    def groupby_agg(self, key: torch.Tensor, price: torch.Tensor, qty: torch.Tensor, sel: torch.Tensor | None = None,
+                    capacity_hint: int = 0, placement: str = "auto", out_cap: int | None = None):
+        _dev_check(key, torch.int64, "key")
+        _dev_check(price, torch.int64, "price")
+        _dev_check(qty, torch.int32, "qty")
+        _dev_check(sel, torch.int32, "sel")
+        n = sel.numel() if sel is not None else key.numel()
+        cap = out_cap if out_cap is not None else max(n, 1)
+        out = _alloc_groups(cap, key.device)
+        opts = TableOpts(capacity_hint, PLACE[placement], 0.0)
+        self.check(lib().rel_groupby_agg(self.h, _ptr(key), _ptr(price), _ptr(qty), _ptr(sel), n, ctypes.byref(opts),
+                                         ctypes.byref(out.c)))
+        return out.result()
+
+    def filter_join_agg(self, fact: dict, dim: dict, day_lt: int, group_by: str, plan: Plan | None = None,
+                        stats: bool = True, out_cap: int | None = None):
+        """The fused pipeline. fact: fk, price_cents, qty, day, flag; dim: pk, prio, grp (device tensors)."""
+        for k, dt in (("fk", torch.int32), ("price_cents", torch.int64), ("qty", torch.int32), ("day", torch.int32),
+                      ("flag", torch.int8)):
+            _dev_check(fact.get(k), dt, k)
+        for k, dt in (("pk", torch.int32), ("prio", torch.int8), ("grp", torch.int32)):
+            _dev_check(dim.get(k), dt, k)
+        n, m = fact["fk"].numel(), dim["pk"].numel()
+        if out_cap is None:
+            out_cap = max(1, min(n, 65536) if group_by == "prio_flag" else min(n, max(m, 1)))
+        out = _alloc_groups(out_cap, fact["fk"].device)
+        f = Fact(_ptr(fact["fk"]), _ptr(fact["price_cents"]), _ptr(fact["qty"]), _ptr(fact["day"]), _ptr(fact.get("flag")), n)
+        d = Dim(_ptr(dim["pk"]), _ptr(dim.get("prio")), _ptr(dim.get("grp")), m)
+        q = Query(int(day_lt), GROUP_BY[group_by])
+        st = Stats()
+        self.check(lib().rel_filter_join_agg(self.h, ctypes.byref(f), ctypes.byref(d), ctypes.byref(q),
+                                             ctypes.byref(plan) if plan is not None else None, ctypes.byref(out.c),
+                                             ctypes.byref(st) if stats else None))
+        return out, (st.as_dict() if stats else None)
+
+
+class JoinTable:
+    def __init__(self, ctx: Context, h, pk, payload):
+        self.ctx, self.h = ctx, h
+        self._keep = (pk, payload)
+
+    def probe(self, fk: torch.Tensor, sel: torch.Tensor | None = None):
+        """(fact_idx, payload) pairs of matching probe rows, unordered. Returns (fact_idx, payload, count)."""
+        _dev_check(fk, torch.int32, "fk")
+        _dev_check(sel, torch.int32, "sel")
+        n = sel.numel() if sel is not None else fk.numel()
+        oi = torch.empty(max(n, 1), dtype=torch.int32, device=fk.device)
+        op = torch.empty(max(n, 1), dtype=torch.int32, device=fk.device)
+        cnt = torch.empty(1, dtype=torch.int64, device=fk.device)
+        self.ctx.check(lib().rel_join_probe(self.ctx.h, self.h, _ptr(fk), _ptr(sel), n, _ptr(oi), _ptr(op), oi.numel(),
+                                            _ptr(cnt)))
+        c = int(cnt.item())
+        return oi[:c], op[:c], c
+
+    def close(self):
+        if self.h:
+            lib().rel_join_table_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Groups:
+    key: torch.Tensor
+    sum_price: torch.Tensor
+    sum_qty: torch.Tensor
+    count: torch.Tensor
+    n_groups: torch.Tensor  # device int64[1]
+    c: GroupsOut
+
+    def result(self) -> "Groups":
+        return self
+
+    def host(self) -> dict:
+        """Copy the first n_groups rows to host numpy arrays."""
+        ng = int(self.n_groups.item())
+        k = min(ng, self.key.numel())
+        return {"key": self.key[:k].cpu().numpy(), "sum_price": self.sum_price[:k].cpu().numpy(),
+                "sum_qty": self.sum_qty[:k].cpu().numpy(), "count": self.count[:k].cpu().numpy(), "n_groups": ng}
+
+
+def _alloc_groups(cap: int, device) -> Groups:
+    cap = max(int(cap), 1)
+    t = torch.empty((4, cap), dtype=torch.int64, device=device)
+    ng = torch.zeros(1, dtype=torch.int64, device=device)
+    g = Groups(t[0], t[1], t[2], t[3], ng, None)
+    g.c = GroupsOut(_ptr(t[0]), _ptr(t[1]), _ptr(t[2]), _ptr(t[3]), cap, _ptr(ng))
+    return g
+
+
+def sorted_groups(h: dict) -> dict:
+    """Canonical order (ascending key) of a host group dict."""
+    import numpy as np
+
+    o = np.argsort(h["key"], kind="stable")
+    return {k: (v[o] if k != "n_groups" else v) for k, v in h.items()}

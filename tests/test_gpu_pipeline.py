@@ -1,0 +1,208 @@
+"""GPU parity: librel's fused pipeline and standalone operators against the CPU
+oracle, element by element after canonical sorting (all results are integers,
+so the bar is bit-exact)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+from paper_2608_13696_amd import rel
+from tests.gpu_util import assert_groups_equal, gpu_groups, to_dev
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = rel.Context(0)
+    yield c
+    c.close()
+
+
+def run_both(ctx, T, plan=None, repeats=1):
+    fact, dim = to_dev(T)
+    ora, ostats = oracle.run_tables(T)
+    for r in range(repeats):
+        out, st = ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, plan=plan)
+        g = gpu_groups(out)
+        assert_groups_equal(g, ora, f"{T.meta} rep {r}")
+        assert st["rows_passed"] == ostats["rows_passed"]
+        assert st["join_matches"] == ostats["join_matches"]
+        assert st["groups"] == ostats["groups"]
+    return st
+
+
+@pytest.mark.parametrize("group_by", ["fk", "prio_flag", "dim_grp"])
+def test_hand_worked_example(ctx, group_by):
+    d = json.load(open(os.path.join(GOLD, "tiny_query.json")))
+    f, dm = d["fact"], d["dim"]
+    dev = lambda a, dt: torch.tensor(a, dtype=dt, device="cuda:0")
+    fact = {"fk": dev(f["fk"], torch.int32), "price_cents": dev(f["price"], torch.int64), "qty": dev(f["qty"], torch.int32),
+            "day": dev(f["day"], torch.int32), "flag": dev(f["flag"], torch.int8)}
+    dim = {"pk": dev(dm["pk"], torch.int32), "prio": dev(dm["prio"], torch.int8), "grp": dev(dm["grp"], torch.int32)}
+    out, st = ctx.filter_join_agg(fact, dim, d["day_lt"], group_by)
+    g = gpu_groups(out)
+    exp = d["expected"][group_by]
+    for k in ("key", "sum_price", "sum_qty", "count"):
+        assert g[k].tolist() == exp[k], k
+    assert st["rows_passed"] == d["stats"]["rows_passed"] and st["join_matches"] == d["stats"]["join_matches"]
+
+
+def test_small_workload(ctx):
+    st = run_both(ctx, datagen.small(), repeats=3)
+    assert st["groups"] == 15 and st["group_placement"] == "lds"
+
+
+def test_medium_workload(ctx):
+    st = run_both(ctx, datagen.medium(), repeats=3)
+    assert st["groups"] == 15
+
+
+@pytest.mark.parametrize("group_by", ["fk", "dim_grp", "prio_flag"])
+@pytest.mark.parametrize("n,m", [(1, 1), (3, 2), (1023, 300), (1025, 257), (60_001, 15_000), (250_007, 40_009)])
+def test_ragged_sizes(ctx, group_by, n, m):
+    T = datagen.make_tables(n, m, 1000 + n, day_lt=1500, group_by=group_by, fk_zipf=0.9 if group_by == "fk" else 0.0,
+                            fk_domain=m + m // 3, grp_card=97 if group_by == "dim_grp" else None)
+    run_both(ctx, T)
+
+
+def test_large_shape_scaled_down(ctx):
+    """The 60M-row workload's distributions (Zipf 0.8 fk, group by fk) at 6M x 1.5M, fully compared."""
+    T = datagen.large(seed=33, n=6_000_000, m=1_500_000)
+    run_both(ctx, T, repeats=2)
+
+
+@pytest.mark.parametrize("case", ["empty_fact", "empty_dim", "all_filtered", "no_match", "extreme_keys"])
+def test_degenerate(ctx, case):
+    T = datagen.make_tables(5000, 1000, 77, day_lt=1800, group_by="dim_grp", grp_card=50)
+    if case == "empty_fact":
+        T = datagen.make_tables(0, 1000, 77, day_lt=1800, group_by="dim_grp", grp_card=50)
+    elif case == "empty_dim":
+        T = datagen.make_tables(5000, 0, 77, day_lt=1800, group_by="dim_grp", grp_card=50)
+        T.grp = np.zeros(0, np.int32)
+    elif case == "all_filtered":
+        T.day_lt = 0
+    elif case == "no_match":
+        T.fk = T.fk + 5000
+    elif case == "extreme_keys":
+        # keys at both int32 ends and -1 (the key that needs the side slot), plus negative payloads
+        ext = np.array([-(2 ** 31), 2 ** 31 - 1, -1, -2, -1_000_000], np.int32)
+        T.pk[:5] = ext
+        T.fk[:200] = np.resize(ext, 200)
+        T.grp[:5] = np.array([-1, -(2 ** 31), 2 ** 31 - 1, 5, -7], np.int32)
+    run_both(ctx, T)
+    T.group_by = "fk"
+    run_both(ctx, T)
+
+
+def test_negative_prio_and_flag(ctx):
+    T = datagen.make_tables(20_000, 3_000, 5, day_lt=2000, group_by="prio_flag")
+    T.prio = datagen.uniform(T.m, -128, 127, np.int8, 5, 100)
+    T.flag = datagen.uniform(T.n, -128, 127, np.int8, 5, 101)
+    run_both(ctx, T)
+
+
+def test_duplicate_pk_reported(ctx):
+    T = datagen.make_tables(1000, 100, 3, group_by="fk")
+    T.pk[7] = T.pk[8]
+    fact, dim = to_dev(T)
+    with pytest.raises(rel.RelError) as e:
+        ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by)
+    assert e.value.status == rel.DUPLICATE_KEY
+
+
+@pytest.mark.parametrize("placement", ["lds", "global"])
+def test_planned_overflow_falls_back_to_plain(ctx, placement):
+    T = datagen.make_tables(200_000, 50_000, 9, day_lt=1800, group_by="dim_grp", grp_card=5000)
+    plan = rel.Plan(group_capacity=16, group_placement=rel.PLACE[placement], join_placement=0, allow_fallback=1)
+    fact, dim = to_dev(T)
+    ora, _ = oracle.run_tables(T)
+    out, st = ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, plan=plan)
+    assert st["fell_back"] == 1 and st["overflowed"] == 1
+    assert_groups_equal(gpu_groups(out), ora, "fallback")
+    plan.allow_fallback = 0
+    with pytest.raises(rel.RelError) as e:
+        ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, plan=plan)
+    assert e.value.status == rel.OVERFLOW
+
+
+def test_planned_right_size_is_identical(ctx):
+    T = datagen.make_tables(300_000, 75_000, 10, day_lt=1200, group_by="dim_grp", grp_card=300)
+    for placement in ("lds", "global"):
+        plan = rel.Plan(group_capacity=400, group_placement=rel.PLACE[placement], join_placement=0, allow_fallback=1)
+        st = run_both(ctx, T, plan=plan)
+        assert st["fell_back"] == 0 and st["group_placement"] == placement
+
+
+# -- standalone operators -------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [0, 1, 15, 4096, 4097, 1_000_003])
+@pytest.mark.parametrize("op", ["lt", "le", "gt", "ge", "eq", "ne"])
+def test_filter_compact(ctx, n, op):
+    col = datagen.uniform(n, -20, 20, np.int32, n + 7, 3)
+    idx, c = ctx.filter_compact(torch.from_numpy(col).cuda(), op, 3)
+    exp = oracle.filter_compact(col, op, 3)
+    assert c == exp.shape[0]
+    assert np.array_equal(idx.cpu().numpy(), exp)
+
+
+def test_filter_compact_large_selectivities(ctx):
+    col = datagen.uniform(60_000_000, 0, 2556, np.int32, 3, datagen.S_DAY)
+    d = torch.from_numpy(col).cuda()
+    for lit in (0, 1200, 2557):
+        idx, c = ctx.filter_compact(d, "lt", lit)
+        exp = oracle.filter_compact(col, "lt", lit)
+        assert c == exp.shape[0] and np.array_equal(idx.cpu().numpy(), exp)
+
+
+@pytest.mark.parametrize("with_sel", [False, True])
+@pytest.mark.parametrize("with_payload", [False, True])
+def test_join_probe(ctx, with_sel, with_payload):
+    rng = np.random.default_rng(11)
+    m, n = 40_000, 300_001
+    pk = datagen.permutation(m, 0, 4, 1)
+    pk[0] = -1  # the key kept in the side slot (replaces a key from 0..m-1, so pk stays unique)
+    fk = rng.integers(-30_000, 30_000, size=n).astype(np.int32)
+    fk[:50] = -1
+    payload = rng.integers(-(2 ** 31), 2 ** 31 - 1, size=m).astype(np.int32) if with_payload else None
+    sel = np.flatnonzero(rng.random(n) < 0.45).astype(np.int32) if with_sel else None
+    t = ctx.join_build(torch.from_numpy(pk).cuda(), torch.from_numpy(payload).cuda() if with_payload else None)
+    fi, pl, c = t.probe(torch.from_numpy(fk).cuda(), torch.from_numpy(sel).cuda() if with_sel else None)
+    efi, epl = oracle.join_probe(fk, sel, pk, payload)
+    fi, pl = fi.cpu().numpy(), pl.cpu().numpy()
+    o = np.argsort(fi)
+    assert c == efi.shape[0]
+    assert np.array_equal(fi[o], efi) and np.array_equal(pl[o], epl)
+    t.close()
+
+
+@pytest.mark.parametrize("placement", ["auto", "lds", "global"])
+@pytest.mark.parametrize("n_keys", [1, 40, 3000, 200_000])
+def test_groupby_agg(ctx, placement, n_keys):
+    rng = np.random.default_rng(n_keys)
+    n = 500_000
+    keys = rng.integers(-(2 ** 63), 2 ** 63 - 1, size=n_keys, dtype=np.int64)
+    keys[0] = np.iinfo(np.int64).min
+    key = keys[rng.integers(0, n_keys, size=n)]
+    price = rng.integers(-(2 ** 62), 2 ** 62, size=n, dtype=np.int64)
+    qty = rng.integers(-(2 ** 31), 2 ** 31 - 1, size=n).astype(np.int32)
+    sel = np.flatnonzero(rng.random(n) < 0.7).astype(np.int32)
+    D = lambda a: torch.from_numpy(a).cuda()
+    g = ctx.groupby_agg(D(key), D(price), D(qty), D(sel), placement=placement)
+    assert_groups_equal(gpu_groups(g), oracle.groupby_agg(key, price, qty, sel), f"groupby {placement} {n_keys}")
+    g = ctx.groupby_agg(D(key), D(price), D(qty), None, placement=placement)
+    assert_groups_equal(gpu_groups(g), oracle.groupby_agg(key, price, qty, None), f"groupby nosel {placement} {n_keys}")
+
+
+def test_invalid_arguments_are_rejected(ctx):
+    x = torch.zeros(16, dtype=torch.int32, device="cuda:0")
+    with pytest.raises(rel.RelError) as e:
+        ctx.filter_compact(x[1:], "lt", 3)  # 4-byte offset: misaligned column
+    assert e.value.status == rel.INVALID_ARG
