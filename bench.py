@@ -37,6 +37,33 @@ FACT_BYTES = {"fk": 20, "dim_grp": 20, "prio_flag": 21}
 # Dim bytes per row read by the build: pk 4 (+ payload column).
 DIM_BYTES = {"fk": 4, "dim_grp": 8, "prio_flag": 5}
 OUT_BYTES_PER_GROUP = 32  # key, SUM(price), SUM(qty), COUNT as int64
+PART_ROW_BYTES = 16  # a partitioned fact row: fk 4 + price 8 + qty 4
+
+
+def kernel_alg_bytes(kernel: str, n: int, m: int, r: int, g: int, group_by: str):
+    """Algorithmic bytes of one launch of `kernel`: each input byte the kernel
+    must read once plus each output byte it must write once (no table or
+    re-read traffic). n fact rows, m dim rows, r rows passing the predicate,
+    g groups. Returns (bytes, description) or (None, None)."""
+    fb, db = FACT_BYTES[group_by], DIM_BYTES[group_by]
+    table = {
+        # plain (device-memory table) pipeline
+        "probe_agg": (fb * n, f"{fb} B per fact row (day, fk, price_cents, qty)"),
+        "join_build": (db * m, f"{db} B per dim row"),
+        "finalize": (OUT_BYTES_PER_GROUP * g, "32 B per output group"),
+        # radix-partitioned groupjoin
+        "fact_p1_hist": (8 * n, "8 B per fact row (day, fk)"),
+        "fact_p1_scatter": (20 * n + PART_ROW_BYTES * r, "20 B per fact row read + 16 B per passing row written"),
+        "fact_p2_hist": (4 * r, "4 B per passing row (fk)"),
+        "fact_p2_scatter": (2 * PART_ROW_BYTES * r, "16 B per passing row read + 16 B written"),
+        "dim_p1_hist": (4 * m, "4 B per dim row"),
+        "dim_p1_scatter": (8 * m, "4 B per dim row read + 4 B written"),
+        "dim_p2_hist": (4 * m, "4 B per dim row"),
+        "dim_p2_scatter": (8 * m, "4 B per dim row read + 4 B written"),
+        "part_groupjoin": (PART_ROW_BYTES * r + 4 * m + OUT_BYTES_PER_GROUP * g,
+                           "16 B per passing row + 4 B per dim key + 32 B per group"),
+    }
+    return table.get(kernel, (None, None))
 
 
 def workload(name: str):
@@ -91,19 +118,20 @@ def cpu_baseline(sample_rows: int, wl: str) -> dict:
     import datagen
     import oracle
 
-    if wl == "large":
+    if wl == "large" and sample_rows < 60_000_000:
         m = max(sample_rows // 4, 1)
         T = datagen.large(seed=3, n=sample_rows, m=m)
         desc = f"same generator and query at {sample_rows:,} fact x {m:,} dim rows (1/{60_000_000 // sample_rows} scale)"
     else:
         T = workload(wl)[0]
-        desc = "the full workload"
+        desc = "the full workload (same seed and inputs as the GPU run)"
     times = []
-    t_end = time.perf_counter() + 10.0
+    t_end = time.perf_counter() + 12.0
     while True:
         t0 = time.perf_counter()
         oracle.run_tables(T)
         times.append(time.perf_counter() - t0)
+        log(f"  oracle run {len(times)}: {times[-1]:.2f} s")
         if time.perf_counter() > t_end or len(times) >= 5:
             break
     times.sort()
@@ -119,7 +147,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large", choices=["large", "medium", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rows", type=int, default=6_000_000)
+    ap.add_argument("--cpu-sample-rows", type=int, default=60_000_000)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -175,15 +203,16 @@ def main() -> int:
     dom = max(kt.items(), key=lambda kv: kv[1][0])
     dom_name, (dom_tot, dom_cnt) = dom
     dom_ms = dom_tot / max(dom_cnt, 1)
-    per_row = FACT_BYTES[T.group_by]
-    if dom_name == "probe_agg":
-        alg_bytes = per_row * n
-        unit_desc = f"{per_row} B per fact row x {n:,} rows"
-    else:
-        alg_bytes = None
-        unit_desc = None
+    r, g = st["rows_passed"], st["groups"]
+    alg_bytes, unit_desc = kernel_alg_bytes(dom_name, n, m, r, g, T.group_by)
     achieved = alg_bytes / (dom_ms / 1e3) / 1e9 if alg_bytes else None
-    pipe_bytes = per_row * n + DIM_BYTES[T.group_by] * m + OUT_BYTES_PER_GROUP * st["groups"]
+    per_kernel = {}
+    for k, (tot, c) in kt.items():
+        kms = tot / max(c, 1)
+        b, _ = kernel_alg_bytes(k, n, m, r, g, T.group_by)
+        per_kernel[k] = {"ms": kms, "alg_gbs": (b / (kms / 1e3) / 1e9) if b else None}
+    per_row = FACT_BYTES[T.group_by]
+    pipe_bytes = per_row * n + DIM_BYTES[T.group_by] * m + OUT_BYTES_PER_GROUP * g
     pipe_gbs = pipe_bytes / (ms / 1e3) / 1e9
 
     result = {
@@ -205,9 +234,9 @@ def main() -> int:
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": traffic_for(dom_name, args.workload), "algorithmic_bytes_per_launch": alg_bytes,
-                     "per_unit": unit_desc, "avg_launch_ms": dom_ms},
+                     "per_unit": unit_desc, "avg_launch_ms": dom_ms, "launches": dom_cnt},
         "pipeline": {"compulsory_bytes": pipe_bytes, "achieved_gbs": pipe_gbs, "hbm_frac": pipe_gbs / HBM_PEAK_GBS,
-                     "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in kt.items()}},
+                     "kernels": per_kernel},
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")

@@ -66,6 +66,67 @@ __device__ __forceinline__ T dev_cas(T* p, T expected, T desired) {
   return expected;  // the value found
 }
 
+// ---- workgroup scan and decoupled look-back ----------------------------------------------------------------------------
+
+// Exclusive prefix sum of v over a workgroup of NT threads (NT a multiple of
+// 64, at most 1024); *total receives the workgroup sum. Uses `scratch`
+// (NT/64 words of LDS) and synchronises the workgroup twice.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* scratch, uint32_t* total) {
+  const uint32_t lane = lane_id();
+  const uint32_t wave = threadIdx.x / kWave;
+  uint32_t incl = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o, kWave);
+    if (lane >= (uint32_t)o) incl += t;
+  }
+  __syncthreads();
+  if (lane == kWave - 1) scratch[wave] = incl;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NT / kWave; ++w) {
+    const uint32_t t = scratch[w];
+    off += (uint32_t)w < wave ? t : 0u;
+    tot += t;
+  }
+  *total = tot;
+  return off + incl - v;
+}
+
+constexpr uint64_t kLbAgg = 1ull << 62;   // a tile's own count is published
+constexpr uint64_t kLbIncl = 2ull << 62;  // a tile's inclusive prefix is published
+constexpr uint64_t kLbVal = (1ull << 62) - 1;
+
+// Decoupled look-back (Merrill and Garland 2016) for one thread of tile
+// `tile` whose own count is `count`: publishes, waits on predecessors and
+// returns the exclusive prefix. Tiles must be numbered in the order their
+// workgroups started (a ticket), so every awaited predecessor is running and
+// publishes without waiting on this tile.
+__device__ __forceinline__ uint64_t lookback_prefix(uint64_t* state, int64_t tile, uint64_t count) {
+  if (tile == 0) {
+    __hip_atomic_store(&state[0], kLbIncl | count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  __hip_atomic_store(&state[tile], kLbAgg | count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t acc = 0;
+  int64_t p = tile - 1;
+  for (;;) {
+    const uint64_t st = __hip_atomic_load(&state[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t flag = st & ~kLbVal;
+    if (flag == 0) {
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    acc += st & kLbVal;
+    if (flag == kLbIncl) break;
+    --p;  // stays >= 0: tile 0 only ever publishes an inclusive prefix
+  }
+  __hip_atomic_store(&state[tile], kLbIncl | (acc + count), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return acc;
+}
+
 // ---- join table -------------------------------------------------------------------------------------------------------
 
 // Slots [0, capacity) hold packed {key, payload}; an in-table key is never

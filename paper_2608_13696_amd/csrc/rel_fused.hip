@@ -182,59 +182,93 @@ struct OutArgs {
   uint32_t* status;
 };
 
-// Wave-cooperative output append: one atomic per wave reserves room for the
-// wave's occupied slots; ranks come from the ballot.
-__device__ __forceinline__ void emit(const OutArgs& o, bool occ, int64_t key, uint64_t sp, uint64_t sq, uint64_t cnt) {
-  const uint64_t b = wave_ballot(occ);
-  if (b == 0) return;
-  int64_t base = 0;
-  if (lane_id() == 0) base = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)o.d_n, (unsigned long long)__popcll(b));
-  base = __shfl(base, 0, kWave);
-  if (!occ) return;
-  const int64_t i = base + mask_rank(b);
-  if (i < o.cap) {
-    o.key[i] = key;
-    o.sum_price[i] = (int64_t)sp;
-    o.sum_qty[i] = (int64_t)sq;
-    o.count[i] = (int64_t)cnt;
-  } else {
-    set_status(o.status, kDevOverflow);
+// Group finalization: stream compaction of the occupied slots into the
+// output, in slot order. Each workgroup takes a tile by ticket, counts its
+// occupied slots, and finds its output offset by decoupled look-back, so no
+// single output counter is contended.
+constexpr int kFinIPT = 8;
+constexpr int64_t kFinTile = (int64_t)kBlock * kFinIPT;
+
+struct SlotSource {  // group table; the last slot holds the key INT64_MIN
+  const GroupSlot* slots;
+  int64_t side;
+  __device__ bool occupied(int64_t i) const { return slots[i].count != 0; }
+  __device__ void get(int64_t i, int64_t* key, uint64_t* sp, uint64_t* sq, uint64_t* cnt) const {
+    const GroupSlot g = slots[i];
+    *key = i == side ? kGroupEmpty : g.key;
+    *sp = g.sum_price;
+    *sq = g.sum_qty;
+    *cnt = g.count;
+  }
+};
+
+struct RowAggSource {  // groupjoin accumulators; the key is the dim row's pk
+  const RowAgg* agg;
+  const int32_t* pk;
+  __device__ bool occupied(int64_t i) const { return agg[i].count != 0; }
+  __device__ void get(int64_t i, int64_t* key, uint64_t* sp, uint64_t* sq, uint64_t* cnt) const {
+    const RowAgg r = agg[i];
+    *key = pk[i];
+    *sp = r.sum_price;
+    *sq = r.sum_qty;
+    *cnt = r.count;
+  }
+};
+
+template <class Src>
+__global__ __launch_bounds__(kBlock) void k_finalize(Src src, int64_t nitems, OutArgs o, uint64_t* __restrict__ state,
+                                                     int64_t* __restrict__ ticket, int64_t ntiles) {
+  __shared__ int64_t s_tile;
+  __shared__ uint64_t s_excl;
+  __shared__ uint32_t scr[kBlock / kWave];
+  if (threadIdx.x == 0) s_tile = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)ticket, 1ull);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t i0 = tile * kFinTile + (int64_t)threadIdx.x * kFinIPT;
+  uint32_t bits = 0;
+#pragma unroll
+  for (int k = 0; k < kFinIPT; ++k)
+    if (i0 + k < nitems && src.occupied(i0 + k)) bits |= 1u << k;
+  uint32_t total;
+  const uint32_t off = block_excl_scan<kBlock>((uint32_t)__popc(bits), scr, &total);
+  if (threadIdx.x == 0) {
+    s_excl = lookback_prefix(state, tile, total);
+    if (tile == ntiles - 1) *o.d_n = (int64_t)(s_excl + total);
+  }
+  __syncthreads();
+  int64_t pos = (int64_t)s_excl + off;
+  for (int k = 0; k < kFinIPT; ++k) {
+    if (!(bits & (1u << k))) continue;
+    if (pos < o.cap) {
+      int64_t key;
+      uint64_t sp, sq, cnt;
+      src.get(i0 + k, &key, &sp, &sq, &cnt);
+      o.key[pos] = key;
+      o.sum_price[pos] = (int64_t)sp;
+      o.sum_qty[pos] = (int64_t)sq;
+      o.count[pos] = (int64_t)cnt;
+    } else {
+      set_status(o.status, kDevOverflow);
+    }
+    ++pos;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_finalize_groups(const GroupSlot* __restrict__ slots, int64_t nslots, int64_t side,
-                                                            OutArgs o) {
-  const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
-  const int64_t n_waves = ((int64_t)gridDim.x * kBlock) / kWave;
-  for (int64_t base = wave * kWave; base < nslots; base += n_waves * kWave) {
-    const int64_t s = base + lane_id();
-    bool occ = false;
-    GroupSlot g{};
-    if (s < nslots) {
-      g = slots[s];
-      occ = g.count != 0;
-      if (s == side) g.key = kGroupEmpty;
-    }
-    emit(o, occ, g.key, g.sum_price, g.sum_qty, g.count);
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_finalize_rowagg(const RowAgg* __restrict__ agg, const int32_t* __restrict__ pk,
-                                                            int64_t m, OutArgs o) {
-  const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
-  const int64_t n_waves = ((int64_t)gridDim.x * kBlock) / kWave;
-  for (int64_t base = wave * kWave; base < m; base += n_waves * kWave) {
-    const int64_t j = base + lane_id();
-    bool occ = false;
-    RowAgg r{};
-    int64_t key = 0;
-    if (j < m) {
-      r = agg[j];
-      occ = r.count != 0;
-      if (occ) key = pk[j];
-    }
-    emit(o, occ, key, r.sum_price, r.sum_qty, r.count);
-  }
+template <class Src>
+rel_status finalize(rel_ctx* ctx, const Src& src, int64_t nitems, const OutArgs& o) {
+  rel_status s = relh::fill_u64(ctx, o.d_n, 1, 0);
+  if (s != REL_OK || nitems == 0) return s;
+  const int64_t ntiles = (nitems + kFinTile - 1) / kFinTile;
+  void* st;
+  if ((s = relh::scratch(ctx, SCR_SCAN_STATE, (size_t)ntiles * 8, &st)) != REL_OK) return s;
+  if ((s = relh::fill_u64(ctx, st, (size_t)ntiles, 0)) != REL_OK) return s;
+  int64_t* ticket = relh::counters(ctx) + CNT_TICKET;
+  if ((s = relh::fill_u64(ctx, ticket, 1, 0)) != REL_OK) return s;
+  relh::KernelTimer kt(ctx, "finalize");
+  hipLaunchKernelGGL(k_finalize<Src>, dim3((unsigned)ntiles), dim3(kBlock), 0, ctx->stream, src, nitems, o,
+                     (uint64_t*)st, ticket, ntiles);
+  REL_LAUNCH_CHECK(ctx, "finalize");
+  return REL_OK;
 }
 
 rel_status init_groups(rel_ctx* ctx, GroupSlot* slots, int64_t nslots) {
@@ -279,6 +313,14 @@ rel_status launch_fused(rel_ctx* ctx, int gp, const FusedArgs& a, unsigned grid)
     if (s_ != REL_OK) return s_;    \
   } while (0)
 
+// GROUP BY fk inputs at least this large take the radix-partitioned path
+// unless a plan says otherwise.
+constexpr int64_t kPartitionMinRows = 1 << 20;
+
+rel_status sync_stats(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, const rel_query* q, const rel_plan* plan,
+                      rel_groups_out* out, rel_stats* stats, int64_t* cnt, int64_t join_cap, int64_t group_cap,
+                      int join_place, int group_place);
+
 }  // namespace
 
 extern "C" {
@@ -310,13 +352,7 @@ rel_status rel_groupby_agg(rel_ctx* ctx, const int64_t* key, const int64_t* pric
       hipLaunchKernelGGL(k_groupby<G_GLOBAL>, dim3(grid), dim3(kBlock), 0, ctx->stream, key, price, qty, sel, n, g);
     REL_LAUNCH_CHECK(ctx, "groupby");
   }
-  TRY(relh::fill_u64(ctx, out->d_n_groups, 1, 0));
-  const unsigned fgrid = relh::grid_for(ctx, nslots, kBlock, 8);
-  relh::KernelTimer kt(ctx, "finalize");
-  hipLaunchKernelGGL(k_finalize_groups, dim3(fgrid), dim3(kBlock), 0, ctx->stream, (const GroupSlot*)tbl, nslots,
-                     nslots - 1, out_args(ctx, out));
-  REL_LAUNCH_CHECK(ctx, "finalize_groups");
-  return REL_OK;
+  return finalize(ctx, SlotSource{(const GroupSlot*)tbl, nslots - 1}, nslots, out_args(ctx, out));
 }
 
 rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, const rel_query* q,
@@ -334,10 +370,19 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
   for (const void* c : cols)
     if (c && !relh::aligned16(c)) return relh::fail(ctx, REL_INVALID_ARG, "rel_filter_join_agg: column not 16-byte aligned");
   if (n >= (1ll << 31) || m >= (1ll << 30)) return relh::fail(ctx, REL_UNSUPPORTED, "rel_filter_join_agg: table too large");
-  if (plan && plan->join_placement == REL_PLACE_PARTITIONED)
-    return relh::fail(ctx, REL_UNSUPPORTED, "rel_filter_join_agg: partitioned join is not built here");
   TRY(relh::ensure_counters(ctx));
   int64_t* cnt = relh::counters(ctx);
+  const bool planned = plan && plan->group_capacity > 0;
+
+  // Radix-partitioned groupjoin: asked for, or chosen for large GROUP BY fk inputs.
+  const int jp = plan ? plan->join_placement : REL_PLACE_AUTO;
+  if (jp == REL_PLACE_PARTITIONED && gb != REL_GROUP_FK)
+    return relh::fail(ctx, REL_UNSUPPORTED, "rel_filter_join_agg: the partitioned path groups by fk only");
+  if (gb == REL_GROUP_FK && (jp == REL_PLACE_PARTITIONED || (jp == REL_PLACE_AUTO && n >= kPartitionMinRows))) {
+    TRY(relh::fill_u64(ctx, cnt, 2, 0));
+    TRY(relh::partitioned_groupjoin(ctx, fact, dim, q->day_lt, out, cnt));
+    return sync_stats(ctx, fact, dim, q, plan, out, stats, cnt, m, m, REL_PLACE_PARTITIONED, REL_PLACE_PARTITIONED);
+  }
 
   // Join table: plain sizing (2m rounded up to a power of two), in device memory.
   const uint32_t jl = relh::join_log2cap(m, nullptr);
@@ -362,7 +407,6 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
   int gp;
   int64_t group_cap = 0;
   void* gt = nullptr;
-  const bool planned = plan && plan->group_capacity > 0;
   if (gb == REL_GROUP_FK) {
     gp = G_ROWAGG;  // group key == join key: per-dim-row accumulators
     group_cap = m;
@@ -395,23 +439,25 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
     else TRY(launch_fused<M_DIM_GRP>(ctx, gp, a, grid));
   }
 
-  TRY(relh::fill_u64(ctx, out->d_n_groups, 1, 0));
   const OutArgs oa = out_args(ctx, out);
-  {
-  relh::KernelTimer kt(ctx, "finalize");
-  if (gp == G_ROWAGG) {
-    if (m > 0) {
-      const unsigned fgrid = relh::grid_for(ctx, m, kBlock, 8);
-      hipLaunchKernelGGL(k_finalize_rowagg, dim3(fgrid), dim3(kBlock), 0, ctx->stream, (const RowAgg*)gt, dim->pk, m, oa);
-    }
-  } else {
-    const unsigned fgrid = relh::grid_for(ctx, group_cap + 1, kBlock, 8);
-    hipLaunchKernelGGL(k_finalize_groups, dim3(fgrid), dim3(kBlock), 0, ctx->stream, (const GroupSlot*)gt, group_cap + 1,
-                       group_cap, oa);
-  }
-  }
-  REL_LAUNCH_CHECK(ctx, "finalize");
+  if (gp == G_ROWAGG) TRY(finalize(ctx, RowAggSource{(const RowAgg*)gt, dim->pk}, m, oa));
+  else TRY(finalize(ctx, SlotSource{(const GroupSlot*)gt, group_cap}, group_cap + 1, oa));
+  return sync_stats(ctx, fact, dim, q, plan, out, stats, cnt, (int64_t)1 << jl, group_cap, REL_PLACE_GLOBAL,
+                    gp == G_LDS ? REL_PLACE_LDS : REL_PLACE_GLOBAL);
+}
 
+}  // extern "C"
+
+namespace {
+
+// Common tail of the fused pipeline: when the caller wants statistics or a
+// planned table may need the fallback, synchronise, read the counters and the
+// status word, and rerun with plain sizing if a planned table overflowed.
+rel_status sync_stats(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, const rel_query* q, const rel_plan* plan,
+                      rel_groups_out* out, rel_stats* stats, int64_t* cnt, int64_t join_cap, int64_t group_cap,
+                      int join_place, int group_place) {
+  const int64_t n = fact->n;
+  const bool planned = plan && plan->group_capacity > 0;
   const bool want_sync = stats != nullptr || (planned && plan->allow_fallback);
   if (!want_sync) return REL_OK;
   REL_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
@@ -442,14 +488,14 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
     stats->rows_passed = hc[0];
     stats->join_matches = hc[1];
     stats->groups = ng;
-    stats->join_capacity = 1ll << jl;
+    stats->join_capacity = join_cap;
     stats->group_capacity = group_cap;
-    stats->join_placement = REL_PLACE_GLOBAL;
-    stats->group_placement = gp == G_LDS ? REL_PLACE_LDS : REL_PLACE_GLOBAL;
+    stats->join_placement = join_place;
+    stats->group_placement = group_place;
     stats->overflowed = 0;
     stats->fell_back = 0;
   }
   return REL_OK;
 }
 
-}  // extern "C"
+}  // namespace

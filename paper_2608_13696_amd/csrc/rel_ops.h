@@ -6,12 +6,19 @@
 namespace relh {
 
 // Source of a join-table payload.
-enum PayloadKind : int { PAY_ROW_ID = 0, PAY_I32 = 1, PAY_I8 = 2 };
+enum PayloadKind : int { PAY_ROW_ID = 0, PAY_I32 = 1, PAY_I8 = 2, PAY_NONE = 3 };
 
 // Fill `slots` (capacity 2^log2cap, plus the side slot) and insert pk[0..m).
 rel_status join_build_into(rel_ctx* ctx, const int32_t* pk, const void* payload, int payload_kind, int64_t m,
                            uint64_t* slots, uint32_t log2cap);
 // log2 of the join-table capacity for m keys under opts (plain: 2m rounded up).
 uint32_t join_log2cap(int64_t m, const rel_table_opts* opts);
+
+// GROUP BY fk of fact JOIN dim ON fk = pk WHERE day < day_lt through radix
+// partitioning of both sides and LDS-resident per-partition tables. Adds the
+// passing-row and join-match counts to counters[CNT_ROWS_PASSED] and
+// counters[CNT_JOIN_MATCHES]; writes groups and *d_n_groups.
+rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, int32_t day_lt,
+                                 rel_groups_out* out, int64_t* counters);
 
 }  // namespace relh

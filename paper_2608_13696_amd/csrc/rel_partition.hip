@@ -1,0 +1,727 @@
+// Radix-partitioned groupjoin for large build sides (GROUP BY fk with fk = pk).
+//
+// A device-memory table updated with device-scope atomics costs one atomic
+// per aggregate per joined row, and those atomics run at a fixed device-wide
+// rate far below what the streaming reads allow. Partitioning both sides by
+// the key's hash makes every partition's dim keys fit a workgroup's LDS, so
+// the build, the probe and all aggregate updates become LDS operations
+// (the paper's Recommendation 2: use the on-chip memories), and device memory
+// sees only sequential partition reads and writes.
+//
+// Passes (each side; fact rows are filtered by the predicate in pass 1):
+//   1. histogram of the top B1 hash bits per input tile; column scan;
+//      scatter into 2^B1 partitions (long runs per tile, so writes coalesce);
+//   2. per first-level partition, the same on the next B2 bits.
+// Then one work unit per (partition, chunk of at most kJChunk dim keys),
+// ordered by decreasing fact-row count, builds an LDS table, streams the
+// partition's fact rows through it, and emits its groups at an offset found
+// by decoupled look-back over the unit order.
+#include "rel_device.h"
+#include "rel_host.h"
+#include "rel_ops.h"
+
+namespace {
+
+using namespace rel;
+
+constexpr int kBlk = 256;
+constexpr int64_t kTile1 = 16384;  // input rows per first-level tile
+constexpr int64_t kTile2 = 16384;  // partition rows per second-level tile
+constexpr int kMaxBins = 256;
+constexpr int kJBlock = 512;
+constexpr int kJSlotBits = 11;
+constexpr int kJSlots = 1 << kJSlotBits;
+constexpr int kJChunk = 1400;  // dim keys per unit: LDS load factor <= 0.69
+constexpr int kCombineMin = 8; // lanes sharing a slot before a wave pre-sums them
+
+__device__ __forceinline__ uint32_t phash(int32_t key) { return (uint32_t)key * 2654435769u; }
+// LDS slot: an independent multiplicative hash, so slot bits do not repeat the partition bits.
+__device__ __forceinline__ uint32_t slot_hash(int32_t key) { return ((uint32_t)key * 0x85EBCA6Bu) >> (32 - kJSlotBits); }
+
+struct PartSide {
+  // first-level inputs
+  const int32_t* key;
+  const int32_t* day;      // fact only
+  const int64_t* price;    // fact only
+  const int32_t* qty;      // fact only
+  const void* payload;     // dim only (PayloadKind)
+  int pkind;
+  int32_t day_lt;
+  int64_t n;
+  // first-level outputs / second-level inputs
+  int32_t* key1;
+  int64_t* price1;
+  int32_t* qty1;
+  int32_t* pay1;
+  // second-level outputs
+  int32_t* key2;
+  int64_t* price2;
+  int32_t* qty2;
+  int32_t* pay2;
+  // bookkeeping
+  uint32_t* hist1;   // [ntiles1][nb1]
+  uint32_t* tot1;    // [nb1]
+  uint32_t* hist2;   // [max tiles2][nb2]
+  uint32_t* pstart;  // [nb1 * nb2]
+  uint32_t* pcount;  // [nb1 * nb2]
+  uint32_t b1, b2;
+};
+
+// ---- first level -------------------------------------------------------------------------------------------------------
+
+template <bool FACT>
+__device__ __forceinline__ bool row_passes(const PartSide& s, int64_t r) {
+  return !FACT || s.day[r] < s.day_lt;
+}
+
+template <bool FACT>
+__global__ __launch_bounds__(kBlk) void k_p1_hist(PartSide s) {
+  __shared__ uint32_t h[kMaxBins];
+  const uint32_t nb1 = 1u << s.b1, shift = 32u - s.b1;
+  for (uint32_t b = threadIdx.x; b < nb1; b += kBlk) h[b] = 0;
+  __syncthreads();
+  const int64_t r0 = blockIdx.x * kTile1;
+  const int64_t r1 = r0 + kTile1 < s.n ? r0 + kTile1 : s.n;
+  for (int64_t r = r0 + 4 * threadIdx.x; r < r1; r += 4 * kBlk) {
+    if (r + 4 <= r1) {
+      const int4 kv = *reinterpret_cast<const int4*>(s.key + r);
+      int4 dv = make_int4(0, 0, 0, 0);
+      if (FACT) dv = *reinterpret_cast<const int4*>(s.day + r);
+      const int32_t ks[4] = {kv.x, kv.y, kv.z, kv.w};
+      const int32_t ds[4] = {dv.x, dv.y, dv.z, dv.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (!FACT || ds[k] < s.day_lt) atomicAdd(&h[phash(ks[k]) >> shift], 1u);
+    } else {
+      for (int64_t q = r; q < r1; ++q)
+        if (row_passes<FACT>(s, q)) atomicAdd(&h[phash(s.key[q]) >> shift], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < nb1; b += kBlk) s.hist1[(size_t)blockIdx.x * nb1 + b] = h[b];
+}
+
+// Column b of hist1 (one bin over all tiles) -> exclusive prefix in place; tot1[b] = column sum.
+__global__ __launch_bounds__(kBlk) void k_p1_colscan(uint32_t* __restrict__ hist1, int64_t ntiles, uint32_t nb1,
+                                                     uint32_t* __restrict__ tot1, int64_t* __restrict__ passed) {
+  __shared__ uint32_t scr[kBlk / kWave];
+  const uint32_t b = blockIdx.x;
+  uint32_t carry = 0;
+  for (int64_t t0 = 0; t0 < ntiles; t0 += kBlk) {
+    const int64_t t = t0 + threadIdx.x;
+    const uint32_t v = t < ntiles ? hist1[(size_t)t * nb1 + b] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<kBlk>(v, scr, &tot);
+    if (t < ntiles) hist1[(size_t)t * nb1 + b] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    tot1[b] = carry;
+    if (passed) dev_add<unsigned long long>((unsigned long long*)passed, (unsigned long long)carry);
+  }
+}
+
+template <bool FACT>
+__device__ __forceinline__ void p1_put(const PartSide& s, int64_t r, int32_t key, uint32_t pos) {
+  s.key1[pos] = key;
+  if (FACT) {
+    s.price1[pos] = s.price[r];
+    s.qty1[pos] = s.qty[r];
+  } else if (s.pkind != relh::PAY_NONE) {
+    s.pay1[pos] = s.pkind == relh::PAY_ROW_ID ? (int32_t)r
+                  : s.pkind == relh::PAY_I32  ? ((const int32_t*)s.payload)[r]
+                                              : (int32_t)((const int8_t*)s.payload)[r];
+  }
+}
+
+template <bool FACT>
+__global__ __launch_bounds__(kBlk) void k_p1_scatter(PartSide s) {
+  __shared__ uint32_t cur[kMaxBins];
+  __shared__ uint32_t scr[kBlk / kWave];
+  const uint32_t nb1 = 1u << s.b1, shift = 32u - s.b1;
+  // partition starts: exclusive scan of the bin totals (nb1 <= kBlk)
+  const uint32_t v = threadIdx.x < nb1 ? s.tot1[threadIdx.x] : 0u;
+  uint32_t tot;
+  const uint32_t base = block_excl_scan<kBlk>(v, scr, &tot);
+  if (threadIdx.x < nb1) cur[threadIdx.x] = base + s.hist1[(size_t)blockIdx.x * nb1 + threadIdx.x];
+  __syncthreads();
+  const int64_t r0 = blockIdx.x * kTile1;
+  const int64_t r1 = r0 + kTile1 < s.n ? r0 + kTile1 : s.n;
+  // Eight consecutive rows per thread per step. Every column of the eight rows
+  // is loaded before any row is placed, so the loads overlap each other
+  // instead of each waiting behind the previous row's LDS atomic and stores.
+  constexpr int R = 8;
+  for (int64_t r = r0 + R * threadIdx.x; r < r1; r += R * kBlk) {
+    if (r + R <= r1) {
+      int32_t ks[R], ds[R], qs[R], ps32[R];
+      int64_t ps[R];
+#pragma unroll
+      for (int v = 0; v < R / 4; ++v) {
+        const int4 kv = *reinterpret_cast<const int4*>(s.key + r + 4 * v);
+        ks[4 * v] = kv.x; ks[4 * v + 1] = kv.y; ks[4 * v + 2] = kv.z; ks[4 * v + 3] = kv.w;
+        if (FACT) {
+          const int4 dv = *reinterpret_cast<const int4*>(s.day + r + 4 * v);
+          const int4 qv = *reinterpret_cast<const int4*>(s.qty + r + 4 * v);
+          const longlong2 pa = *reinterpret_cast<const longlong2*>(s.price + r + 4 * v);
+          const longlong2 pb = *reinterpret_cast<const longlong2*>(s.price + r + 4 * v + 2);
+          ds[4 * v] = dv.x; ds[4 * v + 1] = dv.y; ds[4 * v + 2] = dv.z; ds[4 * v + 3] = dv.w;
+          qs[4 * v] = qv.x; qs[4 * v + 1] = qv.y; qs[4 * v + 2] = qv.z; qs[4 * v + 3] = qv.w;
+          ps[4 * v] = pa.x; ps[4 * v + 1] = pa.y; ps[4 * v + 2] = pb.x; ps[4 * v + 3] = pb.y;
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int64_t q = r + 4 * v + k;
+            ps32[4 * v + k] = s.pkind == relh::PAY_ROW_ID ? (int32_t)q
+                              : s.pkind == relh::PAY_I32  ? ((const int32_t*)s.payload)[q]
+                              : s.pkind == relh::PAY_I8   ? (int32_t)((const int8_t*)s.payload)[q]
+                                                          : 0;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        if (FACT && !(ds[k] < s.day_lt)) continue;
+        const uint32_t pos = atomicAdd(&cur[phash(ks[k]) >> shift], 1u);
+        s.key1[pos] = ks[k];
+        if (FACT) {
+          s.price1[pos] = ps[k];
+          s.qty1[pos] = qs[k];
+        } else if (s.pkind != relh::PAY_NONE) {
+          s.pay1[pos] = ps32[k];
+        }
+      }
+    } else {
+      for (int64_t q = r; q < r1; ++q)
+        if (row_passes<FACT>(s, q)) p1_put<FACT>(s, q, s.key[q], atomicAdd(&cur[phash(s.key[q]) >> shift], 1u));
+    }
+  }
+}
+
+// ---- second level ------------------------------------------------------------------------------------------------------
+
+// Locate this workgroup's second-level tile: first-level partition p, its
+// start, its row range. Returns false for the surplus workgroups of the
+// upper-bound grid. Needs nb1 <= kBlk.
+struct Tile2 {
+  uint32_t p;
+  uint32_t p_start;   // start of partition p in the first-level arrays
+  uint32_t tile_in_p; // index of this tile inside partition p
+  int64_t lo, hi;     // rows [lo, hi) of the first-level arrays
+};
+
+__device__ bool locate_tile2(const PartSide& s, int64_t bid, Tile2* out) {
+  __shared__ uint32_t scr[kBlk / kWave];
+  __shared__ int s_found;
+  __shared__ Tile2 s_t;
+  const uint32_t nb1 = 1u << s.b1;
+  const uint32_t c = threadIdx.x < nb1 ? s.tot1[threadIdx.x] : 0u;
+  const uint32_t ntile = (uint32_t)((c + kTile2 - 1) / kTile2);
+  uint32_t tot;
+  const uint32_t start = block_excl_scan<kBlk>(c, scr, &tot);
+  uint32_t tbase_tot;
+  const uint32_t tbase = block_excl_scan<kBlk>(ntile, scr, &tbase_tot);
+  if (threadIdx.x == 0) s_found = 0;
+  __syncthreads();
+  if (threadIdx.x < nb1 && bid >= tbase && bid < (int64_t)tbase + ntile) {
+    Tile2 t;
+    t.p = threadIdx.x;
+    t.p_start = start;
+    t.tile_in_p = (uint32_t)(bid - tbase);
+    t.lo = (int64_t)start + (int64_t)t.tile_in_p * kTile2;
+    const int64_t end = (int64_t)start + c;
+    t.hi = t.lo + kTile2 < end ? t.lo + kTile2 : end;
+    s_t = t;
+    s_found = 1;
+  }
+  __syncthreads();
+  *out = s_t;
+  return s_found != 0;
+}
+
+__global__ __launch_bounds__(kBlk) void k_p2_hist(PartSide s) {
+  __shared__ uint32_t h[kMaxBins];
+  Tile2 t;
+  if (!locate_tile2(s, blockIdx.x, &t)) return;
+  const uint32_t nb2 = 1u << s.b2, shift = 32u - s.b1 - s.b2, mask = nb2 - 1;
+  for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) h[b] = 0;
+  __syncthreads();
+  for (int64_t r = t.lo + threadIdx.x; r < t.hi; r += kBlk) atomicAdd(&h[(phash(s.key1[r]) >> shift) & mask], 1u);
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) s.hist2[(size_t)blockIdx.x * nb2 + b] = h[b];
+}
+
+// One workgroup per first-level partition p: per second-level bin, prefix over
+// p's tiles (in place) and the final partition starts/counts.
+__global__ __launch_bounds__(kBlk) void k_p2_scan(PartSide s) {
+  __shared__ uint32_t scr[kBlk / kWave];
+  const uint32_t nb1 = 1u << s.b1, nb2 = 1u << s.b2;
+  const uint32_t p = blockIdx.x;
+  const uint32_t c = threadIdx.x < nb1 ? s.tot1[threadIdx.x] : 0u;
+  const uint32_t ntile = (uint32_t)((c + kTile2 - 1) / kTile2);
+  uint32_t tot;
+  const uint32_t start = block_excl_scan<kBlk>(c, scr, &tot);
+  const uint32_t tbase = block_excl_scan<kBlk>(ntile, scr, &tot);
+  __shared__ uint32_t s_start, s_tbase, s_ntile;
+  if (threadIdx.x == p) {
+    s_start = start;
+    s_tbase = tbase;
+    s_ntile = ntile;
+  }
+  __syncthreads();
+  uint32_t bin_tot = 0;
+  if (threadIdx.x < nb2) {
+    for (uint32_t k = 0; k < s_ntile; ++k) {
+      uint32_t* cell = &s.hist2[(size_t)(s_tbase + k) * nb2 + threadIdx.x];
+      const uint32_t v = *cell;
+      *cell = bin_tot;
+      bin_tot += v;
+    }
+  }
+  const uint32_t ex = block_excl_scan<kBlk>(threadIdx.x < nb2 ? bin_tot : 0u, scr, &tot);
+  if (threadIdx.x < nb2) {
+    s.pstart[p * nb2 + threadIdx.x] = s_start + ex;
+    s.pcount[p * nb2 + threadIdx.x] = bin_tot;
+  }
+}
+
+template <bool FACT>
+__global__ __launch_bounds__(kBlk) void k_p2_scatter(PartSide s) {
+  __shared__ uint32_t cur[kMaxBins];
+  Tile2 t;
+  if (!locate_tile2(s, blockIdx.x, &t)) return;
+  const uint32_t nb2 = 1u << s.b2, shift = 32u - s.b1 - s.b2, mask = nb2 - 1;
+  for (uint32_t b = threadIdx.x; b < nb2; b += kBlk)
+    cur[b] = s.pstart[t.p * nb2 + b] + s.hist2[(size_t)blockIdx.x * nb2 + b];
+  __syncthreads();
+  // R rows per thread per step (strided by the workgroup, so each load
+  // instruction stays coalesced), all loaded before any is placed.
+  constexpr int R = 8;
+  const bool pay = !FACT && s.pkind != relh::PAY_NONE;
+  for (int64_t r = t.lo + threadIdx.x; r < t.hi; r += R * kBlk) {
+    int32_t ks[R], qs[R];
+    int64_t ps[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int64_t q = r + (int64_t)k * kBlk;
+      const bool ok = q < t.hi;
+      ks[k] = ok ? s.key1[q] : 0;
+      if (FACT) {
+        ps[k] = ok ? s.price1[q] : 0;
+        qs[k] = ok ? s.qty1[q] : 0;
+      } else {
+        qs[k] = (ok && pay) ? s.pay1[q] : 0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      if (r + (int64_t)k * kBlk >= t.hi) break;
+      const uint32_t pos = atomicAdd(&cur[(phash(ks[k]) >> shift) & mask], 1u);
+      s.key2[pos] = ks[k];
+      if (FACT) {
+        s.price2[pos] = ps[k];
+        s.qty2[pos] = qs[k];
+      } else if (pay) {
+        s.pay2[pos] = qs[k];
+      }
+    }
+  }
+}
+
+// ---- work units -----------------------------------------------------------------------------------------------------------
+
+// Units (partition, dim chunk) for partitions with both dim keys and fact
+// rows, ordered by decreasing size class of the fact-row count (largest first,
+// so skewed partitions start early). One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_make_units(const uint32_t* __restrict__ dcount, const uint32_t* __restrict__ fcount,
+                                                     uint32_t nparts, uint32_t* __restrict__ unit_part,
+                                                     uint32_t* __restrict__ unit_chunk, int64_t* __restrict__ n_units) {
+  __shared__ uint32_t cls_n[33];
+  __shared__ uint32_t cls_cur[33];
+  for (int c = threadIdx.x; c < 33; c += blockDim.x) cls_n[c] = 0;
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < nparts; p += blockDim.x) {
+    const uint32_t fc = fcount[p], dc = dcount[p];
+    if (fc == 0 || dc == 0) continue;
+    const uint32_t chunks = (dc + kJChunk - 1) / kJChunk;
+    atomicAdd(&cls_n[32 - __clz(fc)], chunks);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int c = 32; c >= 0; --c) {  // descending size class
+      cls_cur[c] = acc;
+      acc += cls_n[c];
+    }
+    *n_units = acc;
+  }
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < nparts; p += blockDim.x) {
+    const uint32_t fc = fcount[p], dc = dcount[p];
+    if (fc == 0 || dc == 0) continue;
+    const uint32_t chunks = (dc + kJChunk - 1) / kJChunk;
+    const uint32_t pos = atomicAdd(&cls_cur[32 - __clz(fc)], chunks);
+    for (uint32_t c = 0; c < chunks; ++c) {
+      unit_part[pos + c] = p;
+      unit_chunk[pos + c] = c;
+    }
+  }
+}
+
+// ---- partitioned groupjoin -------------------------------------------------------------------------------------------
+
+struct JoinArgs {
+  const uint32_t* unit_part;
+  const uint32_t* unit_chunk;
+  const int64_t* n_units;
+  const int32_t* dkey;
+  const uint32_t* dstart;
+  const uint32_t* dcount;
+  const int32_t* fkey;
+  const int64_t* fprice;
+  const int32_t* fqty;
+  const uint32_t* fstart;
+  const uint32_t* fcount;
+  uint64_t* state;
+  int64_t* ticket;
+  int64_t* matched;
+  uint32_t* status;
+  int64_t* out_key;
+  int64_t* out_sp;
+  int64_t* out_sq;
+  int64_t* out_cnt;
+  int64_t out_cap;
+  int64_t* d_n;
+};
+
+constexpr uint64_t kLdsEmpty = ~0ull;
+
+// Sum of a 64-bit value over the lanes of a wave (inactive contributions pass 0).
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, o, kWave);
+  return v;
+}
+
+__global__ __launch_bounds__(kJBlock) void k_part_groupjoin(JoinArgs a) {
+  __shared__ uint64_t tkey[kJSlots];  // {key, 1} packed; all ones = empty
+  __shared__ uint32_t tcnt[kJSlots];
+  __shared__ uint64_t tsp[kJSlots];
+  __shared__ uint64_t tsq[kJSlots];
+  __shared__ uint32_t scr[kJBlock / kWave];
+  __shared__ int64_t s_unit;
+  __shared__ uint64_t s_excl;
+  const int64_t n_units = *a.n_units;
+  const uint32_t lane = lane_id();
+  uint64_t matched = 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_unit = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)a.ticket, 1ull);
+    __syncthreads();
+    const int64_t u = s_unit;
+    if (u >= n_units) break;
+    const uint32_t p = a.unit_part[u], chunk = a.unit_chunk[u];
+    const uint32_t dlo = a.dstart[p] + chunk * (uint32_t)kJChunk;
+    const uint32_t dend = a.dstart[p] + a.dcount[p];
+    const uint32_t dhi = dlo + kJChunk < dend ? dlo + kJChunk : dend;
+    const uint32_t flo = a.fstart[p], fhi = flo + a.fcount[p];
+
+    for (int s = threadIdx.x; s < kJSlots; s += kJBlock) {
+      tkey[s] = kLdsEmpty;
+      tcnt[s] = 0;
+      tsp[s] = 0;
+      tsq[s] = 0;
+    }
+    __syncthreads();
+    // build: at most kJChunk unique keys into kJSlots slots, so a free slot always exists
+    for (uint32_t j = dlo + threadIdx.x; j < dhi; j += kJBlock) {
+      const int32_t key = a.dkey[j];
+      const uint64_t want = (uint64_t)(uint32_t)key | (1ull << 32);
+      uint32_t h = slot_hash(key);
+      for (int step = 0; step < kJSlots; ++step) {
+        const uint64_t old = atomicCAS((unsigned long long*)&tkey[h], (unsigned long long)kLdsEmpty, (unsigned long long)want);
+        if (old == kLdsEmpty) break;
+        if (old == want) {
+          set_status(a.status, kDevDupKey);
+          break;
+        }
+        h = (h + 1) & (kJSlots - 1);
+      }
+    }
+    __syncthreads();
+    // probe and aggregate in LDS: R rows per thread per step, loaded together
+    constexpr int R = 4;
+    const uint32_t nrows = fhi - flo;
+    const uint32_t iters = (nrows + R * kJBlock - 1) / (R * kJBlock);  // uniform over the workgroup
+    for (uint32_t it = 0; it < iters; ++it) {
+      const uint32_t i0 = flo + it * (R * kJBlock) + threadIdx.x;
+      int32_t keys[R];
+      uint64_t sps[R], sqs[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const uint32_t i = i0 + k * kJBlock;
+        const bool ok = i < fhi;
+        keys[k] = ok ? a.fkey[i] : 0;
+        sps[k] = ok ? (uint64_t)a.fprice[i] : 0;
+        sqs[k] = ok ? (uint64_t)(int64_t)a.fqty[i] : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        bool found = false;
+        int slot = 0;
+        if (i0 + k * kJBlock < fhi) {
+          const uint64_t want = (uint64_t)(uint32_t)keys[k] | (1ull << 32);
+          uint32_t h = slot_hash(keys[k]);
+          for (int step = 0; step < kJSlots; ++step) {
+            const uint64_t cur = tkey[h];
+            if (cur == want) {
+              found = true;
+              slot = (int)h;
+              break;
+            }
+            if (cur == kLdsEmpty) break;
+            h = (h + 1) & (kJSlots - 1);
+          }
+        }
+        matched += found;
+        // Hot keys: when many lanes of the wave hit one slot, pre-sum them so the
+        // LDS sees one update instead of a serialised run of same-address atomics.
+        const uint64_t act = wave_ballot(found);
+        if (act == 0) continue;
+        const int first = __ffsll((long long)act) - 1;
+        const int s0 = __shfl(slot, first, kWave);
+        const uint64_t same = wave_ballot(found && slot == s0);
+        if (__popcll(same) >= kCombineMin) {
+          const bool mine = found && slot == s0;
+          const uint64_t tsum_p = wave_sum_u64(mine ? sps[k] : 0);
+          const uint64_t tsum_q = wave_sum_u64(mine ? sqs[k] : 0);
+          if ((int)lane == first) {
+            atomicAdd((unsigned long long*)&tsp[s0], (unsigned long long)tsum_p);
+            atomicAdd((unsigned long long*)&tsq[s0], (unsigned long long)tsum_q);
+            atomicAdd(&tcnt[s0], (uint32_t)__popcll(same));
+          }
+          found = found && !mine;
+        }
+        if (found) {
+          atomicAdd((unsigned long long*)&tsp[slot], (unsigned long long)sps[k]);
+          atomicAdd((unsigned long long*)&tsq[slot], (unsigned long long)sqs[k]);
+          atomicAdd(&tcnt[slot], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    // Emit the unit's groups. Output room is reserved with one atomic per unit,
+    // taken when the unit finishes, so no unit waits on another.
+    constexpr int kPer = kJSlots / kJBlock;
+    uint32_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) mine += tcnt[threadIdx.x * kPer + k] != 0;
+    uint32_t total;
+    const uint32_t off = block_excl_scan<kJBlock>(mine, scr, &total);
+    if (threadIdx.x == 0)
+      s_excl = total ? dev_add_ret<unsigned long long>((unsigned long long*)a.d_n, (unsigned long long)total) : 0;
+    __syncthreads();
+    int64_t o = (int64_t)s_excl + off;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int s = threadIdx.x * kPer + k;
+      const uint32_t c = tcnt[s];
+      if (c == 0) continue;
+      if (o < a.out_cap) {
+        a.out_key[o] = (int64_t)(int32_t)(uint32_t)tkey[s];
+        a.out_sp[o] = (int64_t)tsp[s];
+        a.out_sq[o] = (int64_t)tsq[s];
+        a.out_cnt[o] = (int64_t)c;
+      } else {
+        set_status(a.status, kDevOverflow);
+      }
+      ++o;
+    }
+    __syncthreads();
+  }
+  matched = wave_sum_u64(matched);
+  if (lane == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
+}
+
+#define TRY(x)                   \
+  do {                           \
+    rel_status s_ = (x);         \
+    if (s_ != REL_OK) return s_; \
+  } while (0)
+
+rel_status partition_side(rel_ctx* ctx, PartSide& s, bool fact, int64_t* passed) {
+  const uint32_t nb1 = 1u << s.b1;
+  const int64_t ntiles1 = (s.n + kTile1 - 1) / kTile1;
+  const dim3 g1((unsigned)ntiles1), blk(kBlk);
+  if (s.n > 0) {
+    {
+      relh::KernelTimer kt(ctx, fact ? "fact_p1_hist" : "dim_p1_hist");
+      if (fact) hipLaunchKernelGGL(k_p1_hist<true>, g1, blk, 0, ctx->stream, s);
+      else hipLaunchKernelGGL(k_p1_hist<false>, g1, blk, 0, ctx->stream, s);
+    }
+    {
+      relh::KernelTimer kt(ctx, fact ? "fact_p1_colscan" : "dim_p1_colscan");
+      hipLaunchKernelGGL(k_p1_colscan, dim3(nb1), blk, 0, ctx->stream, s.hist1, ntiles1, nb1, s.tot1, passed);
+    }
+    {
+      relh::KernelTimer kt(ctx, fact ? "fact_p1_scatter" : "dim_p1_scatter");
+      if (fact) hipLaunchKernelGGL(k_p1_scatter<true>, g1, blk, 0, ctx->stream, s);
+      else hipLaunchKernelGGL(k_p1_scatter<false>, g1, blk, 0, ctx->stream, s);
+    }
+  } else {
+    TRY(relh::fill_u32(ctx, s.tot1, nb1, 0));
+  }
+  REL_LAUNCH_CHECK(ctx, "partition level 1");
+  // upper bound of second-level tiles: sum over partitions of ceil(c_p / kTile2)
+  const dim3 g2((unsigned)(s.n / kTile2 + nb1));
+  {
+    relh::KernelTimer kt(ctx, fact ? "fact_p2_hist" : "dim_p2_hist");
+    hipLaunchKernelGGL(k_p2_hist, g2, blk, 0, ctx->stream, s);
+  }
+  {
+    relh::KernelTimer kt(ctx, fact ? "fact_p2_scan" : "dim_p2_scan");
+    hipLaunchKernelGGL(k_p2_scan, dim3(nb1), blk, 0, ctx->stream, s);
+  }
+  {
+    relh::KernelTimer kt(ctx, fact ? "fact_p2_scatter" : "dim_p2_scatter");
+    if (fact) hipLaunchKernelGGL(k_p2_scatter<true>, g2, blk, 0, ctx->stream, s);
+    else hipLaunchKernelGGL(k_p2_scatter<false>, g2, blk, 0, ctx->stream, s);
+  }
+  REL_LAUNCH_CHECK(ctx, "partition level 2");
+  return REL_OK;
+}
+
+// Carve a scratch buffer into aligned pieces.
+struct Carver {
+  char* p;
+  size_t used = 0;
+  template <class T>
+  T* take(size_t count) {
+    used = (used + 255) & ~size_t(255);
+    T* r = reinterpret_cast<T*>(p + used);
+    used += count * sizeof(T);
+    return r;
+  }
+};
+
+void split_bits(int64_t m, uint32_t* b1, uint32_t* b2) {
+  // about 1000 dim keys per final partition, split over two levels of at most 8 bits
+  uint32_t pb = 0;
+  while (pb < 16 && (m >> pb) > 1000) ++pb;
+  if (pb < 2) pb = 2;
+  *b1 = (pb + 1) / 2;
+  *b2 = pb - *b1;
+}
+
+}  // namespace
+
+namespace relh {
+
+bool partitioned_supported(int64_t n, int64_t m) { return n < (1ll << 31) && m < (1ll << 30); }
+
+// GROUP BY fk over fact JOIN dim ON fk = pk, WHERE day < day_lt, radix-partitioned.
+rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, int32_t day_lt,
+                                 rel_groups_out* out, int64_t* counters) {
+  const int64_t n = fact->n, m = dim->m;
+  uint32_t b1, b2;
+  split_bits(m, &b1, &b2);
+  const uint32_t nb1 = 1u << b1, nb2 = 1u << b2, nparts = nb1 * nb2;
+  const int64_t fnt1 = (n + kTile1 - 1) / kTile1, dnt1 = (m + kTile1 - 1) / kTile1;
+  const int64_t fnt2 = n / kTile2 + nb1, dnt2 = m / kTile2 + nb1;
+  const int64_t max_units = (int64_t)nparts + m / kJChunk + 1;
+
+  // scratch: partitioned columns (A: fact level 1, B: fact level 2, C: dim both levels), bookkeeping (D)
+  void *pa, *pb, *pc, *pd;
+  const size_t fact_bytes = (size_t)(n > 0 ? n : 1) * 16 + 4 * 256;
+  TRY(scratch(ctx, SCR_PART_A, fact_bytes, &pa));
+  TRY(scratch(ctx, SCR_PART_B, fact_bytes, &pb));
+  TRY(scratch(ctx, SCR_PART_C, (size_t)(m > 0 ? m : 1) * 16 + 4 * 256, &pc));
+  const size_t book = ((size_t)fnt1 * nb1 + (size_t)dnt1 * nb1 + (size_t)fnt2 * nb2 + (size_t)dnt2 * nb2 + 2 * nb1 +
+                       4 * (size_t)nparts + 2 * (size_t)max_units) * 4 + (size_t)max_units * 8 + 64 * 256;
+  TRY(scratch(ctx, SCR_PART_D, book, &pd));
+
+  PartSide F{};
+  F.key = fact->fk;
+  F.day = fact->day;
+  F.price = fact->price_cents;
+  F.qty = fact->qty;
+  F.day_lt = day_lt;
+  F.n = n;
+  F.b1 = b1;
+  F.b2 = b2;
+  Carver ca{(char*)pa}, cb{(char*)pb}, cc{(char*)pc}, cd{(char*)pd};
+  F.key1 = ca.take<int32_t>(n);
+  F.qty1 = ca.take<int32_t>(n);
+  F.price1 = ca.take<int64_t>(n);
+  F.key2 = cb.take<int32_t>(n);
+  F.qty2 = cb.take<int32_t>(n);
+  F.price2 = cb.take<int64_t>(n);
+  F.hist1 = cd.take<uint32_t>((size_t)fnt1 * nb1);
+  F.tot1 = cd.take<uint32_t>(nb1);
+  F.hist2 = cd.take<uint32_t>((size_t)fnt2 * nb2);
+  F.pstart = cd.take<uint32_t>(nparts);
+  F.pcount = cd.take<uint32_t>(nparts);
+
+  PartSide D{};
+  D.key = dim->pk;
+  D.pkind = PAY_NONE;  // the group key is the join key: no dim payload travels
+  D.n = m;
+  D.b1 = b1;
+  D.b2 = b2;
+  D.key1 = cc.take<int32_t>(m);
+  D.pay1 = cc.take<int32_t>(m);
+  D.key2 = cc.take<int32_t>(m);
+  D.pay2 = cc.take<int32_t>(m);
+  D.hist1 = cd.take<uint32_t>((size_t)dnt1 * nb1);
+  D.tot1 = cd.take<uint32_t>(nb1);
+  D.hist2 = cd.take<uint32_t>((size_t)dnt2 * nb2);
+  D.pstart = cd.take<uint32_t>(nparts);
+  D.pcount = cd.take<uint32_t>(nparts);
+
+  uint32_t* unit_part = cd.take<uint32_t>(max_units);
+  uint32_t* unit_chunk = cd.take<uint32_t>(max_units);
+  uint64_t* state = cd.take<uint64_t>(max_units);
+  int64_t* n_units = counters + CNT_AUX0;
+  int64_t* ticket = counters + CNT_TICKET;
+
+  TRY(partition_side(ctx, D, false, nullptr));
+  TRY(partition_side(ctx, F, true, counters + CNT_ROWS_PASSED));
+
+  {
+    {
+      KernelTimer kt(ctx, "make_units");
+      hipLaunchKernelGGL(k_make_units, dim3(1), dim3(1024), 0, ctx->stream, D.pcount, F.pcount, nparts, unit_part,
+                         unit_chunk, n_units);
+    }
+    REL_LAUNCH_CHECK(ctx, "make_units");
+    TRY(fill_u64(ctx, ticket, 1, 0));
+    TRY(fill_u64(ctx, out->d_n_groups, 1, 0));
+    KernelTimer kt(ctx, "part_groupjoin");
+    JoinArgs a{};
+    a.unit_part = unit_part;
+    a.unit_chunk = unit_chunk;
+    a.n_units = n_units;
+    a.dkey = D.key2;
+    a.dstart = D.pstart;
+    a.dcount = D.pcount;
+    a.fkey = F.key2;
+    a.fprice = F.price2;
+    a.fqty = F.qty2;
+    a.fstart = F.pstart;
+    a.fcount = F.pcount;
+    a.state = state;
+    a.ticket = ticket;
+    a.matched = counters + CNT_JOIN_MATCHES;
+    a.status = ctx->d_status;
+    a.out_key = out->key;
+    a.out_sp = out->sum_price;
+    a.out_sq = out->sum_qty;
+    a.out_cnt = out->count;
+    a.out_cap = out->cap;
+    a.d_n = out->d_n_groups;
+    const unsigned grid = (unsigned)ctx->num_cus * 2;
+    hipLaunchKernelGGL(k_part_groupjoin, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
+    REL_LAUNCH_CHECK(ctx, "part_groupjoin");
+  }
+  return REL_OK;
+}
+
+}  // namespace relh

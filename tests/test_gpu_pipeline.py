@@ -206,3 +206,62 @@ def test_invalid_arguments_are_rejected(ctx):
     with pytest.raises(rel.RelError) as e:
         ctx.filter_compact(x[1:], "lt", 3)  # 4-byte offset: misaligned column
     assert e.value.status == rel.INVALID_ARG
+
+
+# -- radix-partitioned groupjoin ------------------------------------------------------------------------------------------
+
+def _partitioned():
+    return rel.Plan(group_capacity=0, group_placement=0, join_placement=rel.PLACE["partitioned"], allow_fallback=0)
+
+
+def _same_partition_keys(count: int, top16: int) -> np.ndarray:
+    """Distinct int32 keys whose multiplicative hash (key * 2654435769 mod 2^32)
+    shares its top 16 bits, so they all land in one partition at any depth <= 16."""
+    inv = pow(2654435769, -1, 2 ** 32)
+    h = (np.uint64(top16) << np.uint64(16)) | np.arange(count, dtype=np.uint64)
+    return ((h * np.uint64(inv)) & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.int32)
+
+
+@pytest.mark.parametrize("n,m,zipf", [(1, 1, 0.0), (1000, 17, 0.0), (100_003, 25_001, 0.0), (2_000_000, 500_000, 1.2),
+                                      (3_000_000, 700_000, 0.8)])
+def test_partitioned_groupjoin(ctx, n, m, zipf):
+    T = datagen.make_tables(n, m, 500 + n, day_lt=1200, group_by="fk", fk_zipf=zipf, fk_domain=m + m // 5)
+    st = run_both(ctx, T, plan=_partitioned(), repeats=2)
+    assert st["join_placement"] == "partitioned"
+
+
+def test_partitioned_oversized_partition_is_chunked(ctx):
+    # 3000 keys in one partition exceed one LDS chunk (1400 keys): the partition
+    # is processed as several units that each see all of its fact rows.
+    hot = _same_partition_keys(3000, 0x1234)
+    rest = datagen.permutation(2000, 1_000_000, 6, 1)
+    pk = np.concatenate([hot, rest]).astype(np.int32)
+    T = datagen.make_tables(400_000, pk.shape[0], 61, day_lt=1800, group_by="fk")
+    T.pk = pk
+    T.fk = pk[datagen.uniform(T.n, 0, pk.shape[0] - 1, np.int64, 61, 77)]
+    T.fk[::7] = 5  # a key that is not in the dim table
+    run_both(ctx, T, plan=_partitioned())
+
+
+@pytest.mark.parametrize("case", ["empty_fact", "empty_dim", "all_filtered", "no_match"])
+def test_partitioned_degenerate(ctx, case):
+    n, m = (0 if case == "empty_fact" else 50_000), (0 if case == "empty_dim" else 9_000)
+    T = datagen.make_tables(n, m, 8, day_lt=0 if case == "all_filtered" else 1800, group_by="fk")
+    if case == "no_match":
+        T.fk = T.fk + 100_000
+    run_both(ctx, T, plan=_partitioned())
+
+
+def test_partitioned_duplicate_pk_reported(ctx):
+    T = datagen.make_tables(10_000, 1000, 3, group_by="fk")
+    T.pk[7] = T.pk[8]
+    fact, dim = to_dev(T)
+    with pytest.raises(rel.RelError) as e:
+        ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, plan=_partitioned())
+    assert e.value.status == rel.DUPLICATE_KEY
+
+
+def test_auto_picks_partitioned_for_large_fk_grouping(ctx):
+    T = datagen.large(seed=34, n=2_000_000, m=500_000)
+    st = run_both(ctx, T)
+    assert st["join_placement"] == "partitioned"
