@@ -31,6 +31,19 @@ __device__ __forceinline__ uint32_t hash64(int64_t key, uint32_t shift) {
 
 __device__ __forceinline__ uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
+// with a private L2. This bijection on [0, G) hands XCD x (the workgroups b
+// with b % 8 == x) one contiguous range of tiles, so the writes of adjacent
+// tiles, which meet inside the same cache lines, are merged in one L2 instead
+// of being written back as partial lines by two. Correctness never depends
+// on the dispatch order; only locality does.
+constexpr uint32_t kNumXcd = 8;
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t G) {
+  const uint32_t x = b % kNumXcd, i = b / kNumXcd;
+  const uint32_t q = G / kNumXcd, r = G % kNumXcd;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // Number of set bits of a wave mask below this lane.
 __device__ __forceinline__ uint32_t mask_rank(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));

@@ -14,8 +14,8 @@
 //   2. per first-level partition, the same on the next B2 bits.
 // Then one work unit per (partition, chunk of at most kJChunk dim keys),
 // ordered by decreasing fact-row count, builds an LDS table, streams the
-// partition's fact rows through it, and emits its groups at an offset found
-// by decoupled look-back over the unit order.
+// partition's fact rows through it, and appends its groups to the output
+// with one atomic offset reservation per unit.
 #include "rel_device.h"
 #include "rel_host.h"
 #include "rel_ops.h"
@@ -25,8 +25,8 @@ namespace {
 using namespace rel;
 
 constexpr int kBlk = 256;
-constexpr int64_t kTile1 = 16384;  // input rows per first-level tile
-constexpr int64_t kTile2 = 16384;  // partition rows per second-level tile
+constexpr int64_t kTile1 = 4096;  // input rows per first-level tile (staged in LDS)
+constexpr int64_t kTile2 = 4096;  // partition rows per second-level tile
 constexpr int kMaxBins = 256;
 constexpr int kJBlock = 512;
 constexpr int kJSlotBits = 11;
@@ -80,7 +80,8 @@ __global__ __launch_bounds__(kBlk) void k_p1_hist(PartSide s) {
   const uint32_t nb1 = 1u << s.b1, shift = 32u - s.b1;
   for (uint32_t b = threadIdx.x; b < nb1; b += kBlk) h[b] = 0;
   __syncthreads();
-  const int64_t r0 = blockIdx.x * kTile1;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t r0 = tile * kTile1;
   const int64_t r1 = r0 + kTile1 < s.n ? r0 + kTile1 : s.n;
   for (int64_t r = r0 + 4 * threadIdx.x; r < r1; r += 4 * kBlk) {
     if (r + 4 <= r1) {
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(kBlk) void k_p1_hist(PartSide s) {
     }
   }
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < nb1; b += kBlk) s.hist1[(size_t)blockIdx.x * nb1 + b] = h[b];
+  for (uint32_t b = threadIdx.x; b < nb1; b += kBlk) s.hist1[(size_t)tile * nb1 + b] = h[b];
 }
 
 // Column b of hist1 (one bin over all tiles) -> exclusive prefix in place; tot1[b] = column sum.
@@ -121,80 +122,111 @@ __global__ __launch_bounds__(kBlk) void k_p1_colscan(uint32_t* __restrict__ hist
   }
 }
 
+// ---- LDS-staged scatter ------------------------------------------------------------------------------------------------
+//
+// Writing each row straight to its partition from the lane that holds it puts
+// 64 lanes' stores on up to 64 different cache lines; partly written lines
+// are then evicted and written back several times over. Instead a tile's rows
+// are first counting-sorted by partition in LDS, then each partition's run is
+// written by consecutive lanes to consecutive addresses. With tiles of one
+// XCD kept contiguous (xcd_tile), the runs of neighbouring tiles meet inside
+// the same L2, and written bytes stay close to the payload.
+
+constexpr int kRowsPerThread = (int)(kTile1 / kBlk);
+static_assert(kTile1 == kTile2, "both levels stage tiles of one size");
+
 template <bool FACT>
-__device__ __forceinline__ void p1_put(const PartSide& s, int64_t r, int32_t key, uint32_t pos) {
-  s.key1[pos] = key;
-  if (FACT) {
-    s.price1[pos] = s.price[r];
-    s.qty1[pos] = s.qty[r];
-  } else if (s.pkind != relh::PAY_NONE) {
-    s.pay1[pos] = s.pkind == relh::PAY_ROW_ID ? (int32_t)r
-                  : s.pkind == relh::PAY_I32  ? ((const int32_t*)s.payload)[r]
-                                              : (int32_t)((const int8_t*)s.payload)[r];
+struct Stage {
+  uint32_t lcnt[kMaxBins];
+  uint32_t lbase[kMaxBins];
+  uint32_t gbase[kMaxBins];
+  uint32_t scr[kBlk / kWave];
+  int32_t key[kTile1];
+  int64_t price[FACT ? kTile1 : 1];
+  int32_t val[kTile1];  // qty (fact) or payload (dim)
+  uint8_t bin[kTile1];
+};
+
+// Rows this thread holds: valid[k], key[k], price[k], val[k], bin[k]. Sorts
+// the workgroup's rows by bin in LDS and writes them to dst at
+// st.gbase[bin] + rank within the bin. st.gbase must be set and visible.
+template <bool FACT, int R>
+__device__ __forceinline__ void stage_and_write(Stage<FACT>& st, const bool (&valid)[R], const int32_t (&key)[R],
+                                                const int64_t (&price)[R], const int32_t (&val)[R],
+                                                const uint32_t (&bin)[R], uint32_t nb, bool with_val, int32_t* dkey,
+                                                int64_t* dprice, int32_t* dval) {
+  for (uint32_t b = threadIdx.x; b < nb; b += kBlk) st.lcnt[b] = 0;
+  __syncthreads();
+  uint32_t rank[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) rank[k] = valid[k] ? atomicAdd(&st.lcnt[bin[k]], 1u) : 0u;
+  __syncthreads();
+  uint32_t total;
+  const uint32_t lb = block_excl_scan<kBlk>(threadIdx.x < nb ? st.lcnt[threadIdx.x] : 0u, st.scr, &total);
+  if (threadIdx.x < nb) st.lbase[threadIdx.x] = lb;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (!valid[k]) continue;
+    const uint32_t slot = st.lbase[bin[k]] + rank[k];
+    st.key[slot] = key[k];
+    if (FACT) st.price[slot] = price[k];
+    st.val[slot] = val[k];
+    st.bin[slot] = (uint8_t)bin[k];
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < total; j += kBlk) {
+    const uint32_t b = st.bin[j];
+    const uint32_t pos = st.gbase[b] + (j - st.lbase[b]);
+    dkey[pos] = st.key[j];
+    if (FACT) {
+      dprice[pos] = st.price[j];
+      dval[pos] = st.val[j];
+    } else if (with_val) {
+      dval[pos] = st.val[j];
+    }
   }
 }
 
 template <bool FACT>
 __global__ __launch_bounds__(kBlk) void k_p1_scatter(PartSide s) {
-  __shared__ uint32_t cur[kMaxBins];
-  __shared__ uint32_t scr[kBlk / kWave];
+  __shared__ Stage<FACT> st;
   const uint32_t nb1 = 1u << s.b1, shift = 32u - s.b1;
   // partition starts: exclusive scan of the bin totals (nb1 <= kBlk)
-  const uint32_t v = threadIdx.x < nb1 ? s.tot1[threadIdx.x] : 0u;
   uint32_t tot;
-  const uint32_t base = block_excl_scan<kBlk>(v, scr, &tot);
-  if (threadIdx.x < nb1) cur[threadIdx.x] = base + s.hist1[(size_t)blockIdx.x * nb1 + threadIdx.x];
-  __syncthreads();
-  const int64_t r0 = blockIdx.x * kTile1;
+  const uint32_t base = block_excl_scan<kBlk>(threadIdx.x < nb1 ? s.tot1[threadIdx.x] : 0u, st.scr, &tot);
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (threadIdx.x < nb1) st.gbase[threadIdx.x] = base + s.hist1[(size_t)tile * nb1 + threadIdx.x];
+  const int64_t r0 = tile * kTile1;
   const int64_t r1 = r0 + kTile1 < s.n ? r0 + kTile1 : s.n;
-  // Eight consecutive rows per thread per step. Every column of the eight rows
-  // is loaded before any row is placed, so the loads overlap each other
-  // instead of each waiting behind the previous row's LDS atomic and stores.
-  constexpr int R = 8;
-  for (int64_t r = r0 + R * threadIdx.x; r < r1; r += R * kBlk) {
-    if (r + R <= r1) {
-      int32_t ks[R], ds[R], qs[R], ps32[R];
-      int64_t ps[R];
+  constexpr int R = kRowsPerThread;
+  bool valid[R];
+  int32_t key[R], val[R];
+  int64_t price[R];
+  uint32_t bin[R];
+  // all loads first (strided by the workgroup, so every load is coalesced)
 #pragma unroll
-      for (int v = 0; v < R / 4; ++v) {
-        const int4 kv = *reinterpret_cast<const int4*>(s.key + r + 4 * v);
-        ks[4 * v] = kv.x; ks[4 * v + 1] = kv.y; ks[4 * v + 2] = kv.z; ks[4 * v + 3] = kv.w;
-        if (FACT) {
-          const int4 dv = *reinterpret_cast<const int4*>(s.day + r + 4 * v);
-          const int4 qv = *reinterpret_cast<const int4*>(s.qty + r + 4 * v);
-          const longlong2 pa = *reinterpret_cast<const longlong2*>(s.price + r + 4 * v);
-          const longlong2 pb = *reinterpret_cast<const longlong2*>(s.price + r + 4 * v + 2);
-          ds[4 * v] = dv.x; ds[4 * v + 1] = dv.y; ds[4 * v + 2] = dv.z; ds[4 * v + 3] = dv.w;
-          qs[4 * v] = qv.x; qs[4 * v + 1] = qv.y; qs[4 * v + 2] = qv.z; qs[4 * v + 3] = qv.w;
-          ps[4 * v] = pa.x; ps[4 * v + 1] = pa.y; ps[4 * v + 2] = pb.x; ps[4 * v + 3] = pb.y;
-        } else {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int64_t q = r + 4 * v + k;
-            ps32[4 * v + k] = s.pkind == relh::PAY_ROW_ID ? (int32_t)q
-                              : s.pkind == relh::PAY_I32  ? ((const int32_t*)s.payload)[q]
-                              : s.pkind == relh::PAY_I8   ? (int32_t)((const int8_t*)s.payload)[q]
-                                                          : 0;
-          }
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < R; ++k) {
-        if (FACT && !(ds[k] < s.day_lt)) continue;
-        const uint32_t pos = atomicAdd(&cur[phash(ks[k]) >> shift], 1u);
-        s.key1[pos] = ks[k];
-        if (FACT) {
-          s.price1[pos] = ps[k];
-          s.qty1[pos] = qs[k];
-        } else if (s.pkind != relh::PAY_NONE) {
-          s.pay1[pos] = ps32[k];
-        }
-      }
+  for (int k = 0; k < R; ++k) {
+    const int64_t q = r0 + threadIdx.x + (int64_t)k * kBlk;
+    const bool in = q < r1;
+    key[k] = in ? s.key[q] : 0;
+    if (FACT) {
+      valid[k] = in && s.day[q] < s.day_lt;
+      price[k] = in ? s.price[q] : 0;
+      val[k] = in ? s.qty[q] : 0;
     } else {
-      for (int64_t q = r; q < r1; ++q)
-        if (row_passes<FACT>(s, q)) p1_put<FACT>(s, q, s.key[q], atomicAdd(&cur[phash(s.key[q]) >> shift], 1u));
+      valid[k] = in;
+      price[k] = 0;
+      val[k] = !in                          ? 0
+               : s.pkind == relh::PAY_ROW_ID ? (int32_t)q
+               : s.pkind == relh::PAY_I32    ? ((const int32_t*)s.payload)[q]
+               : s.pkind == relh::PAY_I8     ? (int32_t)((const int8_t*)s.payload)[q]
+                                             : 0;
     }
+    bin[k] = phash(key[k]) >> shift;
   }
+  stage_and_write<FACT, R>(st, valid, key, price, val, bin, nb1, s.pkind != relh::PAY_NONE, s.key1, s.price1,
+                           FACT ? s.qty1 : s.pay1);
 }
 
 // ---- second level ------------------------------------------------------------------------------------------------------
@@ -241,13 +273,14 @@ __device__ bool locate_tile2(const PartSide& s, int64_t bid, Tile2* out) {
 __global__ __launch_bounds__(kBlk) void k_p2_hist(PartSide s) {
   __shared__ uint32_t h[kMaxBins];
   Tile2 t;
-  if (!locate_tile2(s, blockIdx.x, &t)) return;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (!locate_tile2(s, tile, &t)) return;
   const uint32_t nb2 = 1u << s.b2, shift = 32u - s.b1 - s.b2, mask = nb2 - 1;
   for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) h[b] = 0;
   __syncthreads();
   for (int64_t r = t.lo + threadIdx.x; r < t.hi; r += kBlk) atomicAdd(&h[(phash(s.key1[r]) >> shift) & mask], 1u);
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) s.hist2[(size_t)blockIdx.x * nb2 + b] = h[b];
+  for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) s.hist2[(size_t)tile * nb2 + b] = h[b];
 }
 
 // One workgroup per first-level partition p: per second-level bin, prefix over
@@ -286,45 +319,28 @@ __global__ __launch_bounds__(kBlk) void k_p2_scan(PartSide s) {
 
 template <bool FACT>
 __global__ __launch_bounds__(kBlk) void k_p2_scatter(PartSide s) {
-  __shared__ uint32_t cur[kMaxBins];
+  __shared__ Stage<FACT> st;
   Tile2 t;
-  if (!locate_tile2(s, blockIdx.x, &t)) return;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (!locate_tile2(s, tile, &t)) return;
   const uint32_t nb2 = 1u << s.b2, shift = 32u - s.b1 - s.b2, mask = nb2 - 1;
-  for (uint32_t b = threadIdx.x; b < nb2; b += kBlk)
-    cur[b] = s.pstart[t.p * nb2 + b] + s.hist2[(size_t)blockIdx.x * nb2 + b];
-  __syncthreads();
-  // R rows per thread per step (strided by the workgroup, so each load
-  // instruction stays coalesced), all loaded before any is placed.
-  constexpr int R = 8;
+  for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) st.gbase[b] = s.pstart[t.p * nb2 + b] + s.hist2[(size_t)tile * nb2 + b];
   const bool pay = !FACT && s.pkind != relh::PAY_NONE;
-  for (int64_t r = t.lo + threadIdx.x; r < t.hi; r += R * kBlk) {
-    int32_t ks[R], qs[R];
-    int64_t ps[R];
+  constexpr int R = kRowsPerThread;
+  bool valid[R];
+  int32_t key[R], val[R];
+  int64_t price[R];
+  uint32_t bin[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const int64_t q = r + (int64_t)k * kBlk;
-      const bool ok = q < t.hi;
-      ks[k] = ok ? s.key1[q] : 0;
-      if (FACT) {
-        ps[k] = ok ? s.price1[q] : 0;
-        qs[k] = ok ? s.qty1[q] : 0;
-      } else {
-        qs[k] = (ok && pay) ? s.pay1[q] : 0;
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      if (r + (int64_t)k * kBlk >= t.hi) break;
-      const uint32_t pos = atomicAdd(&cur[(phash(ks[k]) >> shift) & mask], 1u);
-      s.key2[pos] = ks[k];
-      if (FACT) {
-        s.price2[pos] = ps[k];
-        s.qty2[pos] = qs[k];
-      } else if (pay) {
-        s.pay2[pos] = qs[k];
-      }
-    }
+  for (int k = 0; k < R; ++k) {
+    const int64_t q = t.lo + threadIdx.x + (int64_t)k * kBlk;
+    valid[k] = q < t.hi;
+    key[k] = valid[k] ? s.key1[q] : 0;
+    price[k] = (FACT && valid[k]) ? s.price1[q] : 0;
+    val[k] = !valid[k] ? 0 : FACT ? s.qty1[q] : pay ? s.pay1[q] : 0;
+    bin[k] = (phash(key[k]) >> shift) & mask;
   }
+  stage_and_write<FACT, R>(st, valid, key, price, val, bin, nb2, pay, s.key2, s.price2, FACT ? s.qty2 : s.pay2);
 }
 
 // ---- work units -----------------------------------------------------------------------------------------------------------
@@ -395,6 +411,23 @@ struct JoinArgs {
 
 constexpr uint64_t kLdsEmpty = ~0ull;
 
+// Row ranges of one unit: dim keys [dlo, dhi) of its chunk, fact rows [flo, fhi).
+struct UnitBounds {
+  uint32_t dlo, dhi, flo, fhi;
+};
+
+__device__ __forceinline__ UnitBounds unit_bounds(const JoinArgs& a, int64_t u, int64_t n_units) {
+  UnitBounds b{0, 0, 0, 0};
+  if (u >= n_units) return b;
+  const uint32_t p = a.unit_part[u], chunk = a.unit_chunk[u];
+  const uint32_t ds = a.dstart[p], dend = ds + a.dcount[p];
+  b.dlo = ds + chunk * (uint32_t)kJChunk;
+  b.dhi = b.dlo + kJChunk < dend ? b.dlo + kJChunk : dend;
+  b.flo = a.fstart[p];
+  b.fhi = b.flo + a.fcount[p];
+  return b;
+}
+
 // Sum of a 64-bit value over the lanes of a wave (inactive contributions pass 0).
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
@@ -408,22 +441,51 @@ __global__ __launch_bounds__(kJBlock) void k_part_groupjoin(JoinArgs a) {
   __shared__ uint64_t tsp[kJSlots];
   __shared__ uint64_t tsq[kJSlots];
   __shared__ uint32_t scr[kJBlock / kWave];
-  __shared__ int64_t s_unit;
   __shared__ uint64_t s_excl;
   const int64_t n_units = *a.n_units;
   const uint32_t lane = lane_id();
   uint64_t matched = 0;
+  // Units are taken from the largest-first list by ticket (dynamic, so a
+  // workgroup stuck on a skewed partition takes fewer units). The ticket and
+  // bounds of the next unit are fetched one unit ahead by thread 0, and each
+  // unit loads its dim keys and first fact rows together, so a unit waits on
+  // one memory round trip before its LDS work.
+  __shared__ UnitBounds s_cur, s_nxt;
+  __shared__ int64_t s_nxt_u;
+  constexpr int R = 4;                                     // fact rows per thread per step
+  constexpr int DK = (kJChunk + kJBlock - 1) / kJBlock;    // dim keys per thread
+  if (threadIdx.x == 0) {
+    const int64_t t = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)a.ticket, 1ull);
+    s_nxt_u = t;
+    s_nxt = unit_bounds(a, t, n_units);
+  }
+  __syncthreads();
   for (;;) {
-    if (threadIdx.x == 0) s_unit = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)a.ticket, 1ull);
-    __syncthreads();
-    const int64_t u = s_unit;
+    const int64_t u = s_nxt_u;
     if (u >= n_units) break;
-    const uint32_t p = a.unit_part[u], chunk = a.unit_chunk[u];
-    const uint32_t dlo = a.dstart[p] + chunk * (uint32_t)kJChunk;
-    const uint32_t dend = a.dstart[p] + a.dcount[p];
-    const uint32_t dhi = dlo + kJChunk < dend ? dlo + kJChunk : dend;
-    const uint32_t flo = a.fstart[p], fhi = flo + a.fcount[p];
-
+    const UnitBounds cur = s_nxt;
+    int64_t t_next = 0;
+    if (threadIdx.x == 0) t_next = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)a.ticket, 1ull);
+    const uint32_t dlo = cur.dlo, dhi = cur.dhi, flo = cur.flo, fhi = cur.fhi;
+    int32_t dkeys[DK];
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+      const uint32_t j = dlo + threadIdx.x + k * kJBlock;
+      dkeys[k] = j < dhi ? a.dkey[j] : 0;
+    }
+    int32_t keys[R];
+    uint64_t sps[R], sqs[R];
+    auto load_rows = [&](uint32_t i0) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const uint32_t i = i0 + k * kJBlock;
+        const bool ok = i < fhi;
+        keys[k] = ok ? a.fkey[i] : 0;
+        sps[k] = ok ? (uint64_t)a.fprice[i] : 0;
+        sqs[k] = ok ? (uint64_t)(int64_t)a.fqty[i] : 0;
+      }
+    };
+    load_rows(flo + threadIdx.x);
     for (int s = threadIdx.x; s < kJSlots; s += kJBlock) {
       tkey[s] = kLdsEmpty;
       tcnt[s] = 0;
@@ -431,9 +493,15 @@ __global__ __launch_bounds__(kJBlock) void k_part_groupjoin(JoinArgs a) {
       tsq[s] = 0;
     }
     __syncthreads();
+    if (threadIdx.x == 0) {  // the next unit, read by everyone after this unit's last barrier
+      s_nxt_u = t_next;
+      s_nxt = unit_bounds(a, t_next, n_units);
+    }
     // build: at most kJChunk unique keys into kJSlots slots, so a free slot always exists
-    for (uint32_t j = dlo + threadIdx.x; j < dhi; j += kJBlock) {
-      const int32_t key = a.dkey[j];
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+      if (dlo + threadIdx.x + k * kJBlock >= dhi) continue;
+      const int32_t key = dkeys[k];
       const uint64_t want = (uint64_t)(uint32_t)key | (1ull << 32);
       uint32_t h = slot_hash(key);
       for (int step = 0; step < kJSlots; ++step) {
@@ -447,22 +515,12 @@ __global__ __launch_bounds__(kJBlock) void k_part_groupjoin(JoinArgs a) {
       }
     }
     __syncthreads();
-    // probe and aggregate in LDS: R rows per thread per step, loaded together
-    constexpr int R = 4;
+    // probe and aggregate in LDS
     const uint32_t nrows = fhi - flo;
     const uint32_t iters = (nrows + R * kJBlock - 1) / (R * kJBlock);  // uniform over the workgroup
     for (uint32_t it = 0; it < iters; ++it) {
       const uint32_t i0 = flo + it * (R * kJBlock) + threadIdx.x;
-      int32_t keys[R];
-      uint64_t sps[R], sqs[R];
-#pragma unroll
-      for (int k = 0; k < R; ++k) {
-        const uint32_t i = i0 + k * kJBlock;
-        const bool ok = i < fhi;
-        keys[k] = ok ? a.fkey[i] : 0;
-        sps[k] = ok ? (uint64_t)a.fprice[i] : 0;
-        sqs[k] = ok ? (uint64_t)(int64_t)a.fqty[i] : 0;
-      }
+      if (it > 0) load_rows(i0);
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         bool found = false;
@@ -717,7 +775,7 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
     a.out_cnt = out->count;
     a.out_cap = out->cap;
     a.d_n = out->d_n_groups;
-    const unsigned grid = (unsigned)ctx->num_cus * 2;
+    const unsigned grid = (unsigned)ctx->num_cus * 2;  // 56 KB of LDS each: two per CU
     hipLaunchKernelGGL(k_part_groupjoin, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
     REL_LAUNCH_CHECK(ctx, "part_groupjoin");
   }
