@@ -71,6 +71,8 @@ def workload(name: str):
 
     if name == "large":
         return datagen.large(), "fact 60,000,000 x dim 15,000,000, fk ~ Zipf(0.8), day < 1200, group by fk"
+    if name == "large_uniform":
+        return datagen.large_uniform(), "fact 60,000,000 x dim 15,000,000, fk uniform, day < 1200, group by fk"
     if name == "medium":
         return datagen.medium(), "fact 6,000,000 x dim 1,500,000, fk uniform, day < 1800, group by (prio, flag)"
     return datagen.small(), "fact 60,000 x dim 15,000, fk uniform, day < 1800, group by (prio, flag)"
@@ -145,7 +147,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="large", choices=["large", "medium", "small"])
+    ap.add_argument("--workload", default="large", choices=["large", "large_uniform", "medium", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=60_000_000)
     args = ap.parse_args()

@@ -200,6 +200,12 @@ def large(seed: int = 3, n: int = 60_000_000, m: int = 15_000_000) -> Tables:
     return make_tables(n, m, seed, day_lt=1200, group_by="fk", fk_zipf=0.8)
 
 
+def large_uniform(seed: int = 3, n: int = 60_000_000, m: int = 15_000_000) -> Tables:
+    """The large workload's sizes and query with fk uniform over the dim keys
+    (no skew); a companion of `large` that isolates the cost of Zipf hot keys."""
+    return make_tables(n, m, seed, day_lt=1200, group_by="fk")
+
+
 def planner_eval(groups: int, seed: int = 5, n: int = 60_000_000, m: int = 15_000_000) -> Tables:
     """fk ~ Zipf(1.2) over the dim keys, day < 1200, group by dim.grp with grp uniform in [0, groups)."""
     return make_tables(n, m, seed, day_lt=1200, group_by="dim_grp", fk_zipf=1.2, grp_card=groups)

@@ -99,7 +99,8 @@ __global__ __launch_bounds__(kBlk) void k_p1_hist(PartSide s) {
     }
   }
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < nb1; b += kBlk) s.hist1[(size_t)tile * nb1 + b] = h[b];
+  // bin-major [nb1][ntiles], so that each bin's column scan reads contiguously
+  for (uint32_t b = threadIdx.x; b < nb1; b += kBlk) s.hist1[(size_t)b * gridDim.x + tile] = h[b];
 }
 
 // Column b of hist1 (one bin over all tiles) -> exclusive prefix in place; tot1[b] = column sum.
@@ -107,18 +108,22 @@ __global__ __launch_bounds__(kBlk) void k_p1_colscan(uint32_t* __restrict__ hist
                                                      uint32_t* __restrict__ tot1, int64_t* __restrict__ passed) {
   __shared__ uint32_t scr[kBlk / kWave];
   const uint32_t b = blockIdx.x;
-  uint32_t carry = 0;
-  for (int64_t t0 = 0; t0 < ntiles; t0 += kBlk) {
-    const int64_t t = t0 + threadIdx.x;
-    const uint32_t v = t < ntiles ? hist1[(size_t)t * nb1 + b] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan<kBlk>(v, scr, &tot);
-    if (t < ntiles) hist1[(size_t)t * nb1 + b] = carry + ex;
-    carry += tot;
+  uint32_t* col = hist1 + (size_t)b * ntiles;
+  // each thread owns a contiguous run of the column: sum it, scan the sums, rescan the run
+  const int64_t per = (ntiles + kBlk - 1) / kBlk;
+  const int64_t lo = threadIdx.x * per, hi = lo + per < ntiles ? lo + per : ntiles;
+  uint32_t sum = 0;
+  for (int64_t t = lo; t < hi; ++t) sum += col[t];
+  uint32_t tot;
+  uint32_t run = block_excl_scan<kBlk>(sum, scr, &tot);
+  for (int64_t t = lo; t < hi; ++t) {
+    const uint32_t v = col[t];
+    col[t] = run;
+    run += v;
   }
   if (threadIdx.x == 0) {
-    tot1[b] = carry;
-    if (passed) dev_add<unsigned long long>((unsigned long long*)passed, (unsigned long long)carry);
+    tot1[b] = tot;
+    if (passed) dev_add<unsigned long long>((unsigned long long*)passed, (unsigned long long)tot);
   }
 }
 
@@ -196,7 +201,7 @@ __global__ __launch_bounds__(kBlk) void k_p1_scatter(PartSide s) {
   uint32_t tot;
   const uint32_t base = block_excl_scan<kBlk>(threadIdx.x < nb1 ? s.tot1[threadIdx.x] : 0u, st.scr, &tot);
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (threadIdx.x < nb1) st.gbase[threadIdx.x] = base + s.hist1[(size_t)tile * nb1 + threadIdx.x];
+  if (threadIdx.x < nb1) st.gbase[threadIdx.x] = base + s.hist1[(size_t)threadIdx.x * gridDim.x + tile];
   const int64_t r0 = tile * kTile1;
   const int64_t r1 = r0 + kTile1 < s.n ? r0 + kTile1 : s.n;
   constexpr int R = kRowsPerThread;
@@ -278,7 +283,16 @@ __global__ __launch_bounds__(kBlk) void k_p2_hist(PartSide s) {
   const uint32_t nb2 = 1u << s.b2, shift = 32u - s.b1 - s.b2, mask = nb2 - 1;
   for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) h[b] = 0;
   __syncthreads();
-  for (int64_t r = t.lo + threadIdx.x; r < t.hi; r += kBlk) atomicAdd(&h[(phash(s.key1[r]) >> shift) & mask], 1u);
+  constexpr int R = (int)(kTile2 / kBlk);
+  int32_t keys[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {  // all loads first
+    const int64_t q = t.lo + threadIdx.x + (int64_t)k * kBlk;
+    keys[k] = q < t.hi ? s.key1[q] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    if (t.lo + threadIdx.x + (int64_t)k * kBlk < t.hi) atomicAdd(&h[(phash(keys[k]) >> shift) & mask], 1u);
   __syncthreads();
   for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) s.hist2[(size_t)tile * nb2 + b] = h[b];
 }
@@ -473,19 +487,21 @@ __global__ __launch_bounds__(kJBlock) void k_part_groupjoin(JoinArgs a) {
       const uint32_t j = dlo + threadIdx.x + k * kJBlock;
       dkeys[k] = j < dhi ? a.dkey[j] : 0;
     }
-    int32_t keys[R];
-    uint64_t sps[R], sqs[R];
-    auto load_rows = [&](uint32_t i0) {
+    // fact rows in two register sets: while one step's rows are probed, the
+    // next step's are already in flight (long, skewed partitions)
+    int32_t keys[R], nkeys[R];
+    uint64_t sps[R], sqs[R], nsps[R], nsqs[R];
+    auto load_rows = [&](uint32_t i0, int32_t(&kk)[R], uint64_t(&pp)[R], uint64_t(&qq)[R]) {
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         const uint32_t i = i0 + k * kJBlock;
         const bool ok = i < fhi;
-        keys[k] = ok ? a.fkey[i] : 0;
-        sps[k] = ok ? (uint64_t)a.fprice[i] : 0;
-        sqs[k] = ok ? (uint64_t)(int64_t)a.fqty[i] : 0;
+        kk[k] = ok ? a.fkey[i] : 0;
+        pp[k] = ok ? (uint64_t)a.fprice[i] : 0;
+        qq[k] = ok ? (uint64_t)(int64_t)a.fqty[i] : 0;
       }
     };
-    load_rows(flo + threadIdx.x);
+    load_rows(flo + threadIdx.x, keys, sps, sqs);
     for (int s = threadIdx.x; s < kJSlots; s += kJBlock) {
       tkey[s] = kLdsEmpty;
       tcnt[s] = 0;
@@ -520,7 +536,15 @@ __global__ __launch_bounds__(kJBlock) void k_part_groupjoin(JoinArgs a) {
     const uint32_t iters = (nrows + R * kJBlock - 1) / (R * kJBlock);  // uniform over the workgroup
     for (uint32_t it = 0; it < iters; ++it) {
       const uint32_t i0 = flo + it * (R * kJBlock) + threadIdx.x;
-      if (it > 0) load_rows(i0);
+      if (it > 0) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          keys[k] = nkeys[k];
+          sps[k] = nsps[k];
+          sqs[k] = nsqs[k];
+        }
+      }
+      if (it + 1 < iters) load_rows(i0 + R * kJBlock, nkeys, nsps, nsqs);
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         bool found = false;
