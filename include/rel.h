@@ -208,6 +208,48 @@ typedef struct rel_stats {
 rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, const rel_query* q,
                                const rel_plan* plan, rel_groups_out* out, rel_stats* stats);
 
+/* ------------------------------------------------------------------------------------------------------------------
+ * Batched execution: many independent instances of the fused query in one
+ * graph launch. Small kernels leave most of a large GPU idle (the paper's
+ * undersaturation finding, Section 6.1, and its remedy of running work
+ * concurrently); here every phase of every instance is a work item in one
+ * persistent kernel per phase, and the phases are captured once in a HIP
+ * graph, so a run is a single hipGraphLaunch.
+ */
+typedef struct rel_batch_item {
+  rel_fact fact;
+  rel_dim dim;
+  rel_query q;
+  rel_groups_out out;     /* device outputs of this instance */
+  int64_t group_capacity; /* expected distinct groups (e.g. the NDV of dim.grp); 0 = upper bound min(n, m) */
+} rel_batch_item;
+
+/* One size bucket of the tuning table: instances with fact rows
+ * n < 2^log2_rows_below use this configuration. Entries ascend; the last one
+ * also takes every larger instance. */
+typedef struct rel_batch_tuning {
+  int32_t log2_rows_below;
+  int32_t items_per_thread; /* fact rows per thread per step: 1, 2, 4 or 8 */
+  int32_t block;            /* workgroup size: 64, 128, 256 or 512 */
+  int32_t lds_groups_max;   /* LDS group table when the instance's group bound is at most this (<= 512); 0 = never */
+  int32_t rows_per_item;    /* fact rows per work item (multiple of block * items_per_thread) */
+} rel_batch_tuning;
+
+typedef struct rel_batch rel_batch;
+
+/* Plan, allocate and capture a batch of k instances (descriptors are copied;
+ * the column and output buffers they point to must stay valid until
+ * rel_batch_destroy). tuning nullable (library defaults), n_tuning entries. */
+rel_status rel_batch_create(rel_ctx* ctx, const rel_batch_item* items, int32_t k, const rel_batch_tuning* tuning,
+                            int32_t n_tuning, rel_batch** out);
+/* Enqueue one run of every instance on the context's stream (one graph launch). */
+rel_status rel_batch_run(rel_batch* b);
+/* Synchronise and report: stats (nullable, k entries) with rows passed / join
+ * matches / groups per instance; REL_OVERFLOW if any instance's table
+ * overflowed, REL_DUPLICATE_KEY on a repeated pk. */
+rel_status rel_batch_sync(rel_batch* b, rel_stats* stats);
+rel_status rel_batch_destroy(rel_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -172,6 +172,29 @@ __device__ __forceinline__ bool join_lookup(const JoinView& t, int32_t key, int3
   return false;
 }
 
+// Insert (key, payload) into a join table with one 64-bit CAS per attempted
+// slot; a repeated key sets kDevDupKey, a full table kDevOverflow.
+__device__ __forceinline__ void join_insert(uint64_t* slots, uint32_t mask, uint32_t shift, int32_t key, int32_t pl,
+                                            uint32_t* status) {
+  if (key == -1) {
+    const uint64_t old = dev_cas<uint64_t>(&slots[(size_t)mask + 1], kJoinEmpty, (uint64_t)(uint32_t)pl);
+    if (old != kJoinEmpty) set_status(status, kDevDupKey);
+    return;
+  }
+  const uint64_t want = (uint64_t)(uint32_t)key | ((uint64_t)(uint32_t)pl << 32);
+  uint32_t h = hash32(key, shift);
+  for (uint32_t step = 0; step <= mask; ++step) {
+    const uint64_t old = dev_cas<uint64_t>(&slots[h], kJoinEmpty, want);
+    if (old == kJoinEmpty) return;
+    if ((uint32_t)old == (uint32_t)key) {
+      set_status(status, kDevDupKey);
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+  set_status(status, kDevOverflow);
+}
+
 // ---- group table ------------------------------------------------------------------------------------------------------
 
 // One group: key and the three running aggregates. A slot is occupied exactly

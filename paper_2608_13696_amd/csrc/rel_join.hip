@@ -26,26 +26,7 @@ __global__ __launch_bounds__(256) void k_join_build(const int32_t* __restrict__ 
     const int32_t pl = PK == PAY_ROW_ID ? (int32_t)j
                        : PK == PAY_I32  ? ((const int32_t*)payload)[j]
                                         : (int32_t)((const int8_t*)payload)[j];
-    if (key == -1) {
-      const uint64_t old = dev_cas<uint64_t>(&slots[(size_t)mask + 1], kJoinEmpty, (uint64_t)(uint32_t)pl);
-      if (old != kJoinEmpty) set_status(status, kDevDupKey);
-      continue;
-    }
-    const uint64_t want = (uint64_t)(uint32_t)key | ((uint64_t)(uint32_t)pl << 32);
-    uint32_t h = hash32(key, shift);
-    for (uint32_t step = 0;; ++step) {
-      if (step > mask) {
-        set_status(status, kDevOverflow);
-        break;
-      }
-      const uint64_t old = dev_cas<uint64_t>(&slots[h], kJoinEmpty, want);
-      if (old == kJoinEmpty) break;
-      if ((uint32_t)old == (uint32_t)key) {
-        set_status(status, kDevDupKey);
-        break;
-      }
-      h = (h + 1) & mask;
-    }
+    join_insert(slots, mask, shift, key, pl, status);
   }
 }
 

@@ -71,6 +71,18 @@ class Stats(ctypes.Structure):
         return d
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("fact", Fact), ("dim", Dim), ("q", Query), ("out", GroupsOut), ("group_capacity", _i64)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("log2_rows_below", _i32), ("items_per_thread", _i32), ("block", _i32), ("lds_groups_max", _i32),
+                ("rows_per_item", _i32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -96,9 +108,16 @@ def lib():
         L.rel_join_probe.argtypes = [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp]
         L.rel_groupby_agg.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, P(TableOpts), P(GroupsOut)]
         L.rel_filter_join_agg.argtypes = [_vp, P(Fact), P(Dim), P(Query), P(Plan), P(GroupsOut), P(Stats)]
+        L.rel_ctx_enable_timing.argtypes = [_vp, ctypes.c_int]
+        L.rel_ctx_kernel_times.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, P(ctypes.c_int)]
+        L.rel_batch_create.argtypes = [_vp, P(BatchItem), _i32, P(BatchTuning), _i32, P(_vp)]
+        L.rel_batch_run.argtypes = [_vp]
+        L.rel_batch_sync.argtypes = [_vp, P(Stats)]
+        L.rel_batch_destroy.argtypes = [_vp]
         for name in ("rel_ctx_create", "rel_ctx_destroy", "rel_ctx_set_stream", "rel_ctx_sync", "rel_filter_compact",
                      "rel_join_build", "rel_join_table_destroy", "rel_join_probe", "rel_groupby_agg",
-                     "rel_filter_join_agg"):
+                     "rel_filter_join_agg", "rel_ctx_enable_timing", "rel_ctx_kernel_times", "rel_batch_create",
+                     "rel_batch_run", "rel_batch_sync", "rel_batch_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -212,6 +231,62 @@ class Context:
                                              ctypes.byref(plan) if plan is not None else None, ctypes.byref(out.c),
                                              ctypes.byref(st) if stats else None))
         return out, (st.as_dict() if stats else None)
+
+
+class Batch:
+    """Many independent fused queries captured into one graph launch.
+
+    instances: list of (fact dict, dim dict, day_lt, group_by[, group_capacity]).
+    Outputs are allocated here, one Groups per instance."""
+
+    def __init__(self, ctx: Context, instances, tuning: list[dict] | None = None):
+        self.ctx = ctx
+        self.k = len(instances)
+        self._keep = []
+        self.outs = []
+        arr = (BatchItem * max(self.k, 1))()
+        for i, inst in enumerate(instances):
+            fact, dim, day_lt, group_by = inst[:4]
+            gcap = inst[4] if len(inst) > 4 else 0
+            n, m = fact["fk"].numel(), dim["pk"].numel()
+            bound = min(n, 65536) if group_by == "prio_flag" else min(n, max(m, 1))
+            if gcap:
+                bound = min(bound, gcap)
+            out = _alloc_groups(max(bound, 1), fact["fk"].device)
+            self.outs.append(out)
+            self._keep.append((fact, dim))
+            arr[i].fact = Fact(_ptr(fact["fk"]), _ptr(fact["price_cents"]), _ptr(fact["qty"]), _ptr(fact["day"]),
+                               _ptr(fact.get("flag")), n)
+            arr[i].dim = Dim(_ptr(dim["pk"]), _ptr(dim.get("prio")), _ptr(dim.get("grp")), m)
+            arr[i].q = Query(int(day_lt), GROUP_BY[group_by])
+            arr[i].out = out.c
+            arr[i].group_capacity = int(gcap)
+        tarr, nt = None, 0
+        if tuning:
+            tarr = (BatchTuning * len(tuning))(*[BatchTuning(**t) for t in tuning])
+            nt = len(tuning)
+        h = ctypes.c_void_p()
+        ctx.check(lib().rel_batch_create(ctx.h, arr, self.k, tarr, nt, ctypes.byref(h)))
+        self.h = h
+
+    def run(self):
+        self.ctx.check(lib().rel_batch_run(self.h))
+
+    def sync(self) -> list[dict]:
+        st = (Stats * max(self.k, 1))()
+        self.ctx.check(lib().rel_batch_sync(self.h, st))
+        return [st[i].as_dict() for i in range(self.k)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rel_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class JoinTable:
