@@ -142,20 +142,131 @@ def cpu_baseline(sample_rows: int, wl: str) -> dict:
             "sample": f"{desc}; median of {len(times)} runs, {med:.2f} s each, generation excluded"}
 
 
+def run_batch(args) -> int:
+    """Batched form: 4096 independent instances (fact rows log-uniform in
+    [1e3, 1e6], dim = fact/4, group cardinality log-uniform in [1, 65536] via
+    dim.grp, selectivity uniform in [0.05, 0.95]) as one graph launch, against
+    the same instances issued as 4096 plain pipeline calls on the same GPU."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_2608_13696_amd import autotune, rel
+
+    t0 = time.perf_counter()
+    specs = datagen.batch_specs(args.batch_k, seed=4)
+    dev = torch.device("cuda:0")
+    insts, n_tot, m_tot = [], 0, 0
+    for s in specs:
+        T = datagen.batch_instance(s)
+        d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        fact = {"fk": d(T.fk), "price_cents": d(T.price_cents), "qty": d(T.qty), "day": d(T.day), "flag": d(T.flag)}
+        dim = {"pk": d(T.pk), "prio": d(T.prio), "grp": d(T.grp)}
+        insts.append((fact, dim, T.day_lt, "dim_grp", s.groups))
+        n_tot += T.n
+        m_tot += T.m
+    torch.cuda.synchronize()
+    log(f"generated {len(specs)} instances ({n_tot:,} fact rows, {m_tot:,} dim rows) in {time.perf_counter() - t0:.1f} s")
+    ctx = rel.Context(0)
+    tuning = None
+    if args.autotune:
+        by_bucket = {}
+        for inst in insts:
+            by_bucket.setdefault(autotune.bucket_of(inst[0]["fk"].numel()), []).append(inst)
+
+        def bucket_measure(i):
+            lst = by_bucket.get(i)
+            if not lst:
+                return None
+            return autotune.gpu_measure(ctx, lst)  # the bucket's own instances, run alone
+
+        t1 = time.perf_counter()
+        tuning, report = autotune.tune(bucket_measure)
+        autotune.save(tuning, report=report)
+        log(f"autotuned in {time.perf_counter() - t1:.1f} s: {tuning}")
+    else:
+        tuning = autotune.load()
+    b = rel.Batch(ctx, insts, tuning=tuning)
+    b.run()
+    st = b.sync()
+    groups = sum(x["groups"] for x in st)
+    for _ in range(args.warmup):
+        b.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        b.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    log(f"batched: {ms:.3f} ms per run of {len(insts)} instances")
+
+    # the same instances as sequential plain calls (prebuilt argument structs, no host sync)
+    L = rel.lib()
+    calls = []
+    for (fact, dim, day_lt, gb, gcap), out in zip(insts, b.outs):
+        f = rel.Fact(rel._ptr(fact["fk"]), rel._ptr(fact["price_cents"]), rel._ptr(fact["qty"]), rel._ptr(fact["day"]),
+                     rel._ptr(fact["flag"]), fact["fk"].numel())
+        dd = rel.Dim(rel._ptr(dim["pk"]), rel._ptr(dim["prio"]), rel._ptr(dim["grp"]), dim["pk"].numel())
+        q = rel.Query(int(day_lt), rel.GROUP_BY[gb])
+        p = rel.Plan(int(gcap), 0, 0, 0, 0)
+        calls.append((ctypes.byref(f), ctypes.byref(dd), ctypes.byref(q), ctypes.byref(p), ctypes.byref(out.c), f, dd, q, p))
+
+    def sequential():
+        for c in calls:
+            st_ = L.rel_filter_join_agg(ctx.h, c[0], c[1], c[2], c[3], c[4], None)
+            if st_ != 0:
+                ctx.check(st_)
+
+    sequential()
+    torch.cuda.synchronize()
+    seq_steps = max(1, min(args.steps, 5))
+    e0.record()
+    t_host = time.perf_counter()
+    for _ in range(seq_steps):
+        sequential()
+    e1.record()
+    torch.cuda.synchronize()
+    seq_ms = e0.elapsed_time(e1) / seq_steps
+    log(f"sequential plain calls: {seq_ms:.3f} ms per pass ({(time.perf_counter() - t_host) / seq_steps * 1e3:.1f} ms host)")
+    comp = 20 * n_tot + 8 * m_tot + 32 * groups
+    result = {
+        "metric": "batched input rows/s, 4096 filter-join-groupby instances in one graph launch",
+        "value": n_tot / (ms / 1e3), "unit": "rows/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": f"{len(insts)} instances, fact rows log-uniform [1e3, 1e6] ({n_tot:,} total), dim = fact/4, "
+                               "groups log-uniform [1, 65536] by dim.grp, selectivity uniform [0.05, 0.95]",
+                   "groups": groups, "tuning": tuning},
+        "sequential_plain": {"value": n_tot / (seq_ms / 1e3), "unit": "rows/s", "ms_per_pass": seq_ms},
+        "speedup_vs_sequential": seq_ms / ms,
+        "pipeline": {"compulsory_bytes": comp, "achieved_gbs": comp / (ms / 1e3) / 1e9},
+    }
+    print(json.dumps(result), flush=True)
+    b.close()
+    ctx.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="large", choices=["large", "large_uniform", "medium", "small"])
+    ap.add_argument("--workload", default="large", choices=["large", "large_uniform", "medium", "small", "batch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=60_000_000)
+    ap.add_argument("--batch-k", type=int, default=4096)
+    ap.add_argument("--autotune", action="store_true", help="batch: measure and save the tuning table first")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md on sharding); "
               "run with --gpus 1", file=sys.stderr)
         return 2
+    if args.workload == "batch":
+        return run_batch(args)
 
     import numpy as np
     import torch
