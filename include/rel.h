@@ -250,6 +250,56 @@ rel_status rel_batch_run(rel_batch* b);
 rel_status rel_batch_sync(rel_batch* b, rel_stats* stats);
 rel_status rel_batch_destroy(rel_batch* b);
 
+/* ------------------------------------------------------------------------------------------------------------------
+ * Learned planner. The paper's engine logs operator statistics (row counts,
+ * selectivity, match ratios; Section 4.1) and cuDF sizes a join's output with
+ * a separate counting kernel (Section 7). Here a small MLP predicts the join
+ * output rows and the group count from a cheap sketch, so hash tables are
+ * sized and placed before the build; an overflow reruns the plain pipeline,
+ * so results never depend on the prediction.
+ */
+#define REL_SKETCH_FEATURES 40
+#define REL_MLP_PARAMS 6914 /* 40x64 + 64 + 64x64 + 64 + 64x2 + 2 */
+
+/* Sketch of a query's inputs: 64-register HyperLogLog of fact.fk (all rows)
+ * and of dim.grp (when given), and statistics of k sampled fact rows and k
+ * sampled dim rows, assembled into 40 features (layout in the design doc and the
+ * sketch kernel). d_fact_sample / d_dim_sample: device int64[k] row indices in
+ * [0, n) / [0, m), drawn by the caller. Outputs (device): d_features float[40],
+ * d_hll uint8[128] (fk registers, then grp registers). */
+rel_status rel_sketch(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, const rel_query* q,
+                      const int64_t* d_fact_sample, const int64_t* d_dim_sample, int32_t k, float* d_features,
+                      uint8_t* d_hll);
+
+/* MLP 40 -> 64 -> 64 -> 2 with ReLU, FP32, parameters packed as
+ * W1[40][64], b1[64], W2[64][64], b2[64], W3[64][2], b3[2] (input index
+ * first, so a layer computes y[o] = b[o] + sum_i x[i] W[i][o]).
+ * Forward: d_x float[B][40] -> d_y float[B][2]. */
+rel_status rel_mlp_forward(rel_ctx* ctx, const float* d_params, const float* d_x, int32_t B, float* d_y);
+/* Loss L = 1/(2B) sum (y - t)^2 and its gradient d_grad float[6914];
+ * d_loss float[1] (nullable). Deterministic: no floating-point atomics. */
+rel_status rel_mlp_backward(rel_ctx* ctx, const float* d_params, const float* d_x, const float* d_t, int32_t B,
+                            float* d_grad, float* d_loss);
+/* One Adam update (Kingma and Ba 2015) at step t >= 1 of params / first and
+ * second moments (all device float[6914]). */
+rel_status rel_mlp_adam_step(rel_ctx* ctx, float* d_params, float* d_m, float* d_v, const float* d_grad, int32_t t,
+                             float lr, float beta1, float beta2, float eps);
+
+typedef struct rel_planner rel_planner;
+
+/* A planner from host arrays: params[6914], feature standardisation
+ * mean[40] / scale[40] (x' = (x - mean) / scale), and the safety margin in
+ * log2 units added to the predicted group count. */
+rel_status rel_planner_create(rel_ctx* ctx, const float* params, const float* mean, const float* scale,
+                              float margin_log2, rel_planner** out);
+/* Sketch, predict and fill *plan (group capacity and placement, fallback
+ * allowed). Synchronises once (two floats come back). pred (host, nullable)
+ * receives the raw predictions log2(1 + join rows), log2(1 + groups). */
+rel_status rel_planner_plan(rel_planner* p, const rel_fact* fact, const rel_dim* dim, const rel_query* q,
+                            const int64_t* d_fact_sample, const int64_t* d_dim_sample, int32_t k, rel_plan* plan,
+                            float* pred);
+rel_status rel_planner_destroy(rel_planner* p);
+
 #ifdef __cplusplus
 }
 #endif

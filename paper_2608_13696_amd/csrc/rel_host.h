@@ -29,6 +29,7 @@ enum ScratchId : int {
   SCR_PART_D,
   SCR_PART_E,
   SCR_SKETCH,
+  SCR_MLP,
   SCR_COUNT
 };
 

@@ -8,6 +8,10 @@ namespace relh {
 // Source of a join-table payload.
 enum PayloadKind : int { PAY_ROW_ID = 0, PAY_I32 = 1, PAY_I8 = 2, PAY_NONE = 3 };
 
+// Largest group count the fused pipeline keeps in its per-workgroup LDS table
+// (1024 slots, load <= 0.5).
+constexpr int64_t kLdsGroupCap = 512;
+
 // Fill `slots` (capacity 2^log2cap, plus the side slot) and insert pk[0..m).
 rel_status join_build_into(rel_ctx* ctx, const int32_t* pk, const void* payload, int payload_kind, int64_t m,
                            uint64_t* slots, uint32_t log2cap);

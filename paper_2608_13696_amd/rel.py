@@ -114,10 +114,20 @@ def lib():
         L.rel_batch_run.argtypes = [_vp]
         L.rel_batch_sync.argtypes = [_vp, P(Stats)]
         L.rel_batch_destroy.argtypes = [_vp]
+        L.rel_sketch.argtypes = [_vp, P(Fact), P(Dim), P(Query), _vp, _vp, _i32, _vp, _vp]
+        L.rel_mlp_forward.argtypes = [_vp, _vp, _vp, _i32, _vp]
+        L.rel_mlp_backward.argtypes = [_vp, _vp, _vp, _vp, _i32, _vp, _vp]
+        L.rel_mlp_adam_step.argtypes = [_vp, _vp, _vp, _vp, _vp, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_float]
+        L.rel_planner_create.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_float, P(_vp)]
+        L.rel_planner_plan.argtypes = [_vp, P(Fact), P(Dim), P(Query), _vp, _vp, _i32, P(Plan), _vp]
+        L.rel_planner_destroy.argtypes = [_vp]
         for name in ("rel_ctx_create", "rel_ctx_destroy", "rel_ctx_set_stream", "rel_ctx_sync", "rel_filter_compact",
                      "rel_join_build", "rel_join_table_destroy", "rel_join_probe", "rel_groupby_agg",
                      "rel_filter_join_agg", "rel_ctx_enable_timing", "rel_ctx_kernel_times", "rel_batch_create",
-                     "rel_batch_run", "rel_batch_sync", "rel_batch_destroy"):
+                     "rel_batch_run", "rel_batch_sync", "rel_batch_destroy", "rel_sketch", "rel_mlp_forward",
+                     "rel_mlp_backward", "rel_mlp_adam_step", "rel_planner_create", "rel_planner_plan",
+                     "rel_planner_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -231,6 +241,82 @@ class Context:
                                              ctypes.byref(plan) if plan is not None else None, ctypes.byref(out.c),
                                              ctypes.byref(st) if stats else None))
         return out, (st.as_dict() if stats else None)
+
+
+def _fact_dim_query(fact: dict, dim: dict, day_lt: int, group_by: str):
+    f = Fact(_ptr(fact["fk"]), _ptr(fact.get("price_cents")), _ptr(fact.get("qty")), _ptr(fact["day"]),
+             _ptr(fact.get("flag")), fact["fk"].numel())
+    d = Dim(_ptr(dim["pk"]), _ptr(dim.get("prio")), _ptr(dim.get("grp")), dim["pk"].numel())
+    return f, d, Query(int(day_lt), GROUP_BY[group_by])
+
+
+def sketch(ctx: Context, fact: dict, dim: dict, day_lt: int, group_by: str, fsample: torch.Tensor,
+           dsample: torch.Tensor):
+    """(features float32[40], HLL registers uint8[128]) on the device."""
+    _dev_check(fsample, torch.int64, "fsample")
+    _dev_check(dsample, torch.int64, "dsample")
+    f, d, q = _fact_dim_query(fact, dim, day_lt, group_by)
+    feat = torch.empty(40, dtype=torch.float32, device=fact["fk"].device)
+    hll = torch.empty(128, dtype=torch.uint8, device=fact["fk"].device)
+    ctx.check(lib().rel_sketch(ctx.h, ctypes.byref(f), ctypes.byref(d), ctypes.byref(q), _ptr(fsample), _ptr(dsample),
+                               fsample.numel(), _ptr(feat), _ptr(hll)))
+    return feat, hll
+
+
+def mlp_forward(ctx: Context, params: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    _dev_check(params, torch.float32, "params")
+    _dev_check(x, torch.float32, "x")
+    y = torch.empty((x.shape[0], 2), dtype=torch.float32, device=x.device)
+    ctx.check(lib().rel_mlp_forward(ctx.h, _ptr(params), _ptr(x), x.shape[0], _ptr(y)))
+    return y
+
+
+def mlp_backward(ctx: Context, params: torch.Tensor, x: torch.Tensor, t: torch.Tensor, grad: torch.Tensor | None = None,
+                 loss: torch.Tensor | None = None):
+    for name, a in (("params", params), ("x", x), ("t", t)):
+        _dev_check(a, torch.float32, name)
+    grad = grad if grad is not None else torch.empty_like(params)
+    loss = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=x.device)
+    ctx.check(lib().rel_mlp_backward(ctx.h, _ptr(params), _ptr(x), _ptr(t), x.shape[0], _ptr(grad), _ptr(loss)))
+    return grad, loss
+
+
+def mlp_adam_step(ctx: Context, params, m, v, grad, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    ctx.check(lib().rel_mlp_adam_step(ctx.h, _ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(t), lr, beta1, beta2, eps))
+
+
+class Planner:
+    """Learned planner: params float32[6914], feature mean / scale float32[40],
+    margin in log2 units (host numpy arrays)."""
+
+    def __init__(self, ctx: Context, params, mean, scale, margin_log2: float):
+        import numpy as np
+
+        self.ctx = ctx
+        self._arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (params, mean, scale)]
+        h = ctypes.c_void_p()
+        ctx.check(lib().rel_planner_create(ctx.h, *[a.ctypes.data for a in self._arrs], float(margin_log2),
+                                           ctypes.byref(h)))
+        self.h = h
+
+    def plan(self, fact: dict, dim: dict, day_lt: int, group_by: str, fsample: torch.Tensor, dsample: torch.Tensor):
+        f, d, q = _fact_dim_query(fact, dim, day_lt, group_by)
+        p = Plan()
+        pred = (ctypes.c_float * 2)()
+        self.ctx.check(lib().rel_planner_plan(self.h, ctypes.byref(f), ctypes.byref(d), ctypes.byref(q), _ptr(fsample),
+                                              _ptr(dsample), fsample.numel(), ctypes.byref(p), pred))
+        return p, (pred[0], pred[1])
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rel_planner_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:
