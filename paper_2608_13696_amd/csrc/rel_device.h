@@ -243,6 +243,37 @@ __device__ __forceinline__ void group_add(const GroupView& t, int64_t key, uint6
   dev_add<uint64_t>(&g->count, cnt);
 }
 
+// Sum of a 64-bit value over the 64 lanes of a wave.
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, o, kWave);
+  return v;
+}
+
+// Lanes sharing a key before a wave pre-sums them (below this the extra
+// shuffles cost more than the atomics they save).
+constexpr int kWaveCombineMin = 4;
+
+// group_add for one row per active lane, called by every lane of the wave.
+// Lanes whose key equals the first active lane's key are summed across the
+// wave first, so a hot key (a skewed join) costs one set of device atomics per
+// wave instead of one per row.
+__device__ __forceinline__ void group_add_wave(const GroupView& t, bool active, int64_t key, uint64_t sp, uint64_t sq) {
+  const uint64_t act = wave_ballot(active);
+  if (act == 0) return;
+  const int first = __ffsll((long long)act) - 1;
+  const int64_t k0 = __shfl(key, first, kWave);
+  const bool mine = active && key == k0;
+  const uint64_t same = wave_ballot(mine);
+  if (__popcll(same) >= kWaveCombineMin) {
+    const uint64_t s1 = wave_sum_u64(mine ? sp : 0);
+    const uint64_t s2 = wave_sum_u64(mine ? sq : 0);
+    if ((int)lane_id() == first) group_add(t, k0, s1, s2, (uint64_t)__popcll(same));
+    active = active && !mine;
+  }
+  if (active) group_add(t, key, sp, sq, 1ull);
+}
+
 // Per-dim-row aggregates of the groupjoin (group key == join key).
 struct alignas(8) RowAgg {
   uint64_t sum_price;

@@ -25,6 +25,7 @@ constexpr int kBlock = 256;
 constexpr int kIPT = 4;  // rows per thread per tile: one 16-byte load per int32 column
 constexpr int kLdsSlots = 1024;
 constexpr int kLdsProbe = 32;
+constexpr int kLdsCacheProbe = 4;
 // A table sized from a prediction gives up after this many probe steps (at a
 // load of 0.5 linear probing practically never walks that far), so that an
 // undersized table reports overflow instead of degrading to a linear scan.
@@ -42,6 +43,7 @@ struct FusedArgs {
   GroupView groups;
   RowAgg* row_agg;
   int64_t* counters;  // [0] rows passed, [1] join matches
+  int32_t lds_probe;  // LDS probe budget before a row goes to device memory
 };
 
 template <int MODE>
@@ -100,23 +102,31 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a) {
     }
 #pragma unroll
     for (int k = 0; k < kIPT; ++k) {
-      if (k >= nv || !(d[k] < a.day_lt)) continue;
-      ++passed;
-      int32_t pl;
-      if (!join_lookup(a.join, f[k], &pl)) continue;
-      ++matched;
+      // no early exits: the device-memory update below is a wave-wide call
+      const bool pass = k < nv && d[k] < a.day_lt;
+      passed += pass;
+      int32_t pl = 0;
+      const bool hit = pass && join_lookup(a.join, f[k], &pl);
+      matched += hit;
       const uint64_t sp = (uint64_t)p[k], sq = (uint64_t)(int64_t)q[k];
       if (GP == G_ROWAGG) {
-        RowAgg* r = &a.row_agg[pl];
-        dev_add<uint64_t>(&r->sum_price, sp);
-        dev_add<uint64_t>(&r->sum_qty, sq);
-        dev_add<uint64_t>(&r->count, 1ull);
+        if (hit) {
+          RowAgg* r = &a.row_agg[pl];
+          dev_add<uint64_t>(&r->sum_price, sp);
+          dev_add<uint64_t>(&r->sum_qty, sq);
+          dev_add<uint64_t>(&r->count, 1ull);
+        }
       } else {
-        const int64_t key = group_key<MODE>(pl, f[k], fl[k]);
-        int s = -1;
-        if (GP == G_LDS) s = lds.find(key, kLdsProbe);
-        if (s >= 0) lds.add(s, sp, sq, 1ull);
-        else group_add(a.groups, key, sp, sq, 1ull);
+        const int64_t key = hit ? group_key<MODE>(pl, f[k], fl[k]) : 0;
+        bool global = hit;
+        if (GP == G_LDS && hit) {
+          const int s = lds.find(key, a.lds_probe);
+          if (s >= 0) {
+            lds.add(s, sp, sq, 1ull);
+            global = false;
+          }
+        }
+        group_add_wave(a.groups, global, key, sp, sq);
       }
     }
   }
@@ -423,6 +433,11 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
     if (placement == REL_PLACE_PARTITIONED) return relh::fail(ctx, REL_UNSUPPORTED, "rel_filter_join_agg: partitioned group-by");
     if (placement == REL_PLACE_AUTO) placement = (gb == REL_GROUP_PRIO_FLAG || expected <= kLdsSlots / 2) ? REL_PLACE_LDS : REL_PLACE_GLOBAL;
     gp = placement == REL_PLACE_LDS ? G_LDS : G_GLOBAL;
+    // With more groups than the LDS table holds, LDS acts as a cache in front of
+    // the device-memory table (it keeps the keys each workgroup meets first,
+    // which under skew are the hot ones); a short probe budget bounds the cost
+    // of rows whose key is not cached.
+    a.lds_probe = expected <= relh::kLdsGroupCap ? kLdsProbe : kLdsCacheProbe;
     const uint32_t gl = group_log2cap(expected, 0.5);
     if (gl > 31) return relh::fail(ctx, REL_UNSUPPORTED, "rel_filter_join_agg: group table above 2^31 slots");
     group_cap = 1ll << gl;

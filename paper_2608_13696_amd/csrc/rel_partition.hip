@@ -442,12 +442,6 @@ __device__ __forceinline__ UnitBounds unit_bounds(const JoinArgs& a, int64_t u, 
   return b;
 }
 
-// Sum of a 64-bit value over the lanes of a wave (inactive contributions pass 0).
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, o, kWave);
-  return v;
-}
 
 __global__ __launch_bounds__(kJBlock) void k_part_groupjoin(JoinArgs a) {
   __shared__ uint64_t tkey[kJSlots];  // {key, 1} packed; all ones = empty

@@ -384,10 +384,18 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
   p[i] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-__global__ void k_normalize(float* __restrict__ x, const float* __restrict__ mean, const float* __restrict__ scale) {
+// Standardise the features in place; keep the raw sampled max frequency
+// (feature 10), which the sizing rule reads as a skew signal.
+__global__ void k_normalize(float* __restrict__ x, const float* __restrict__ mean, const float* __restrict__ scale,
+                            float* __restrict__ raw_maxfreq) {
   const int i = threadIdx.x;
+  if (i == 10) *raw_maxfreq = x[i];
   if (i < kFeat) x[i] = (x[i] - mean[i]) / scale[i];
 }
+
+// A key seen this often among the sampled rows marks a heavy hitter (about
+// 1.5% of the rows or more).
+constexpr float kSkewMaxFreq = 4.0f / 256.0f;
 
 #define TRY(e)                   \
   do {                           \
@@ -492,7 +500,7 @@ rel_status rel_planner_create(rel_ctx* ctx, const float* params, const float* me
   rel_planner* p = new rel_planner();
   p->ctx = ctx;
   p->margin = margin_log2;
-  const size_t floats = kParams + 3 * kFeat + 2 + 64;  // + features, prediction, HLL bytes
+  const size_t floats = kParams + 3 * kFeat + 4 + 64;  // params, mean, scale, features, prediction + skew, HLL bytes
   hipError_t e = hipMalloc(&p->mem, floats * sizeof(float));
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -519,16 +527,17 @@ rel_status rel_planner_plan(rel_planner* p, const rel_fact* fact, const rel_dim*
   float* mean = params + kParams;
   float* scale = mean + kFeat;
   float* feat = scale + kFeat;
-  float* y = feat + kFeat;
-  uint8_t* hll = (uint8_t*)(y + 2);
+  float* y = feat + kFeat;  // y[0], y[1]: prediction; y[2]: raw sampled max frequency
+  uint8_t* hll = (uint8_t*)(y + 4);
   TRY(rel_sketch(ctx, fact, dim, q, d_fact_sample, d_dim_sample, k, feat, hll));
   {
     relh::KernelTimer kt(ctx, "planner_normalize");
-    hipLaunchKernelGGL(k_normalize, dim3(1), dim3(64), 0, ctx->stream, feat, (const float*)mean, (const float*)scale);
+    hipLaunchKernelGGL(k_normalize, dim3(1), dim3(64), 0, ctx->stream, feat, (const float*)mean, (const float*)scale,
+                       y + 2);
   }
   REL_LAUNCH_CHECK(ctx, "normalize");
   TRY(rel_mlp_forward(ctx, params, feat, 1, y));
-  float hy[2];
+  float hy[3];
   REL_HIP_CHECK(ctx, hipMemcpyAsync(hy, y, sizeof hy, hipMemcpyDeviceToHost, ctx->stream));
   REL_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
   if (pred) {
@@ -543,7 +552,10 @@ rel_status rel_planner_plan(rel_planner* p, const rel_fact* fact, const rel_dim*
   int64_t expected = (int64_t)std::ceil(e);
   if (expected < 1) expected = 1;
   plan->group_capacity = expected;
-  plan->group_placement = expected <= relh::kLdsGroupCap ? REL_PLACE_LDS : REL_PLACE_GLOBAL;
+  // LDS holds every group when they are few; under a heavy hitter it also pays
+  // as a cache in front of a larger device-memory table
+  const bool skewed = hy[2] >= kSkewMaxFreq;
+  plan->group_placement = (expected <= relh::kLdsGroupCap || skewed) ? REL_PLACE_LDS : REL_PLACE_GLOBAL;
   plan->join_placement = REL_PLACE_AUTO;
   plan->allow_fallback = 1;
   plan->reserved = 0;

@@ -1,0 +1,85 @@
+"""The learned planner never changes results: planned runs equal the plain
+pipeline and the oracle, and an undersized plan falls back to the plain
+pipeline with identical output. Uses the committed model."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+from paper_2608_13696_amd import planner_train, rel
+from tests.gpu_util import assert_groups_equal, gpu_groups, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = rel.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def planner(ctx):
+    if not os.path.exists(planner_train.MODEL):
+        pytest.skip("no trained planner model")
+    params, mean, scale, margin, _ = planner_train.load_model()
+    p = rel.Planner(ctx, params, mean, scale, margin)
+    yield p
+    p.close()
+
+
+def _samples(T):
+    fs = torch.from_numpy(datagen.sample_index(256, max(T.n, 1), T.meta["seed"], datagen.S_SAMPLE)).cuda()
+    ds = torch.from_numpy(datagen.sample_index(256, max(T.m, 1), T.meta["seed"], datagen.S_SAMPLE + 1)).cuda()
+    return fs, ds
+
+
+@pytest.mark.parametrize("groups", [100, 10_000, 1_000_000])
+def test_planned_equals_plain_and_oracle(ctx, planner, groups):
+    T = datagen.planner_eval(groups, seed=55, n=3_000_000, m=750_000)
+    fact, dim = to_dev(T)
+    fs, ds = _samples(T)
+    plan, pred = planner.plan(fact, dim, T.day_lt, T.group_by, fs, ds)
+    assert plan.allow_fallback == 1 and plan.group_capacity >= 1
+    out_p, st_p = ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, plan=plan)
+    out_0, st_0 = ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by)
+    ora, ost = oracle.run_tables(T)
+    gp, g0 = gpu_groups(out_p), gpu_groups(out_0)
+    assert_groups_equal(gp, ora, f"planned G={groups}")
+    assert_groups_equal(g0, ora, f"plain G={groups}")
+    assert st_p["groups"] == ost["groups"]
+
+
+def test_undersized_plan_falls_back_identically(ctx):
+    # a network that predicts zero groups: the plan is one slot, it overflows
+    # and the plain pipeline reruns
+    z = np.zeros(6914, np.float32)
+    p = rel.Planner(ctx, z, np.zeros(40, np.float32), np.ones(40, np.float32), 0.0)
+    T = datagen.planner_eval(5000, seed=56, n=1_000_000, m=250_000)
+    fact, dim = to_dev(T)
+    fs, ds = _samples(T)
+    plan, pred = p.plan(fact, dim, T.day_lt, T.group_by, fs, ds)
+    assert plan.group_capacity == 1 and pred == (0.0, 0.0)
+    out, st = ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, plan=plan)
+    assert st["fell_back"] == 1 and st["overflowed"] == 1
+    assert_groups_equal(gpu_groups(out), oracle.run_tables(T)[0], "fallback")
+    p.close()
+
+
+def test_prediction_tracks_group_count(ctx, planner):
+    # not a parity check (the prediction has no oracle): the trained network
+    # should order group counts correctly across three decades
+    preds = []
+    for groups in (100, 10_000, 1_000_000):
+        T = datagen.planner_eval(groups, seed=57, n=2_000_000, m=500_000)
+        fact, dim = to_dev(T)
+        fs, ds = _samples(T)
+        _, pred = planner.plan(fact, dim, T.day_lt, T.group_by, fs, ds)
+        preds.append(pred[1])
+    assert preds[0] < preds[1] < preds[2]
