@@ -249,12 +249,97 @@ def run_batch(args) -> int:
     return 0
 
 
+def run_planner(args) -> int:
+    """Learned-planner form: 60M fact x 15M dim rows, fk ~ Zipf(1.2) over the dim
+    keys, day < 1200, group by dim.grp with grp uniform in [0, G) for
+    G = 1e2 ... 1e7. Plain pipeline (tables sized for the upper bound) against
+    planned runs (sketch + MLP + one host read + sized run, fallback allowed),
+    both timed end to end; outputs must be identical."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_2608_13696_amd import planner_train, rel
+
+    t0 = time.perf_counter()
+    T = datagen.planner_eval(100)
+    dev = torch.device("cuda:0")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    fact = {"fk": d(T.fk), "price_cents": d(T.price_cents), "qty": d(T.qty), "day": d(T.day), "flag": d(T.flag)}
+    dim = {"pk": d(T.pk), "prio": d(T.prio), "grp": None}
+    fs = d(datagen.sample_index(256, T.n, T.meta["seed"], datagen.S_SAMPLE))
+    ds = d(datagen.sample_index(256, T.m, T.meta["seed"], datagen.S_SAMPLE + 1))
+    log(f"generated planner workload in {time.perf_counter() - t0:.1f} s")
+    ctx = rel.Context(0)
+    params, mean, scale, margin, meta = planner_train.load_model()
+    planner = rel.Planner(ctx, params, mean, scale, margin)
+    rows = []
+    tot_plain = tot_plan = 0.0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for G in (100, 1_000, 10_000, 100_000, 1_000_000, 10_000_000):
+        dim["grp"] = d(datagen.uniform(T.m, 0, G - 1, np.int32, T.meta["seed"], datagen.S_GRP))
+
+        def plain():
+            return ctx.filter_join_agg(fact, dim, T.day_lt, "dim_grp", stats=False)
+
+        def planned():
+            plan, pred = planner.plan(fact, dim, T.day_lt, "dim_grp", fs, ds)
+            return ctx.filter_join_agg(fact, dim, T.day_lt, "dim_grp", plan=plan, stats=False), plan, pred
+
+        out0, st0 = ctx.filter_join_agg(fact, dim, T.day_lt, "dim_grp", stats=True)
+        plan, pred = planner.plan(fact, dim, T.day_lt, "dim_grp", fs, ds)
+        out1, st1 = ctx.filter_join_agg(fact, dim, T.day_lt, "dim_grp", plan=plan, stats=True)
+        a, b = rel.sorted_groups(out0.host()), rel.sorted_groups(out1.host())
+        same = a["n_groups"] == b["n_groups"] and all(np.array_equal(a[k], b[k]) for k in ("key", "sum_price", "sum_qty", "count"))
+        if not same:
+            log(f"G={G}: planned output differs from plain")
+            return 1
+        times = {}
+        for name, fn in (("plain", plain), ("planned", planned)):
+            fn()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            times[name] = e0.elapsed_time(e1) / args.steps
+        tot_plain += times["plain"]
+        tot_plan += times["planned"]
+        row = {"groups_param": G, "groups": st0["groups"], "pred_log2_groups": pred[1],
+               "plan_capacity": plan.group_capacity, "plan_placement": rel.PLACE_NAME[plan.group_placement],
+               "fell_back": st1["fell_back"], "plain_ms": times["plain"], "planned_ms": times["planned"],
+               "speedup": times["plain"] / times["planned"]}
+        rows.append(row)
+        log(f"G={G:>9,}: groups {st0['groups']:>9,} pred 2^{pred[1]:.2f}-1 capacity {plan.group_capacity:,} "
+            f"{row['plan_placement']}, plain {times['plain']:.3f} ms, planned {times['planned']:.3f} ms "
+            f"({row['speedup']:.2f}x){' FELL BACK' if st1['fell_back'] else ''}")
+    n6 = 6 * T.n
+    result = {
+        "metric": "learned-planner input rows/s, filter-join-groupby, 60M rows, group counts 1e2..1e7",
+        "value": n6 / (tot_plan / 1e3), "unit": "rows/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": tot_plan / 6, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "fact 60,000,000 x dim 15,000,000, fk ~ Zipf(1.2), day < 1200, group by dim.grp, "
+                               "grp uniform in [0, G), G = 1e2..1e7",
+                   "model": {k: v for k, v in meta.items() if k != "val_mse_hist"}},
+        "plain": {"value": n6 / (tot_plain / 1e3), "unit": "rows/s", "ms_per_query": tot_plain / 6},
+        "speedup_vs_plain": tot_plain / tot_plan,
+        "per_group_count": rows,
+    }
+    print(json.dumps(result), flush=True)
+    planner.close()
+    ctx.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="large", choices=["large", "large_uniform", "medium", "small", "batch"])
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "large_uniform", "medium", "small", "batch", "planner"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=60_000_000)
     ap.add_argument("--batch-k", type=int, default=4096)
@@ -267,6 +352,8 @@ def main() -> int:
         return 2
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "planner":
+        return run_planner(args)
 
     import numpy as np
     import torch
