@@ -333,13 +333,37 @@ def run_planner(args) -> int:
     return 0
 
 
+def run_copy_calibration(args) -> int:
+    """A plain device copy of known size (1 GiB read + 1 GiB written per
+    launch), for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+
+    n = 1 << 27  # int64 elements: 1 GiB
+    a = torch.arange(n, dtype=torch.int64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(args.warmup):
+        torch.add(a, 1, out=b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        torch.add(a, 1, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    print(json.dumps({"workload": "copy calibration", "bytes_read_per_launch": 8 * n, "bytes_written_per_launch": 8 * n,
+                      "ms_per_launch": ms, "gbs": 16 * n / (ms / 1e3) / 1e9, "launches": args.steps + args.warmup}),
+          flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "large_uniform", "medium", "small", "batch", "planner"])
+                    choices=["large", "large_uniform", "medium", "small", "batch", "planner", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=60_000_000)
     ap.add_argument("--batch-k", type=int, default=4096)
@@ -354,6 +378,8 @@ def main() -> int:
         return run_batch(args)
     if args.workload == "planner":
         return run_planner(args)
+    if args.workload == "copy":
+        return run_copy_calibration(args)
 
     import numpy as np
     import torch
