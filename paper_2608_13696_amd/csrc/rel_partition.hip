@@ -358,22 +358,68 @@ __global__ __launch_bounds__(kBlk) void k_p2_scatter(PartSide s) {
 }
 
 // ---- work units -----------------------------------------------------------------------------------------------------------
+//
+// A unit is (partition, chunk of at most kJChunk dim keys, range of the
+// partition's fact rows). Units are ordered by decreasing size class of their
+// fact-row count, largest first, so long units start early.
+//
+// Key skew (Zipf) concentrates fact rows in the few partitions that hold the
+// hottest keys; one workgroup streaming such a partition alone would set the
+// kernel's length. A single-chunk partition with more than max(kSplitMin,
+// 4 x the mean) fact rows is therefore split into sub-units of kSubRows fact
+// rows. Each sub-unit builds the same LDS table, adds its partial sums into a
+// per-chunk device accumulator, and the sub-unit that finishes last emits the
+// chunk's groups from it (and clears it for the next call).
 
-// Units (partition, dim chunk) for partitions with both dim keys and fact
-// rows, ordered by decreasing size class of the fact-row count (largest first,
-// so skewed partitions start early). One workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_make_units(const uint32_t* __restrict__ dcount, const uint32_t* __restrict__ fcount,
-                                                     uint32_t nparts, uint32_t* __restrict__ unit_part,
-                                                     uint32_t* __restrict__ unit_chunk, int64_t* __restrict__ n_units) {
+constexpr uint32_t kSubRows = 8192;
+constexpr uint32_t kSplitMin = 3 * kSubRows / 2;
+constexpr uint32_t kMaxSplit = 256;  // split chunks per call (more are processed whole)
+constexpr uint32_t kNoSplit = ~0u;
+
+struct SplitAcc {
+  uint64_t sp, sq, cnt;
+};
+
+__device__ __forceinline__ uint32_t size_class(uint32_t rows) { return 32 - __clz(rows); }
+
+// One workgroup of 1024 threads. desc[u] = {dlo, dhi, flo, fhi}; split[u] =
+// {split id + 1 (0: not split), sub-units of the chunk}. sbase: nparts words.
+__global__ __launch_bounds__(1024) void k_make_units(const uint32_t* __restrict__ dstart, const uint32_t* __restrict__ dcount,
+                                                     const uint32_t* __restrict__ fstart, const uint32_t* __restrict__ fcount,
+                                                     uint32_t nparts, uint4* __restrict__ desc, uint2* __restrict__ split,
+                                                     uint32_t* __restrict__ sbase, int64_t* __restrict__ n_units) {
   __shared__ uint32_t cls_n[33];
   __shared__ uint32_t cls_cur[33];
+  __shared__ unsigned long long s_rows;
+  __shared__ uint32_t s_nsplit;
   for (int c = threadIdx.x; c < 33; c += blockDim.x) cls_n[c] = 0;
+  if (threadIdx.x == 0) {
+    s_rows = 0;
+    s_nsplit = 0;
+  }
   __syncthreads();
+  unsigned long long rows = 0;
+  for (uint32_t p = threadIdx.x; p < nparts; p += blockDim.x) rows += dcount[p] ? fcount[p] : 0u;
+  atomicAdd(&s_rows, rows);
+  __syncthreads();
+  const uint64_t mean4 = 4 * s_rows / (nparts ? nparts : 1);
+  const uint32_t thr = mean4 > kSplitMin ? (uint32_t)(mean4 < 0xffffffffull ? mean4 : 0xffffffffull) : kSplitMin;
   for (uint32_t p = threadIdx.x; p < nparts; p += blockDim.x) {
     const uint32_t fc = fcount[p], dc = dcount[p];
-    if (fc == 0 || dc == 0) continue;
-    const uint32_t chunks = (dc + kJChunk - 1) / kJChunk;
-    atomicAdd(&cls_n[32 - __clz(fc)], chunks);
+    uint32_t sb = kNoSplit;
+    if (fc != 0 && dc != 0) {
+      const uint32_t chunks = (dc + kJChunk - 1) / kJChunk;
+      uint32_t nsub = 1;
+      if (chunks == 1 && fc > thr) {
+        const uint32_t id = atomicAdd(&s_nsplit, 1u);
+        if (id < kMaxSplit) {
+          sb = id;
+          nsub = (fc + kSubRows - 1) / kSubRows;
+        }
+      }
+      atomicAdd(&cls_n[size_class(nsub > 1 ? kSubRows : fc)], chunks * nsub);
+    }
+    sbase[p] = sb;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -388,11 +434,24 @@ __global__ __launch_bounds__(1024) void k_make_units(const uint32_t* __restrict_
   for (uint32_t p = threadIdx.x; p < nparts; p += blockDim.x) {
     const uint32_t fc = fcount[p], dc = dcount[p];
     if (fc == 0 || dc == 0) continue;
+    const uint32_t ds = dstart[p], fs = fstart[p], sb = sbase[p];
     const uint32_t chunks = (dc + kJChunk - 1) / kJChunk;
-    const uint32_t pos = atomicAdd(&cls_cur[32 - __clz(fc)], chunks);
-    for (uint32_t c = 0; c < chunks; ++c) {
-      unit_part[pos + c] = p;
-      unit_chunk[pos + c] = c;
+    if (sb != kNoSplit) {
+      const uint32_t nsub = (fc + kSubRows - 1) / kSubRows;
+      uint32_t pos = atomicAdd(&cls_cur[size_class(kSubRows)], nsub);
+      for (uint32_t k = 0; k < nsub; ++k, ++pos) {
+        const uint32_t flo = fs + k * kSubRows;
+        const uint32_t fhi = flo + kSubRows < fs + fc ? flo + kSubRows : fs + fc;
+        desc[pos] = make_uint4(ds, ds + dc, flo, fhi);
+        split[pos] = make_uint2(sb + 1, nsub);
+      }
+    } else {
+      uint32_t pos = atomicAdd(&cls_cur[size_class(fc)], chunks);
+      for (uint32_t c = 0; c < chunks; ++c, ++pos) {
+        const uint32_t dlo = ds + c * kJChunk;
+        desc[pos] = make_uint4(dlo, dlo + kJChunk < ds + dc ? dlo + kJChunk : ds + dc, fs, fs + fc);
+        split[pos] = make_uint2(0, 1);
+      }
     }
   }
 }
@@ -400,18 +459,15 @@ __global__ __launch_bounds__(1024) void k_make_units(const uint32_t* __restrict_
 // ---- partitioned groupjoin -------------------------------------------------------------------------------------------
 
 struct JoinArgs {
-  const uint32_t* unit_part;
-  const uint32_t* unit_chunk;
+  const uint4* unit_desc;
+  const uint2* unit_split;
   const int64_t* n_units;
   const int32_t* dkey;
-  const uint32_t* dstart;
-  const uint32_t* dcount;
   const int32_t* fkey;
   const int64_t* fprice;
   const int32_t* fqty;
-  const uint32_t* fstart;
-  const uint32_t* fcount;
-  uint64_t* state;
+  SplitAcc* split_acc;    // [kMaxSplit][kJChunk], zero between calls
+  uint32_t* split_done;   // [kMaxSplit], zero between calls
   int64_t* ticket;
   int64_t* matched;
   uint32_t* status;
@@ -421,102 +477,135 @@ struct JoinArgs {
   int64_t* out_cnt;
   int64_t out_cap;
   int64_t* d_n;
+  uint32_t zero;  // 0 at run time; see take_ticket
 };
 
 constexpr uint64_t kLdsEmpty = ~0ull;
+constexpr int kJR = 4;                                   // fact rows per thread per step
+constexpr int kJDK = (kJChunk + kJBlock - 1) / kJBlock;  // dim keys per thread
+constexpr int kJPer = kJSlots / kJBlock;                 // LDS slots per thread at emission
 
-// Row ranges of one unit: dim keys [dlo, dhi) of its chunk, fact rows [flo, fhi).
-struct UnitBounds {
-  uint32_t dlo, dhi, flo, fhi;
-};
-
-__device__ __forceinline__ UnitBounds unit_bounds(const JoinArgs& a, int64_t u, int64_t n_units) {
-  UnitBounds b{0, 0, 0, 0};
-  if (u >= n_units) return b;
-  const uint32_t p = a.unit_part[u], chunk = a.unit_chunk[u];
-  const uint32_t ds = a.dstart[p], dend = ds + a.dcount[p];
-  b.dlo = ds + chunk * (uint32_t)kJChunk;
-  b.dhi = b.dlo + kJChunk < dend ? b.dlo + kJChunk : dend;
-  b.flo = a.fstart[p];
-  b.fhi = b.flo + a.fcount[p];
-  return b;
+// The next unit's ticket. The address is written so that the compiler cannot
+// prove it uniform (zero is a run-time 0): a uniform-address atomic would be
+// rewritten into a wave-wide one whose result is broadcast at once, stalling
+// the wave on the round trip; this way the wave waits only where the ticket
+// is used, after the current unit's build.
+__device__ __forceinline__ int64_t take_ticket(const JoinArgs& a) {
+  unsigned long long* t = (unsigned long long*)a.ticket + threadIdx.x * a.zero;
+  return (int64_t)__hip_atomic_fetch_add(t, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+struct RowRegs {
+  int32_t key[kJR];
+  int32_t qty[kJR];
+  uint64_t sp[kJR];
+};
 
-__global__ __launch_bounds__(kJBlock) void k_part_groupjoin(JoinArgs a) {
+__device__ __forceinline__ void load_rows(const JoinArgs& a, uint32_t i0, uint32_t fhi, RowRegs& r) {
+#pragma unroll
+  for (int k = 0; k < kJR; ++k) {
+    const uint32_t i = i0 + k * kJBlock;
+    const bool ok = i < fhi;
+    r.key[k] = ok ? a.fkey[i] : 0;
+    r.sp[k] = ok ? (uint64_t)a.fprice[i] : 0;
+    r.qty[k] = ok ? a.fqty[i] : 0;
+  }
+}
+
+__device__ __forceinline__ void load_dkeys(const JoinArgs& a, uint32_t dlo, uint32_t dhi, int32_t (&dk)[kJDK]) {
+#pragma unroll
+  for (int k = 0; k < kJDK; ++k) {
+    const uint32_t j = dlo + threadIdx.x + k * kJBlock;
+    dk[k] = j < dhi ? a.dkey[j] : 0;
+  }
+}
+
+// Reserve room for `mine` groups of this thread (block-wide scan, one atomic
+// per call) and return this thread's first output row.
+__device__ __forceinline__ int64_t reserve_out(const JoinArgs& a, uint32_t mine, uint32_t* scr, uint64_t* s_excl) {
+  uint32_t total;
+  const uint32_t off = block_excl_scan<kJBlock>(mine, scr, &total);
+  if (threadIdx.x == 0)
+    *s_excl = total ? dev_add_ret<unsigned long long>((unsigned long long*)a.d_n, (unsigned long long)total) : 0;
+  __syncthreads();
+  return (int64_t)*s_excl + off;
+}
+
+__device__ __forceinline__ void put_group(const JoinArgs& a, int64_t o, int64_t key, uint64_t sp, uint64_t sq, uint64_t c) {
+  if (o < a.out_cap) {
+    a.out_key[o] = key;
+    a.out_sp[o] = (int64_t)sp;
+    a.out_sq[o] = (int64_t)sq;
+    a.out_cnt[o] = (int64_t)c;
+  } else {
+    set_status(a.status, kDevOverflow);
+  }
+}
+
+// Two workgroups per CU (LDS), so at most 128 VGPRs (four waves per SIMD).
+__global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
   __shared__ uint64_t tkey[kJSlots];  // {key, 1} packed; all ones = empty
   __shared__ uint32_t tcnt[kJSlots];
   __shared__ uint64_t tsp[kJSlots];
   __shared__ uint64_t tsq[kJSlots];
+  __shared__ uint16_t tpos[kJSlots];  // the key's position in its chunk (split units)
   __shared__ uint32_t scr[kJBlock / kWave];
   __shared__ uint64_t s_excl;
+  __shared__ uint4 s_desc;
+  __shared__ uint2 s_split;
+  __shared__ int64_t s_u;
+  __shared__ uint32_t s_last;
   const int64_t n_units = *a.n_units;
-  const uint32_t lane = lane_id();
+  const uint32_t tid = threadIdx.x, lane = lane_id();
   uint64_t matched = 0;
-  // Units are taken from the largest-first list by ticket (dynamic, so a
-  // workgroup stuck on a skewed partition takes fewer units). The ticket and
-  // bounds of the next unit are fetched one unit ahead by thread 0, and each
-  // unit loads its dim keys and first fact rows together, so a unit waits on
-  // one memory round trip before its LDS work.
-  __shared__ UnitBounds s_cur, s_nxt;
-  __shared__ int64_t s_nxt_u;
-  constexpr int R = 4;                                     // fact rows per thread per step
-  constexpr int DK = (kJChunk + kJBlock - 1) / kJBlock;    // dim keys per thread
-  if (threadIdx.x == 0) {
-    const int64_t t = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)a.ticket, 1ull);
-    s_nxt_u = t;
-    s_nxt = unit_bounds(a, t, n_units);
+  // Units come from the largest-first list by ticket (dynamic, so a workgroup
+  // held up by a long unit takes fewer). While a unit probes, thread 0 already
+  // holds the next ticket and reads the next unit's descriptor; after the
+  // probe every thread issues the next unit's dim-key and first fact-row loads,
+  // which then travel during this unit's emission.
+  if (tid == 0) {
+    const int64_t t = take_ticket(a);
+    s_u = t;
+    if (t < n_units) {
+      s_desc = a.unit_desc[t];
+      s_split = a.unit_split[t];
+    }
   }
   __syncthreads();
-  for (;;) {
-    const int64_t u = s_nxt_u;
-    if (u >= n_units) break;
-    const UnitBounds cur = s_nxt;
-    int64_t t_next = 0;
-    if (threadIdx.x == 0) t_next = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)a.ticket, 1ull);
-    const uint32_t dlo = cur.dlo, dhi = cur.dhi, flo = cur.flo, fhi = cur.fhi;
-    int32_t dkeys[DK];
-#pragma unroll
-    for (int k = 0; k < DK; ++k) {
-      const uint32_t j = dlo + threadIdx.x + k * kJBlock;
-      dkeys[k] = j < dhi ? a.dkey[j] : 0;
-    }
-    // fact rows in two register sets: while one step's rows are probed, the
-    // next step's are already in flight (long, skewed partitions)
-    int32_t keys[R], nkeys[R];
-    uint64_t sps[R], sqs[R], nsps[R], nsqs[R];
-    auto load_rows = [&](uint32_t i0, int32_t(&kk)[R], uint64_t(&pp)[R], uint64_t(&qq)[R]) {
-#pragma unroll
-      for (int k = 0; k < R; ++k) {
-        const uint32_t i = i0 + k * kJBlock;
-        const bool ok = i < fhi;
-        kk[k] = ok ? a.fkey[i] : 0;
-        pp[k] = ok ? (uint64_t)a.fprice[i] : 0;
-        qq[k] = ok ? (uint64_t)(int64_t)a.fqty[i] : 0;
-      }
-    };
-    load_rows(flo + threadIdx.x, keys, sps, sqs);
-    for (int s = threadIdx.x; s < kJSlots; s += kJBlock) {
+  int64_t u = s_u;
+  uint4 d = s_desc;
+  uint2 sp = s_split;
+  int32_t dkeys[kJDK];
+  RowRegs cur, nxt;
+  if (u < n_units) {
+    load_dkeys(a, d.x, d.y, dkeys);
+    load_rows(a, d.z + tid, d.w, cur);
+  }
+  while (u < n_units) {
+    const uint32_t dlo = d.x, dhi = d.y, flo = d.z, fhi = d.w;
+    int64_t tn = 0;
+    if (tid == 0) tn = take_ticket(a);
+    for (int s = tid; s < kJSlots; s += kJBlock) {
       tkey[s] = kLdsEmpty;
       tcnt[s] = 0;
       tsp[s] = 0;
       tsq[s] = 0;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {  // the next unit, read by everyone after this unit's last barrier
-      s_nxt_u = t_next;
-      s_nxt = unit_bounds(a, t_next, n_units);
-    }
     // build: at most kJChunk unique keys into kJSlots slots, so a free slot always exists
 #pragma unroll
-    for (int k = 0; k < DK; ++k) {
-      if (dlo + threadIdx.x + k * kJBlock >= dhi) continue;
+    for (int k = 0; k < kJDK; ++k) {
+      const uint32_t pos = tid + k * kJBlock;
+      if (dlo + pos >= dhi) continue;
       const int32_t key = dkeys[k];
       const uint64_t want = (uint64_t)(uint32_t)key | (1ull << 32);
       uint32_t h = slot_hash(key);
       for (int step = 0; step < kJSlots; ++step) {
         const uint64_t old = atomicCAS((unsigned long long*)&tkey[h], (unsigned long long)kLdsEmpty, (unsigned long long)want);
-        if (old == kLdsEmpty) break;
+        if (old == kLdsEmpty) {
+          tpos[h] = (uint16_t)pos;
+          break;
+        }
         if (old == want) {
           set_status(a.status, kDevDupKey);
           break;
@@ -525,35 +614,34 @@ __global__ __launch_bounds__(kJBlock) void k_part_groupjoin(JoinArgs a) {
       }
     }
     __syncthreads();
-    // probe and aggregate in LDS
+    uint4 nd = make_uint4(0, 0, 0, 0);
+    uint2 ns = make_uint2(0, 0);
+    if (tid == 0 && tn < n_units) {
+      nd = a.unit_desc[tn];
+      ns = a.unit_split[tn];
+    }
+    // probe and aggregate in LDS; long units stream further steps through nxt
     const uint32_t nrows = fhi - flo;
-    const uint32_t iters = (nrows + R * kJBlock - 1) / (R * kJBlock);  // uniform over the workgroup
+    const uint32_t iters = (nrows + kJR * kJBlock - 1) / (kJR * kJBlock);  // uniform over the workgroup
     for (uint32_t it = 0; it < iters; ++it) {
-      const uint32_t i0 = flo + it * (R * kJBlock) + threadIdx.x;
-      if (it > 0) {
+      const uint32_t i0 = flo + it * (kJR * kJBlock) + tid;
+      if (it > 0) cur = nxt;
+      if (it + 1 < iters) load_rows(a, i0 + kJR * kJBlock, fhi, nxt);
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-          keys[k] = nkeys[k];
-          sps[k] = nsps[k];
-          sqs[k] = nsqs[k];
-        }
-      }
-      if (it + 1 < iters) load_rows(i0 + R * kJBlock, nkeys, nsps, nsqs);
-#pragma unroll
-      for (int k = 0; k < R; ++k) {
+      for (int k = 0; k < kJR; ++k) {
         bool found = false;
         int slot = 0;
         if (i0 + k * kJBlock < fhi) {
-          const uint64_t want = (uint64_t)(uint32_t)keys[k] | (1ull << 32);
-          uint32_t h = slot_hash(keys[k]);
+          const uint64_t want = (uint64_t)(uint32_t)cur.key[k] | (1ull << 32);
+          uint32_t h = slot_hash(cur.key[k]);
           for (int step = 0; step < kJSlots; ++step) {
-            const uint64_t cur = tkey[h];
-            if (cur == want) {
+            const uint64_t c = tkey[h];
+            if (c == want) {
               found = true;
               slot = (int)h;
               break;
             }
-            if (cur == kLdsEmpty) break;
+            if (c == kLdsEmpty) break;
             h = (h + 1) & (kJSlots - 1);
           }
         }
@@ -567,8 +655,8 @@ __global__ __launch_bounds__(kJBlock) void k_part_groupjoin(JoinArgs a) {
         const uint64_t same = wave_ballot(found && slot == s0);
         if (__popcll(same) >= kCombineMin) {
           const bool mine = found && slot == s0;
-          const uint64_t tsum_p = wave_sum_u64(mine ? sps[k] : 0);
-          const uint64_t tsum_q = wave_sum_u64(mine ? sqs[k] : 0);
+          const uint64_t tsum_p = wave_sum_u64(mine ? cur.sp[k] : 0);
+          const uint64_t tsum_q = wave_sum_u64(mine ? (uint64_t)(int64_t)cur.qty[k] : 0);
           if ((int)lane == first) {
             atomicAdd((unsigned long long*)&tsp[s0], (unsigned long long)tsum_p);
             atomicAdd((unsigned long long*)&tsq[s0], (unsigned long long)tsum_q);
@@ -577,41 +665,91 @@ __global__ __launch_bounds__(kJBlock) void k_part_groupjoin(JoinArgs a) {
           found = found && !mine;
         }
         if (found) {
-          atomicAdd((unsigned long long*)&tsp[slot], (unsigned long long)sps[k]);
-          atomicAdd((unsigned long long*)&tsq[slot], (unsigned long long)sqs[k]);
+          atomicAdd((unsigned long long*)&tsp[slot], (unsigned long long)cur.sp[k]);
+          atomicAdd((unsigned long long*)&tsq[slot], (unsigned long long)(int64_t)cur.qty[k]);
           atomicAdd(&tcnt[slot], 1u);
         }
       }
     }
-    __syncthreads();
-    // Emit the unit's groups. Output room is reserved with one atomic per unit,
-    // taken when the unit finishes, so no unit waits on another.
-    constexpr int kPer = kJSlots / kJBlock;
-    uint32_t mine = 0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) mine += tcnt[threadIdx.x * kPer + k] != 0;
-    uint32_t total;
-    const uint32_t off = block_excl_scan<kJBlock>(mine, scr, &total);
-    if (threadIdx.x == 0)
-      s_excl = total ? dev_add_ret<unsigned long long>((unsigned long long*)a.d_n, (unsigned long long)total) : 0;
-    __syncthreads();
-    int64_t o = (int64_t)s_excl + off;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int s = threadIdx.x * kPer + k;
-      const uint32_t c = tcnt[s];
-      if (c == 0) continue;
-      if (o < a.out_cap) {
-        a.out_key[o] = (int64_t)(int32_t)(uint32_t)tkey[s];
-        a.out_sp[o] = (int64_t)tsp[s];
-        a.out_sq[o] = (int64_t)tsq[s];
-        a.out_cnt[o] = (int64_t)c;
-      } else {
-        set_status(a.status, kDevOverflow);
-      }
-      ++o;
+    if (tid == 0) {
+      s_u = tn;
+      s_desc = nd;
+      s_split = ns;
     }
     __syncthreads();
+    const int64_t un = s_u;
+    const uint4 dn = s_desc;
+    const uint2 sn = s_split;
+    int32_t ndkeys[kJDK];
+    if (un < n_units) {
+      load_dkeys(a, dn.x, dn.y, ndkeys);
+      load_rows(a, dn.z + tid, dn.w, nxt);
+    }
+    if (sp.x == 0) {
+      // Whole unit: emit its groups. Output room is reserved with one atomic
+      // per unit, taken when the unit finishes, so no unit waits on another.
+      uint32_t mine = 0;
+#pragma unroll
+      for (int k = 0; k < kJPer; ++k) mine += tcnt[tid * kJPer + k] != 0;
+      int64_t o = reserve_out(a, mine, scr, &s_excl);
+#pragma unroll
+      for (int k = 0; k < kJPer; ++k) {
+        const int s = tid * kJPer + k;
+        const uint32_t c = tcnt[s];
+        if (c == 0) continue;
+        put_group(a, o++, (int64_t)(int32_t)(uint32_t)tkey[s], tsp[s], tsq[s], c);
+      }
+    } else {
+      // Sub-unit of a split chunk: add the partial sums into the chunk's
+      // accumulator; the last sub-unit to finish emits and clears it.
+      SplitAcc* acc = a.split_acc + (size_t)(sp.x - 1) * kJChunk;
+#pragma unroll
+      for (int k = 0; k < kJPer; ++k) {
+        const int s = tid * kJPer + k;
+        const uint32_t c = tcnt[s];
+        if (c == 0) continue;
+        SplitAcc* e = acc + tpos[s];
+        dev_add<uint64_t>(&e->sp, tsp[s]);
+        dev_add<uint64_t>(&e->sq, tsq[s]);
+        dev_add<uint64_t>(&e->cnt, (uint64_t)c);
+      }
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) s_last = dev_add_ret<uint32_t>(&a.split_done[sp.x - 1], 1u) + 1 == sp.y;
+      __syncthreads();
+      if (s_last) {
+        __threadfence();
+        // a count fits 32 bits (fewer than 2^31 fact rows); the sums are read again when written
+        uint32_t vc[kJDK];
+        uint32_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < kJDK; ++k) {
+          const uint32_t pos = tid + k * kJBlock;
+          vc[k] = dlo + pos < dhi ? (uint32_t)__hip_atomic_load(&acc[pos].cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+          mine += vc[k] != 0;
+        }
+        if (tid == 0) a.split_done[sp.x - 1] = 0;
+        int64_t o = reserve_out(a, mine, scr, &s_excl);
+#pragma unroll
+        for (int k = 0; k < kJDK; ++k) {
+          if (vc[k] == 0) continue;
+          SplitAcc* e = acc + tid + k * kJBlock;
+          const uint64_t vp = __hip_atomic_load(&e->sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const uint64_t vq = __hip_atomic_load(&e->sq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          put_group(a, o++, (int64_t)dkeys[k], vp, vq, vc[k]);
+          e->sp = 0;
+          e->sq = 0;
+          e->cnt = 0;
+        }
+      }
+    }
+    __syncthreads();  // the table, s_excl and s_last are reused by the next unit
+    u = un;
+    d = dn;
+    sp = sn;
+#pragma unroll
+    for (int k = 0; k < kJDK; ++k) dkeys[k] = ndkeys[k];
+    cur = nxt;
   }
   matched = wave_sum_u64(matched);
   if (lane == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
@@ -702,7 +840,8 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   const uint32_t nb1 = 1u << b1, nb2 = 1u << b2, nparts = nb1 * nb2;
   const int64_t fnt1 = (n + kTile1 - 1) / kTile1, dnt1 = (m + kTile1 - 1) / kTile1;
   const int64_t fnt2 = n / kTile2 + nb1, dnt2 = m / kTile2 + nb1;
-  const int64_t max_units = (int64_t)nparts + m / kJChunk + 1;
+  // whole chunks, plus the sub-units of split chunks (each split chunk adds at most one partial sub-unit)
+  const int64_t max_units = (int64_t)nparts + m / kJChunk + 1 + n / kSubRows + kMaxSplit;
 
   // scratch: partitioned columns (A: fact level 1, B: fact level 2, C: dim both levels), bookkeeping (D)
   void *pa, *pb, *pc, *pd;
@@ -711,8 +850,15 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   TRY(scratch(ctx, SCR_PART_B, fact_bytes, &pb));
   TRY(scratch(ctx, SCR_PART_C, (size_t)(m > 0 ? m : 1) * 16 + 4 * 256, &pc));
   const size_t book = ((size_t)fnt1 * nb1 + (size_t)dnt1 * nb1 + (size_t)fnt2 * nb2 + (size_t)dnt2 * nb2 + 2 * nb1 +
-                       4 * (size_t)nparts + 2 * (size_t)max_units) * 4 + (size_t)max_units * 8 + 64 * 256;
+                       5 * (size_t)nparts) * 4 + (size_t)max_units * (sizeof(uint4) + sizeof(uint2)) + 64 * 256;
   TRY(scratch(ctx, SCR_PART_D, book, &pd));
+  // split-chunk accumulators and their done counters: zero when allocated, and
+  // left zero by every call (the last sub-unit of a chunk clears what it emits)
+  void* pe;
+  const size_t split_bytes = (size_t)kMaxSplit * kJChunk * sizeof(SplitAcc) + kMaxSplit * sizeof(uint32_t);
+  const bool fresh = ctx->scratch[SCR_PART_E].bytes < split_bytes;
+  TRY(scratch(ctx, SCR_PART_E, split_bytes, &pe));
+  if (fresh) TRY(fill_u32(ctx, pe, split_bytes / 4, 0));
 
   PartSide F{};
   F.key = fact->fk;
@@ -752,9 +898,9 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   D.pstart = cd.take<uint32_t>(nparts);
   D.pcount = cd.take<uint32_t>(nparts);
 
-  uint32_t* unit_part = cd.take<uint32_t>(max_units);
-  uint32_t* unit_chunk = cd.take<uint32_t>(max_units);
-  uint64_t* state = cd.take<uint64_t>(max_units);
+  uint4* unit_desc = cd.take<uint4>(max_units);
+  uint2* unit_split = cd.take<uint2>(max_units);
+  uint32_t* sbase = cd.take<uint32_t>(nparts);
   int64_t* n_units = counters + CNT_AUX0;
   int64_t* ticket = counters + CNT_TICKET;
 
@@ -764,26 +910,24 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   {
     {
       KernelTimer kt(ctx, "make_units");
-      hipLaunchKernelGGL(k_make_units, dim3(1), dim3(1024), 0, ctx->stream, D.pcount, F.pcount, nparts, unit_part,
-                         unit_chunk, n_units);
+      hipLaunchKernelGGL(k_make_units, dim3(1), dim3(1024), 0, ctx->stream, D.pstart, D.pcount, F.pstart, F.pcount,
+                         nparts, unit_desc, unit_split, sbase, n_units);
     }
     REL_LAUNCH_CHECK(ctx, "make_units");
     TRY(fill_u64(ctx, ticket, 1, 0));
     TRY(fill_u64(ctx, out->d_n_groups, 1, 0));
     KernelTimer kt(ctx, "part_groupjoin");
     JoinArgs a{};
-    a.unit_part = unit_part;
-    a.unit_chunk = unit_chunk;
+    a.unit_desc = unit_desc;
+    a.unit_split = unit_split;
     a.n_units = n_units;
     a.dkey = D.key2;
-    a.dstart = D.pstart;
-    a.dcount = D.pcount;
     a.fkey = F.key2;
     a.fprice = F.price2;
     a.fqty = F.qty2;
-    a.fstart = F.pstart;
-    a.fcount = F.pcount;
-    a.state = state;
+    a.split_acc = (SplitAcc*)pe;
+    a.split_done = (uint32_t*)((char*)pe + (size_t)kMaxSplit * kJChunk * sizeof(SplitAcc));
+    a.zero = 0;
     a.ticket = ticket;
     a.matched = counters + CNT_JOIN_MATCHES;
     a.status = ctx->d_status;
@@ -793,7 +937,7 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
     a.out_cnt = out->count;
     a.out_cap = out->cap;
     a.d_n = out->d_n_groups;
-    const unsigned grid = (unsigned)ctx->num_cus * 2;  // 56 KB of LDS each: two per CU
+    const unsigned grid = (unsigned)ctx->num_cus * 2;  // 60 KB of LDS each: two per CU
     hipLaunchKernelGGL(k_part_groupjoin, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
     REL_LAUNCH_CHECK(ctx, "part_groupjoin");
   }

@@ -243,6 +243,28 @@ def test_partitioned_oversized_partition_is_chunked(ctx):
     run_both(ctx, T, plan=_partitioned())
 
 
+def test_partitioned_hot_partitions_are_split(ctx):
+    # Zipf(1.5): the hottest key alone holds about a third of the rows, so its
+    # partition is split into sub-units that merge through a device accumulator.
+    # Three calls in a row: each must find the accumulators cleared by the last.
+    T = datagen.make_tables(2_000_000, 400_000, 71, day_lt=1800, group_by="fk", fk_zipf=1.5, fk_domain=420_000)
+    run_both(ctx, T, plan=_partitioned(), repeats=3)
+
+
+def test_partitioned_more_hot_partitions_than_split_slots(ctx):
+    # 300 hot keys take 80% of 12M rows: more hot partitions than a call can
+    # split (the rest run whole). Hot keys include -1 and a key absent from dim.
+    n, m = 12_000_000, 2_000_000
+    T = datagen.make_tables(n, m, 72, day_lt=2557, group_by="fk", fk_domain=m)
+    hot = T.pk[datagen.sample_index(300, m, 72, 90)].copy()
+    T.pk[int(datagen.sample_index(1, m, 72, 91)[0])] = -1
+    hot[0], hot[1] = -1, m + 100  # m + 100 is not a dim key
+    pick = datagen.uniform(n, 0, 299, np.int64, 72, 92)
+    is_hot = datagen.unit(n, 72, 93) < 0.8
+    T.fk = np.where(is_hot, hot[pick], T.fk).astype(np.int32)
+    run_both(ctx, T, plan=_partitioned(), repeats=2)
+
+
 @pytest.mark.parametrize("case", ["empty_fact", "empty_dim", "all_filtered", "no_match"])
 def test_partitioned_degenerate(ctx, case):
     n, m = (0 if case == "empty_fact" else 50_000), (0 if case == "empty_dim" else 9_000)
