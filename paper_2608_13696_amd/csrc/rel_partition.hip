@@ -24,9 +24,12 @@ namespace {
 
 using namespace rel;
 
-constexpr int kBlk = 256;
-constexpr int64_t kTile1 = 4096;  // input rows per first-level tile (staged in LDS)
-constexpr int64_t kTile2 = 4096;  // partition rows per second-level tile
+constexpr int kBlk = 256;         // histogram and scan kernels
+constexpr int kSBlk = 512;        // scatter kernels
+// First level: one 2048-row tile per workgroup (36 KB of LDS, four per CU).
+// Second level: persistent workgroups over 4096-row tiles (two per CU).
+constexpr int64_t kTile1 = 2048;
+constexpr int64_t kTile = 4096;
 constexpr int kMaxBins = 256;
 constexpr int kJBlock = 512;
 constexpr int kJSlotBits = 11;
@@ -67,6 +70,30 @@ struct PartSide {
   uint32_t b1, b2;
 };
 
+// ---- tile walks -------------------------------------------------------------------------------------------------------
+//
+// The scatter and second-level kernels are persistent: a fixed grid (a
+// multiple of 8) walks the tiles, each workgroup loading its next tile while
+// it sorts and writes the current one. XCD x (= blockIdx % 8, the hardware's
+// round-robin dispatch) takes the contiguous tile range [x T / 8, (x + 1) T / 8)
+// with its workgroups interleaved inside it, so the tiles an XCD holds at one
+// time are neighbours: their runs in each partition are adjacent in memory and
+// meet in that XCD's L2 before they are written back.
+struct TileWalk {
+  int64_t next, hi, step;
+  __device__ TileWalk(int64_t T) {
+    const uint32_t x = blockIdx.x % kNumXcd, i = blockIdx.x / kNumXcd;
+    step = gridDim.x / kNumXcd;
+    next = T * x / kNumXcd + i;
+    hi = T * (x + 1) / kNumXcd;
+  }
+  __device__ int64_t take() {
+    const int64_t t = next < hi ? next : -1;
+    next += step;
+    return t;
+  }
+};
+
 // ---- first level -------------------------------------------------------------------------------------------------------
 
 template <bool FACT>
@@ -103,27 +130,49 @@ __global__ __launch_bounds__(kBlk) void k_p1_hist(PartSide s) {
   for (uint32_t b = threadIdx.x; b < nb1; b += kBlk) s.hist1[(size_t)b * gridDim.x + tile] = h[b];
 }
 
-// Column b of hist1 (one bin over all tiles) -> exclusive prefix in place; tot1[b] = column sum.
+// Column b of hist1 (one bin over all tiles) -> exclusive prefix in place;
+// tot1[b] = column sum. The column goes through LDS in chunks so that global
+// reads and writes are coalesced while each thread scans a contiguous run.
+constexpr int kColPer = 16;
 __global__ __launch_bounds__(kBlk) void k_p1_colscan(uint32_t* __restrict__ hist1, int64_t ntiles, uint32_t nb1,
                                                      uint32_t* __restrict__ tot1, int64_t* __restrict__ passed) {
+  __shared__ uint32_t buf[kBlk * kColPer];
   __shared__ uint32_t scr[kBlk / kWave];
-  const uint32_t b = blockIdx.x;
-  uint32_t* col = hist1 + (size_t)b * ntiles;
-  // each thread owns a contiguous run of the column: sum it, scan the sums, rescan the run
-  const int64_t per = (ntiles + kBlk - 1) / kBlk;
-  const int64_t lo = threadIdx.x * per, hi = lo + per < ntiles ? lo + per : ntiles;
-  uint32_t sum = 0;
-  for (int64_t t = lo; t < hi; ++t) sum += col[t];
-  uint32_t tot;
-  uint32_t run = block_excl_scan<kBlk>(sum, scr, &tot);
-  for (int64_t t = lo; t < hi; ++t) {
-    const uint32_t v = col[t];
-    col[t] = run;
-    run += v;
+  uint32_t* col = hist1 + (size_t)blockIdx.x * ntiles;
+  uint32_t carry = 0;
+  for (int64_t c0 = 0; c0 < ntiles; c0 += kBlk * kColPer) {
+    const int64_t len = ntiles - c0 < kBlk * kColPer ? ntiles - c0 : kBlk * kColPer;
+    uint32_t v[kColPer];
+#pragma unroll
+    for (int k = 0; k < kColPer; ++k) {
+      const int64_t j = threadIdx.x + k * kBlk;
+      v[k] = j < len ? col[c0 + j] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kColPer; ++k) buf[threadIdx.x + k * kBlk] = v[k];
+    __syncthreads();
+    uint32_t run[kColPer], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kColPer; ++k) {
+      run[k] = sum;
+      sum += buf[threadIdx.x * kColPer + k];
+    }
+    uint32_t tot;
+    const uint32_t off = block_excl_scan<kBlk>(sum, scr, &tot);
+#pragma unroll
+    for (int k = 0; k < kColPer; ++k) buf[threadIdx.x * kColPer + k] = carry + off + run[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kColPer; ++k) {
+      const int64_t j = threadIdx.x + k * kBlk;
+      if (j < len) col[c0 + j] = buf[j];
+    }
+    carry += tot;
+    __syncthreads();
   }
   if (threadIdx.x == 0) {
-    tot1[b] = tot;
-    if (passed) dev_add<unsigned long long>((unsigned long long*)passed, (unsigned long long)tot);
+    tot1[blockIdx.x] = carry;
+    if (passed) dev_add<unsigned long long>((unsigned long long*)passed, (unsigned long long)carry);
   }
 }
 
@@ -133,228 +182,369 @@ __global__ __launch_bounds__(kBlk) void k_p1_colscan(uint32_t* __restrict__ hist
 // 64 lanes' stores on up to 64 different cache lines; partly written lines
 // are then evicted and written back several times over. Instead a tile's rows
 // are first counting-sorted by partition in LDS, then each partition's run is
-// written by consecutive lanes to consecutive addresses. With tiles of one
-// XCD kept contiguous (xcd_tile), the runs of neighbouring tiles meet inside
-// the same L2, and written bytes stay close to the payload.
+// written by consecutive lanes to consecutive addresses.
 
-constexpr int kRowsPerThread = (int)(kTile1 / kBlk);
-static_assert(kTile1 == kTile2, "both levels stage tiles of one size");
-
-template <bool FACT>
+template <bool FACT, int TILE>
 struct Stage {
-  uint32_t lcnt[kMaxBins];
-  uint32_t lbase[kMaxBins];
-  uint32_t gbase[kMaxBins];
-  uint32_t scr[kBlk / kWave];
-  int32_t key[kTile1];
-  int64_t price[FACT ? kTile1 : 1];
-  int32_t val[kTile1];  // qty (fact) or payload (dim)
-  uint8_t bin[kTile1];
+  uint32_t lcnt[kMaxBins];   // rows per bin in this tile; zero between tiles
+  uint32_t lbase[kMaxBins];  // first LDS row of each bin
+  uint32_t delta[kMaxBins];  // gbase - lbase (mod 2^32): output position = delta[bin] + LDS row
+  uint32_t gbase[kMaxBins];  // this tile's start in each bin's output run
+  uint32_t total;            // rows staged in this tile
+  uint32_t scr[kSBlk / kWave];
+  int2 kv[TILE];             // {key, qty (fact) or payload (dim)}
+  int64_t price[FACT ? TILE : 1];
 };
 
-// Rows this thread holds: valid[k], key[k], price[k], val[k], bin[k]. Sorts
-// the workgroup's rows by bin in LDS and writes them to dst at
-// st.gbase[bin] + rank within the bin. st.gbase must be set and visible.
-template <bool FACT, int R>
-__device__ __forceinline__ void stage_and_write(Stage<FACT>& st, const bool (&valid)[R], const int32_t (&key)[R],
-                                                const int64_t (&price)[R], const int32_t (&val)[R],
-                                                const uint32_t (&bin)[R], uint32_t nb, bool with_val, int32_t* dkey,
+// The rows one thread holds for one tile. valid: bit k set when row k is in
+// range; with DAY (fact rows at the first level) the predicate on day[k] is
+// applied only when the rows are used, so a prefetched tile's loads are not
+// waited for early.
+template <bool FACT, bool DAY, int R>
+struct TileRows {
+  int32_t key[R];
+  int32_t val[R];
+  int64_t price[FACT ? R : 1];
+  int32_t day[DAY ? R : 1];
+  uint32_t valid;
+};
+
+// Bin of a key at a level: `shift` drops the low hash bits, `mask` keeps the level's bits.
+struct BinOf {
+  uint32_t shift, mask;
+  __device__ uint32_t operator()(int32_t key) const { return (phash(key) >> shift) & mask; }
+};
+
+// Sorts the workgroup's rows by bin in LDS and writes each to its bin's output
+// run at gbase[bin] + rank within the bin. Three barriers per tile:
+//   ranks (LDS atomics) | wave 0 scans the counts and clears them for the next
+//   tile | rows move to their LDS rows | written out in LDS order.
+// Callers write st.gbase before the call (it is read after the first barrier)
+// and clear st.lcnt once before the first tile. No barrier at the end: the
+// next tile's first barrier orders its scan after this tile's write-out.
+template <bool FACT, bool DAY, int NT, int TILE>
+__device__ __forceinline__ void stage_and_write(Stage<FACT, TILE>& st, TileRows<FACT, DAY, TILE / NT>& r, int32_t day_lt,
+                                                BinOf bin_of, uint32_t nb, bool with_val, int32_t* dkey,
                                                 int64_t* dprice, int32_t* dval) {
-  for (uint32_t b = threadIdx.x; b < nb; b += kBlk) st.lcnt[b] = 0;
-  __syncthreads();
+  constexpr int R = TILE / NT;
+  if (DAY) {
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+      if (r.day[k] >= day_lt) r.valid &= ~(1u << k);
+  }
   uint32_t rank[R];
 #pragma unroll
-  for (int k = 0; k < R; ++k) rank[k] = valid[k] ? atomicAdd(&st.lcnt[bin[k]], 1u) : 0u;
+  for (int k = 0; k < R; ++k) rank[k] = (r.valid >> k) & 1u ? atomicAdd(&st.lcnt[bin_of(r.key[k])], 1u) : 0u;
   __syncthreads();
-  uint32_t total;
-  const uint32_t lb = block_excl_scan<kBlk>(threadIdx.x < nb ? st.lcnt[threadIdx.x] : 0u, st.scr, &total);
-  if (threadIdx.x < nb) st.lbase[threadIdx.x] = lb;
+  if (threadIdx.x < kWave) {
+    // wave 0: exclusive scan of the counts, four bins per lane (nb <= 256)
+    constexpr int kPerLane = kMaxBins / kWave;
+    const uint32_t lane = threadIdx.x;
+    uint32_t c[kPerLane], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPerLane; ++k) {
+      const uint32_t b = lane * kPerLane + k;
+      c[k] = b < nb ? st.lcnt[b] : 0u;
+      sum += c[k];
+    }
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t t = __shfl_up(incl, o, kWave);
+      if (lane >= (uint32_t)o) incl += t;
+    }
+    uint32_t run = incl - sum;
+#pragma unroll
+    for (int k = 0; k < kPerLane; ++k) {
+      const uint32_t b = lane * kPerLane + k;
+      if (b < nb) {
+        st.lbase[b] = run;
+        st.delta[b] = st.gbase[b] - run;
+        st.lcnt[b] = 0;
+      }
+      run += c[k];
+    }
+    if (lane == kWave - 1) st.total = incl;
+  }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    if (!valid[k]) continue;
-    const uint32_t slot = st.lbase[bin[k]] + rank[k];
-    st.key[slot] = key[k];
-    if (FACT) st.price[slot] = price[k];
-    st.val[slot] = val[k];
-    st.bin[slot] = (uint8_t)bin[k];
+    if (!((r.valid >> k) & 1u)) continue;
+    const uint32_t slot = st.lbase[bin_of(r.key[k])] + rank[k];
+    st.kv[slot] = make_int2(r.key[k], r.val[k]);
+    if (FACT) st.price[slot] = r.price[k];
   }
   __syncthreads();
-  for (uint32_t j = threadIdx.x; j < total; j += kBlk) {
-    const uint32_t b = st.bin[j];
-    const uint32_t pos = st.gbase[b] + (j - st.lbase[b]);
-    dkey[pos] = st.key[j];
+  const uint32_t total = st.total;
+  for (uint32_t j = threadIdx.x; j < total; j += NT) {
+    const int2 kv = st.kv[j];
+    const uint32_t pos = st.delta[bin_of(kv.x)] + j;
+    dkey[pos] = kv.x;
     if (FACT) {
       dprice[pos] = st.price[j];
-      dval[pos] = st.val[j];
+      dval[pos] = kv.y;
     } else if (with_val) {
-      dval[pos] = st.val[j];
+      dval[pos] = kv.y;
     }
   }
 }
 
+constexpr int kR1 = (int)(kTile1 / kSBlk);  // rows per thread at the first level
+using Rows1F = TileRows<true, true, kR1>;
+
+// One row of a first-level tile (q < s.n).
 template <bool FACT>
-__global__ __launch_bounds__(kBlk) void k_p1_scatter(PartSide s) {
-  __shared__ Stage<FACT> st;
-  const uint32_t nb1 = 1u << s.b1, shift = 32u - s.b1;
-  // partition starts: exclusive scan of the bin totals (nb1 <= kBlk)
-  uint32_t tot;
-  const uint32_t base = block_excl_scan<kBlk>(threadIdx.x < nb1 ? s.tot1[threadIdx.x] : 0u, st.scr, &tot);
-  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (threadIdx.x < nb1) st.gbase[threadIdx.x] = base + s.hist1[(size_t)threadIdx.x * gridDim.x + tile];
-  const int64_t r0 = tile * kTile1;
-  const int64_t r1 = r0 + kTile1 < s.n ? r0 + kTile1 : s.n;
-  constexpr int R = kRowsPerThread;
-  bool valid[R];
-  int32_t key[R], val[R];
-  int64_t price[R];
-  uint32_t bin[R];
-  // all loads first (strided by the workgroup, so every load is coalesced)
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    const int64_t q = r0 + threadIdx.x + (int64_t)k * kBlk;
-    const bool in = q < r1;
-    key[k] = in ? s.key[q] : 0;
-    if (FACT) {
-      valid[k] = in && s.day[q] < s.day_lt;
-      price[k] = in ? s.price[q] : 0;
-      val[k] = in ? s.qty[q] : 0;
-    } else {
-      valid[k] = in;
-      price[k] = 0;
-      val[k] = !in                          ? 0
-               : s.pkind == relh::PAY_ROW_ID ? (int32_t)q
-               : s.pkind == relh::PAY_I32    ? ((const int32_t*)s.payload)[q]
-               : s.pkind == relh::PAY_I8     ? (int32_t)((const int8_t*)s.payload)[q]
-                                             : 0;
-    }
-    bin[k] = phash(key[k]) >> shift;
+__device__ __forceinline__ void load_p1_row(const PartSide& s, int64_t q, int k, TileRows<FACT, FACT, kR1>& r) {
+  r.key[k] = s.key[q];
+  if (FACT) {
+    r.val[k] = s.qty[q];
+    r.price[k] = s.price[q];
+    r.day[k] = s.day[q];
+  } else {
+    r.val[k] = s.pkind == relh::PAY_ROW_ID ? (int32_t)q
+             : s.pkind == relh::PAY_I32    ? ((const int32_t*)s.payload)[q]
+             : s.pkind == relh::PAY_I8     ? (int32_t)((const int8_t*)s.payload)[q]
+                                           : 0;
   }
-  stage_and_write<FACT, R>(st, valid, key, price, val, bin, nb1, s.pkind != relh::PAY_NONE, s.key1, s.price1,
-                           FACT ? s.qty1 : s.pay1);
+}
+
+// One first-level tile per workgroup (tiles of one XCD contiguous, xcd_tile);
+// four workgroups per CU, so one's loads overlap another's sort and stores.
+template <bool FACT>
+__global__ __launch_bounds__(kSBlk) void k_p1_scatter(PartSide s) {
+  __shared__ Stage<FACT, (int)kTile1> st;
+  const uint32_t nb1 = 1u << s.b1;
+  const BinOf bin_of{32u - s.b1, nb1 - 1};
+  const int64_t ntiles = gridDim.x;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  TileRows<FACT, FACT, kR1> r;
+  const int64_t r0 = (int64_t)tile * kTile1 + threadIdx.x;
+  if ((int64_t)tile * kTile1 + kTile1 <= s.n) {  // full tile: unconditional loads, issued back to back
+#pragma unroll
+    for (int k = 0; k < kR1; ++k) load_p1_row<FACT>(s, r0 + (int64_t)k * kSBlk, k, r);
+    r.valid = (1u << kR1) - 1;
+  } else {
+    r.valid = 0;
+#pragma unroll
+    for (int k = 0; k < kR1; ++k) {
+      const int64_t q = r0 + (int64_t)k * kSBlk;
+      if (q < s.n) {
+        load_p1_row<FACT>(s, q, k, r);
+        r.valid |= 1u << k;
+      } else {
+        r.key[k] = 0;
+        r.val[k] = 0;
+        if (FACT) {
+          r.price[k] = 0;
+          r.day[k] = 0;
+        }
+      }
+    }
+  }
+  const uint32_t h = threadIdx.x < nb1 ? s.hist1[(size_t)threadIdx.x * ntiles + tile] : 0u;
+  // partition starts: exclusive scan of the bin totals (nb1 <= kSBlk)
+  uint32_t tot;
+  const uint32_t pbase = block_excl_scan<kSBlk>(threadIdx.x < nb1 ? s.tot1[threadIdx.x] : 0u, st.scr, &tot);
+  if (threadIdx.x < kMaxBins) st.lcnt[threadIdx.x] = 0;
+  if (threadIdx.x < nb1) st.gbase[threadIdx.x] = pbase + h;
+  __syncthreads();
+  stage_and_write<FACT, FACT, kSBlk, (int)kTile1>(st, r, s.day_lt, bin_of, nb1, s.pkind != relh::PAY_NONE, s.key1,
+                                                  s.price1, FACT ? s.qty1 : s.pay1);
 }
 
 // ---- second level ------------------------------------------------------------------------------------------------------
+//
+// Second-level tiles cut each first-level partition into kTile-row pieces;
+// tile ids run over the partitions in order. Every workgroup derives the tile
+// table from the first-level totals once, in LDS.
 
-// Locate this workgroup's second-level tile: first-level partition p, its
-// start, its row range. Returns false for the surplus workgroups of the
-// upper-bound grid. Needs nb1 <= kBlk.
-struct Tile2 {
-  uint32_t p;
-  uint32_t p_start;   // start of partition p in the first-level arrays
-  uint32_t tile_in_p; // index of this tile inside partition p
-  int64_t lo, hi;     // rows [lo, hi) of the first-level arrays
+struct L2Map {
+  uint32_t start[kMaxBins];  // first row of partition p in the first-level arrays
+  uint32_t cnt[kMaxBins];    // rows of partition p
+  uint32_t tbase[kMaxBins];  // first tile id of partition p
+  uint32_t ntiles;           // tiles over all partitions
 };
 
-__device__ bool locate_tile2(const PartSide& s, int64_t bid, Tile2* out) {
-  __shared__ uint32_t scr[kBlk / kWave];
-  __shared__ int s_found;
-  __shared__ Tile2 s_t;
+template <int NT>
+__device__ void build_l2map(const PartSide& s, L2Map& mp, uint32_t* scr) {
   const uint32_t nb1 = 1u << s.b1;
   const uint32_t c = threadIdx.x < nb1 ? s.tot1[threadIdx.x] : 0u;
-  const uint32_t ntile = (uint32_t)((c + kTile2 - 1) / kTile2);
-  uint32_t tot;
-  const uint32_t start = block_excl_scan<kBlk>(c, scr, &tot);
-  uint32_t tbase_tot;
-  const uint32_t tbase = block_excl_scan<kBlk>(ntile, scr, &tbase_tot);
-  if (threadIdx.x == 0) s_found = 0;
-  __syncthreads();
-  if (threadIdx.x < nb1 && bid >= tbase && bid < (int64_t)tbase + ntile) {
-    Tile2 t;
-    t.p = threadIdx.x;
-    t.p_start = start;
-    t.tile_in_p = (uint32_t)(bid - tbase);
-    t.lo = (int64_t)start + (int64_t)t.tile_in_p * kTile2;
-    const int64_t end = (int64_t)start + c;
-    t.hi = t.lo + kTile2 < end ? t.lo + kTile2 : end;
-    s_t = t;
-    s_found = 1;
+  const uint32_t nt = (uint32_t)((c + kTile - 1) / kTile);
+  uint32_t tot, ntot;
+  const uint32_t start = block_excl_scan<NT>(c, scr, &tot);
+  const uint32_t tb = block_excl_scan<NT>(nt, scr, &ntot);
+  if (threadIdx.x < nb1) {
+    mp.start[threadIdx.x] = start;
+    mp.cnt[threadIdx.x] = c;
+    mp.tbase[threadIdx.x] = tb;
   }
+  if (threadIdx.x == 0) mp.ntiles = ntot;
   __syncthreads();
-  *out = s_t;
-  return s_found != 0;
 }
 
-__global__ __launch_bounds__(kBlk) void k_p2_hist(PartSide s) {
-  __shared__ uint32_t h[kMaxBins];
-  Tile2 t;
-  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (!locate_tile2(s, tile, &t)) return;
-  const uint32_t nb2 = 1u << s.b2, shift = 32u - s.b1 - s.b2, mask = nb2 - 1;
-  for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) h[b] = 0;
-  __syncthreads();
-  constexpr int R = (int)(kTile2 / kBlk);
-  int32_t keys[R];
-#pragma unroll
-  for (int k = 0; k < R; ++k) {  // all loads first
-    const int64_t q = t.lo + threadIdx.x + (int64_t)k * kBlk;
-    keys[k] = q < t.hi ? s.key1[q] : 0;
+struct Tile2 {
+  uint32_t p;
+  int64_t lo, hi;  // rows [lo, hi) of the first-level arrays
+};
+
+// The partition holding tile t: the last p with tbase[p] <= t (partitions
+// without tiles share their successor's tbase, so the last one is never empty).
+__device__ __forceinline__ Tile2 find_tile(const L2Map& mp, uint32_t nb1, int64_t t) {
+  uint32_t lo = 0, hi = nb1 - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) / 2;
+    if ((int64_t)mp.tbase[mid] <= t) lo = mid;
+    else hi = mid - 1;
   }
+  Tile2 r;
+  r.p = lo;
+  r.lo = (int64_t)mp.start[lo] + (t - (int64_t)mp.tbase[lo]) * kTile;
+  const int64_t end = (int64_t)mp.start[lo] + mp.cnt[lo];
+  r.hi = r.lo + kTile < end ? r.lo + kTile : end;
+  return r;
+}
+
+// Per second-level tile: histogram of the next b2 hash bits. Persistent.
+constexpr int kHR = (int)(kTile / kBlk);
+__global__ __launch_bounds__(kBlk) void k_p2_hist(PartSide s) {
+  __shared__ L2Map mp;
+  __shared__ uint32_t scr[kBlk / kWave];
+  __shared__ uint32_t h[kMaxBins];
+  build_l2map<kBlk>(s, mp, scr);
+  const uint32_t nb1 = 1u << s.b1, nb2 = 1u << s.b2;
+  const BinOf bin_of{32u - s.b1 - s.b2, nb2 - 1};
+  TileWalk w(mp.ntiles);
+  int64_t t = w.take();
+  int32_t cur[kHR], nxt[kHR];
+  Tile2 tc{}, tn2{};
+  auto load = [&](const Tile2& x, int32_t(&keys)[kHR]) {
 #pragma unroll
-  for (int k = 0; k < R; ++k)
-    if (t.lo + threadIdx.x + (int64_t)k * kBlk < t.hi) atomicAdd(&h[(phash(keys[k]) >> shift) & mask], 1u);
-  __syncthreads();
-  for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) s.hist2[(size_t)tile * nb2 + b] = h[b];
+    for (int k = 0; k < kHR; ++k) {
+      const int64_t q = x.lo + threadIdx.x + (int64_t)k * kBlk;
+      keys[k] = q < x.hi ? s.key1[q] : 0;
+    }
+  };
+  if (t >= 0) {
+    tc = find_tile(mp, nb1, t);
+    load(tc, cur);
+  }
+  while (t >= 0) {
+    const int64_t tn = w.take();
+    if (tn >= 0) {
+      tn2 = find_tile(mp, nb1, tn);
+      load(tn2, nxt);
+    }
+    for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) h[b] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kHR; ++k)
+      if (tc.lo + threadIdx.x + (int64_t)k * kBlk < tc.hi) atomicAdd(&h[bin_of(cur[k])], 1u);
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) s.hist2[(size_t)t * nb2 + b] = h[b];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kHR; ++k) cur[k] = nxt[k];
+    tc = tn2;
+    t = tn;
+  }
 }
 
 // One workgroup per first-level partition p: per second-level bin, prefix over
 // p's tiles (in place) and the final partition starts/counts.
+constexpr int kScanBatch = 8;
 __global__ __launch_bounds__(kBlk) void k_p2_scan(PartSide s) {
+  __shared__ L2Map mp;
   __shared__ uint32_t scr[kBlk / kWave];
-  const uint32_t nb1 = 1u << s.b1, nb2 = 1u << s.b2;
+  build_l2map<kBlk>(s, mp, scr);
+  const uint32_t nb2 = 1u << s.b2;
   const uint32_t p = blockIdx.x;
-  const uint32_t c = threadIdx.x < nb1 ? s.tot1[threadIdx.x] : 0u;
-  const uint32_t ntile = (uint32_t)((c + kTile2 - 1) / kTile2);
-  uint32_t tot;
-  const uint32_t start = block_excl_scan<kBlk>(c, scr, &tot);
-  const uint32_t tbase = block_excl_scan<kBlk>(ntile, scr, &tot);
-  __shared__ uint32_t s_start, s_tbase, s_ntile;
-  if (threadIdx.x == p) {
-    s_start = start;
-    s_tbase = tbase;
-    s_ntile = ntile;
-  }
-  __syncthreads();
+  const uint32_t tb = mp.tbase[p], nt = (uint32_t)((mp.cnt[p] + kTile - 1) / kTile);
   uint32_t bin_tot = 0;
   if (threadIdx.x < nb2) {
-    for (uint32_t k = 0; k < s_ntile; ++k) {
-      uint32_t* cell = &s.hist2[(size_t)(s_tbase + k) * nb2 + threadIdx.x];
-      const uint32_t v = *cell;
-      *cell = bin_tot;
-      bin_tot += v;
+    for (uint32_t k0 = 0; k0 < nt; k0 += kScanBatch) {
+      uint32_t v[kScanBatch];
+#pragma unroll
+      for (int k = 0; k < kScanBatch; ++k)
+        v[k] = k0 + k < nt ? s.hist2[(size_t)(tb + k0 + k) * nb2 + threadIdx.x] : 0u;
+#pragma unroll
+      for (int k = 0; k < kScanBatch; ++k) {
+        if (k0 + k < nt) s.hist2[(size_t)(tb + k0 + k) * nb2 + threadIdx.x] = bin_tot;
+        bin_tot += v[k];
+      }
     }
   }
+  uint32_t tot;
   const uint32_t ex = block_excl_scan<kBlk>(threadIdx.x < nb2 ? bin_tot : 0u, scr, &tot);
   if (threadIdx.x < nb2) {
-    s.pstart[p * nb2 + threadIdx.x] = s_start + ex;
+    s.pstart[p * nb2 + threadIdx.x] = mp.start[p] + ex;
     s.pcount[p * nb2 + threadIdx.x] = bin_tot;
   }
 }
 
+constexpr int kR2 = (int)(kTile / kSBlk);  // rows per thread at the second level
+
 template <bool FACT>
-__global__ __launch_bounds__(kBlk) void k_p2_scatter(PartSide s) {
-  __shared__ Stage<FACT> st;
-  Tile2 t;
-  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (!locate_tile2(s, tile, &t)) return;
-  const uint32_t nb2 = 1u << s.b2, shift = 32u - s.b1 - s.b2, mask = nb2 - 1;
-  for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) st.gbase[b] = s.pstart[t.p * nb2 + b] + s.hist2[(size_t)tile * nb2 + b];
-  const bool pay = !FACT && s.pkind != relh::PAY_NONE;
-  constexpr int R = kRowsPerThread;
-  bool valid[R];
-  int32_t key[R], val[R];
-  int64_t price[R];
-  uint32_t bin[R];
+__device__ __forceinline__ void load_p2(const PartSide& s, const Tile2& x, bool pay, TileRows<FACT, false, kR2>& r) {
+  const int64_t r0 = x.lo + threadIdx.x;
+  if (x.lo + kTile <= x.hi) {  // full tile: unconditional loads, issued back to back
 #pragma unroll
-  for (int k = 0; k < R; ++k) {
-    const int64_t q = t.lo + threadIdx.x + (int64_t)k * kBlk;
-    valid[k] = q < t.hi;
-    key[k] = valid[k] ? s.key1[q] : 0;
-    price[k] = (FACT && valid[k]) ? s.price1[q] : 0;
-    val[k] = !valid[k] ? 0 : FACT ? s.qty1[q] : pay ? s.pay1[q] : 0;
-    bin[k] = (phash(key[k]) >> shift) & mask;
+    for (int k = 0; k < kR2; ++k) {
+      const int64_t q = r0 + (int64_t)k * kSBlk;
+      r.key[k] = s.key1[q];
+      if (FACT) r.price[k] = s.price1[q];
+      r.val[k] = FACT ? s.qty1[q] : pay ? s.pay1[q] : 0;
+    }
+    r.valid = (1u << kR2) - 1;
+  } else {
+    r.valid = 0;
+#pragma unroll
+    for (int k = 0; k < kR2; ++k) {
+      const int64_t q = r0 + (int64_t)k * kSBlk;
+      const bool in = q < x.hi;
+      r.key[k] = in ? s.key1[q] : 0;
+      if (FACT) r.price[k] = in ? s.price1[q] : 0;
+      r.val[k] = !in ? 0 : FACT ? s.qty1[q] : pay ? s.pay1[q] : 0;
+      r.valid |= (uint32_t)in << k;
+    }
   }
-  stage_and_write<FACT, R>(st, valid, key, price, val, bin, nb2, pay, s.key2, s.price2, FACT ? s.qty2 : s.pay2);
+}
+
+// Persistent over the second-level tiles; two workgroups per CU (LDS).
+template <bool FACT>
+__global__ __launch_bounds__(kSBlk, 4) void k_p2_scatter(PartSide s) {
+  __shared__ Stage<FACT, (int)kTile> st;
+  __shared__ L2Map mp;
+  for (uint32_t b = threadIdx.x; b < kMaxBins; b += kSBlk) st.lcnt[b] = 0;
+  build_l2map<kSBlk>(s, mp, st.scr);  // ends with a barrier
+  const uint32_t nb1 = 1u << s.b1, nb2 = 1u << s.b2;
+  const BinOf bin_of{32u - s.b1 - s.b2, nb2 - 1};
+  const bool pay = !FACT && s.pkind != relh::PAY_NONE;
+  TileWalk w(mp.ntiles);
+  int64_t t = w.take();
+  TileRows<FACT, false, kR2> cur, nxt;
+  uint32_t gcur = 0, gnxt = 0;  // thread b < nb2: the tile's start in bin b
+  auto gstart = [&](const Tile2& x, int64_t tile) {
+    return threadIdx.x < nb2 ? s.pstart[x.p * nb2 + threadIdx.x] + s.hist2[(size_t)tile * nb2 + threadIdx.x] : 0u;
+  };
+  if (t >= 0) {
+    const Tile2 x = find_tile(mp, nb1, t);
+    load_p2<FACT>(s, x, pay, cur);
+    gcur = gstart(x, t);
+  }
+  while (t >= 0) {
+    if (threadIdx.x < nb2) st.gbase[threadIdx.x] = gcur;
+    const int64_t tn = w.take();
+    if (tn >= 0) {
+      const Tile2 x = find_tile(mp, nb1, tn);
+      load_p2<FACT>(s, x, pay, nxt);
+      gnxt = gstart(x, tn);
+    }
+    stage_and_write<FACT, false, kSBlk, (int)kTile>(st, cur, 0, bin_of, nb2, pay, s.key2, s.price2,
+                                                    FACT ? s.qty2 : s.pay2);
+    cur = nxt;
+    gcur = gnxt;
+    t = tn;
+  }
 }
 
 // ---- work units -----------------------------------------------------------------------------------------------------------
@@ -764,12 +954,15 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
 rel_status partition_side(rel_ctx* ctx, PartSide& s, bool fact, int64_t* passed) {
   const uint32_t nb1 = 1u << s.b1;
   const int64_t ntiles1 = (s.n + kTile1 - 1) / kTile1;
-  const dim3 g1((unsigned)ntiles1), blk(kBlk);
+  const dim3 blk(kBlk), sblk(kSBlk);
+  // persistent grids, multiples of 8 (one share per XCD)
+  const unsigned gs = (unsigned)(ctx->num_cus * 2 / 8 * 8 > 8 ? ctx->num_cus * 2 / 8 * 8 : 8);
+  const unsigned gh = gs * 2;
   if (s.n > 0) {
     {
       relh::KernelTimer kt(ctx, fact ? "fact_p1_hist" : "dim_p1_hist");
-      if (fact) hipLaunchKernelGGL(k_p1_hist<true>, g1, blk, 0, ctx->stream, s);
-      else hipLaunchKernelGGL(k_p1_hist<false>, g1, blk, 0, ctx->stream, s);
+      if (fact) hipLaunchKernelGGL(k_p1_hist<true>, dim3((unsigned)ntiles1), blk, 0, ctx->stream, s);
+      else hipLaunchKernelGGL(k_p1_hist<false>, dim3((unsigned)ntiles1), blk, 0, ctx->stream, s);
     }
     {
       relh::KernelTimer kt(ctx, fact ? "fact_p1_colscan" : "dim_p1_colscan");
@@ -777,18 +970,16 @@ rel_status partition_side(rel_ctx* ctx, PartSide& s, bool fact, int64_t* passed)
     }
     {
       relh::KernelTimer kt(ctx, fact ? "fact_p1_scatter" : "dim_p1_scatter");
-      if (fact) hipLaunchKernelGGL(k_p1_scatter<true>, g1, blk, 0, ctx->stream, s);
-      else hipLaunchKernelGGL(k_p1_scatter<false>, g1, blk, 0, ctx->stream, s);
+      if (fact) hipLaunchKernelGGL(k_p1_scatter<true>, dim3((unsigned)ntiles1), sblk, 0, ctx->stream, s);
+      else hipLaunchKernelGGL(k_p1_scatter<false>, dim3((unsigned)ntiles1), sblk, 0, ctx->stream, s);
     }
   } else {
     TRY(relh::fill_u32(ctx, s.tot1, nb1, 0));
   }
   REL_LAUNCH_CHECK(ctx, "partition level 1");
-  // upper bound of second-level tiles: sum over partitions of ceil(c_p / kTile2)
-  const dim3 g2((unsigned)(s.n / kTile2 + nb1));
   {
     relh::KernelTimer kt(ctx, fact ? "fact_p2_hist" : "dim_p2_hist");
-    hipLaunchKernelGGL(k_p2_hist, g2, blk, 0, ctx->stream, s);
+    hipLaunchKernelGGL(k_p2_hist, dim3(gh), blk, 0, ctx->stream, s);
   }
   {
     relh::KernelTimer kt(ctx, fact ? "fact_p2_scan" : "dim_p2_scan");
@@ -796,8 +987,8 @@ rel_status partition_side(rel_ctx* ctx, PartSide& s, bool fact, int64_t* passed)
   }
   {
     relh::KernelTimer kt(ctx, fact ? "fact_p2_scatter" : "dim_p2_scatter");
-    if (fact) hipLaunchKernelGGL(k_p2_scatter<true>, g2, blk, 0, ctx->stream, s);
-    else hipLaunchKernelGGL(k_p2_scatter<false>, g2, blk, 0, ctx->stream, s);
+    if (fact) hipLaunchKernelGGL(k_p2_scatter<true>, dim3(gs), sblk, 0, ctx->stream, s);
+    else hipLaunchKernelGGL(k_p2_scatter<false>, dim3(gs), sblk, 0, ctx->stream, s);
   }
   REL_LAUNCH_CHECK(ctx, "partition level 2");
   return REL_OK;
@@ -839,7 +1030,8 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   split_bits(m, &b1, &b2);
   const uint32_t nb1 = 1u << b1, nb2 = 1u << b2, nparts = nb1 * nb2;
   const int64_t fnt1 = (n + kTile1 - 1) / kTile1, dnt1 = (m + kTile1 - 1) / kTile1;
-  const int64_t fnt2 = n / kTile2 + nb1, dnt2 = m / kTile2 + nb1;
+  // second-level tiles: sum over partitions of ceil(c_p / kTile) <= rows / kTile + partitions
+  const int64_t fnt2 = n / kTile + nb1, dnt2 = m / kTile + nb1;
   // whole chunks, plus the sub-units of split chunks (each split chunk adds at most one partial sub-unit)
   const int64_t max_units = (int64_t)nparts + m / kJChunk + 1 + n / kSubRows + kMaxSplit;
 
