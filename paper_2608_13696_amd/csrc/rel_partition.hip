@@ -106,24 +106,32 @@ __global__ __launch_bounds__(kBlk) void k_p1_hist(PartSide s) {
   __shared__ uint32_t h[kMaxBins];
   const uint32_t nb1 = 1u << s.b1, shift = 32u - s.b1;
   for (uint32_t b = threadIdx.x; b < nb1; b += kBlk) h[b] = 0;
-  __syncthreads();
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t r0 = tile * kTile1;
   const int64_t r1 = r0 + kTile1 < s.n ? r0 + kTile1 : s.n;
-  for (int64_t r = r0 + 4 * threadIdx.x; r < r1; r += 4 * kBlk) {
-    if (r + 4 <= r1) {
-      const int4 kv = *reinterpret_cast<const int4*>(s.key + r);
-      int4 dv = make_int4(0, 0, 0, 0);
-      if (FACT) dv = *reinterpret_cast<const int4*>(s.day + r);
-      const int32_t ks[4] = {kv.x, kv.y, kv.z, kv.w};
-      const int32_t ds[4] = {dv.x, dv.y, dv.z, dv.w};
+  constexpr int V = (int)(kTile1 / (4 * kBlk));  // 16-byte loads per column per thread
+  if (r1 - r0 == kTile1) {
+    // full tile: every load first, then the counting
+    int4 kv[V], dv[V];
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (!FACT || ds[k] < s.day_lt) atomicAdd(&h[phash(ks[k]) >> shift], 1u);
-    } else {
-      for (int64_t q = r; q < r1; ++q)
-        if (row_passes<FACT>(s, q)) atomicAdd(&h[phash(s.key[q]) >> shift], 1u);
+    for (int k = 0; k < V; ++k) {
+      const int64_t r = r0 + 4 * (threadIdx.x + (int64_t)k * kBlk);
+      kv[k] = *reinterpret_cast<const int4*>(s.key + r);
+      dv[k] = FACT ? *reinterpret_cast<const int4*>(s.day + r) : make_int4(0, 0, 0, 0);
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const int32_t ks[4] = {kv[k].x, kv[k].y, kv[k].z, kv[k].w};
+      const int32_t ds[4] = {dv[k].x, dv[k].y, dv[k].z, dv[k].w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (!FACT || ds[e] < s.day_lt) atomicAdd(&h[phash(ks[e]) >> shift], 1u);
+    }
+  } else {
+    __syncthreads();
+    for (int64_t q = r0 + threadIdx.x; q < r1; q += kBlk)
+      if (row_passes<FACT>(s, q)) atomicAdd(&h[phash(s.key[q]) >> shift], 1u);
   }
   __syncthreads();
   // bin-major [nb1][ntiles], so that each bin's column scan reads contiguously
@@ -572,76 +580,141 @@ struct SplitAcc {
 
 __device__ __forceinline__ uint32_t size_class(uint32_t rows) { return 32 - __clz(rows); }
 
-// One workgroup of 1024 threads. desc[u] = {dlo, dhi, flo, fhi}; split[u] =
-// {split id + 1 (0: not split), sub-units of the chunk}. sbase: nparts words.
-__global__ __launch_bounds__(1024) void k_make_units(const uint32_t* __restrict__ dstart, const uint32_t* __restrict__ dcount,
-                                                     const uint32_t* __restrict__ fstart, const uint32_t* __restrict__ fcount,
-                                                     uint32_t nparts, uint4* __restrict__ desc, uint2* __restrict__ split,
-                                                     uint32_t* __restrict__ sbase, int64_t* __restrict__ n_units) {
-  __shared__ uint32_t cls_n[33];
-  __shared__ uint32_t cls_cur[33];
-  __shared__ unsigned long long s_rows;
-  __shared__ uint32_t s_nsplit;
-  for (int c = threadIdx.x; c < 33; c += blockDim.x) cls_n[c] = 0;
-  if (threadIdx.x == 0) {
-    s_rows = 0;
-    s_nsplit = 0;
+// Adds v to ctr[key] for every active lane with one LDS atomic per distinct
+// key in the wave, and returns each lane's exclusive position in what its key
+// received (the old value plus the v of lower lanes with the same key). Every
+// lane of the wave must call it.
+__device__ __forceinline__ uint32_t wave_grouped_add(uint32_t* ctr, uint32_t key, uint32_t v, bool active) {
+  const uint32_t lane = lane_id();
+  uint32_t result = 0;
+  uint64_t todo = wave_ballot(active);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const uint32_t k = __shfl(key, leader, kWave);
+    const bool mine = active && key == k;
+    const uint32_t x = mine ? v : 0u;
+    uint32_t incl = x;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t t = __shfl_up(incl, o, kWave);
+      if (lane >= (uint32_t)o) incl += t;
+    }
+    const uint32_t total = __shfl(incl, kWave - 1, kWave);
+    uint32_t base = 0;
+    if ((int)lane == leader) base = atomicAdd(&ctr[k], total);
+    base = __shfl(base, leader, kWave);
+    if (mine) result = base + incl - x;
+    todo &= ~wave_ballot(mine);
   }
+  return result;
+}
+
+// Unit lists in two kernels of one thread per partition. k_unit_count:
+// decides the splits and counts units per size class in each workgroup.
+// k_unit_emit: every workgroup derives its own start in each class from
+// those counts (classes in descending order, workgroups in order) and writes
+// its units. desc[u] = {dlo, dhi, flo, fhi}; split[u] = {split id + 1 (0: not
+// split), sub-units of the chunk}.
+constexpr int kUBlk = 256;
+constexpr int kClasses = 33;
+constexpr int kMaxUnitWgs = (1 << 16) / kUBlk;  // partitions never exceed 2^16
+
+struct UnitArgs {
+  const uint32_t* dstart;
+  const uint32_t* dcount;
+  const uint32_t* fstart;
+  const uint32_t* fcount;
+  uint32_t nparts;
+  const int64_t* rows_passed;  // fact rows that passed the predicate (all partitions)
+  uint32_t* split_ctr;         // split ids handed out; zero between calls
+  uint32_t* sbase;             // [nparts] split id or kNoSplit
+  uint32_t* wg_cls;            // [workgroups][kClasses]
+  uint4* desc;
+  uint2* split;
+  int64_t* n_units;
+};
+
+__global__ __launch_bounds__(kUBlk) void k_unit_count(UnitArgs a) {
+  __shared__ uint32_t cls_n[kClasses];
+  if (threadIdx.x < kClasses) cls_n[threadIdx.x] = 0;
   __syncthreads();
-  unsigned long long rows = 0;
-  for (uint32_t p = threadIdx.x; p < nparts; p += blockDim.x) rows += dcount[p] ? fcount[p] : 0u;
-  atomicAdd(&s_rows, rows);
-  __syncthreads();
-  const uint64_t mean4 = 4 * s_rows / (nparts ? nparts : 1);
+  const uint32_t p = blockIdx.x * kUBlk + threadIdx.x;
+  const uint32_t fc = p < a.nparts ? a.fcount[p] : 0u, dc = p < a.nparts ? a.dcount[p] : 0u;
+  const uint64_t mean4 = 4 * (uint64_t)*a.rows_passed / a.nparts;
   const uint32_t thr = mean4 > kSplitMin ? (uint32_t)(mean4 < 0xffffffffull ? mean4 : 0xffffffffull) : kSplitMin;
-  for (uint32_t p = threadIdx.x; p < nparts; p += blockDim.x) {
-    const uint32_t fc = fcount[p], dc = dcount[p];
-    uint32_t sb = kNoSplit;
-    if (fc != 0 && dc != 0) {
-      const uint32_t chunks = (dc + kJChunk - 1) / kJChunk;
-      uint32_t nsub = 1;
-      if (chunks == 1 && fc > thr) {
-        const uint32_t id = atomicAdd(&s_nsplit, 1u);
-        if (id < kMaxSplit) {
-          sb = id;
-          nsub = (fc + kSubRows - 1) / kSubRows;
-        }
-      }
-      atomicAdd(&cls_n[size_class(nsub > 1 ? kSubRows : fc)], chunks * nsub);
-    }
-    sbase[p] = sb;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (int c = 32; c >= 0; --c) {  // descending size class
-      cls_cur[c] = acc;
-      acc += cls_n[c];
-    }
-    *n_units = acc;
-  }
-  __syncthreads();
-  for (uint32_t p = threadIdx.x; p < nparts; p += blockDim.x) {
-    const uint32_t fc = fcount[p], dc = dcount[p];
-    if (fc == 0 || dc == 0) continue;
-    const uint32_t ds = dstart[p], fs = fstart[p], sb = sbase[p];
+  const bool live = fc != 0 && dc != 0;
+  uint32_t sb = kNoSplit, units = 0, cls = 0;
+  if (live) {
     const uint32_t chunks = (dc + kJChunk - 1) / kJChunk;
-    if (sb != kNoSplit) {
-      const uint32_t nsub = (fc + kSubRows - 1) / kSubRows;
-      uint32_t pos = atomicAdd(&cls_cur[size_class(kSubRows)], nsub);
-      for (uint32_t k = 0; k < nsub; ++k, ++pos) {
-        const uint32_t flo = fs + k * kSubRows;
-        const uint32_t fhi = flo + kSubRows < fs + fc ? flo + kSubRows : fs + fc;
-        desc[pos] = make_uint4(ds, ds + dc, flo, fhi);
-        split[pos] = make_uint2(sb + 1, nsub);
+    uint32_t nsub = 1;
+    if (chunks == 1 && fc > thr) {
+      const uint32_t id = dev_add_ret<uint32_t>(a.split_ctr, 1u);
+      if (id < kMaxSplit) {
+        sb = id;
+        nsub = (fc + kSubRows - 1) / kSubRows;
       }
-    } else {
-      uint32_t pos = atomicAdd(&cls_cur[size_class(fc)], chunks);
-      for (uint32_t c = 0; c < chunks; ++c, ++pos) {
-        const uint32_t dlo = ds + c * kJChunk;
-        desc[pos] = make_uint4(dlo, dlo + kJChunk < ds + dc ? dlo + kJChunk : ds + dc, fs, fs + fc);
-        split[pos] = make_uint2(0, 1);
-      }
+    }
+    units = chunks * nsub;
+    cls = size_class(nsub > 1 ? kSubRows : fc);
+  }
+  wave_grouped_add(cls_n, cls, units, live);
+  if (p < a.nparts) a.sbase[p] = sb;
+  __syncthreads();
+  if (threadIdx.x < kClasses) a.wg_cls[blockIdx.x * kClasses + threadIdx.x] = cls_n[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kUBlk) void k_unit_emit(UnitArgs a) {
+  __shared__ uint32_t tab[kMaxUnitWgs * kClasses];
+  __shared__ uint32_t tot[kClasses];
+  __shared__ uint32_t bef[kClasses];
+  __shared__ uint32_t cur[kClasses];
+  const uint32_t nwg = gridDim.x;
+  for (uint32_t i = threadIdx.x; i < nwg * kClasses; i += kUBlk) tab[i] = a.wg_cls[i];  // coalesced, all in flight
+  __syncthreads();
+  if (threadIdx.x < kClasses) {
+    uint32_t before = 0, total = 0;
+    for (uint32_t w = 0; w < nwg; ++w) {
+      const uint32_t v = tab[w * kClasses + threadIdx.x];
+      before += w < blockIdx.x ? v : 0u;
+      total += v;
+    }
+    tot[threadIdx.x] = total;
+    bef[threadIdx.x] = before;
+  }
+  __syncthreads();
+  if (threadIdx.x < kClasses) {
+    uint32_t start = 0;  // classes in descending order: class c follows every larger class
+    for (int c = kClasses - 1; c > (int)threadIdx.x; --c) start += tot[c];
+    cur[threadIdx.x] = start + bef[threadIdx.x];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      *a.n_units = (int64_t)start + tot[0];
+      *a.split_ctr = 0;  // k_unit_count has finished with it: clear it for the next call
+    }
+  }
+  __syncthreads();
+  const uint32_t p = blockIdx.x * kUBlk + threadIdx.x;
+  const bool in = p < a.nparts;
+  const uint32_t fc = in ? a.fcount[p] : 0u, dc = in ? a.dcount[p] : 0u;
+  const uint32_t ds = in ? a.dstart[p] : 0u, fs = in ? a.fstart[p] : 0u, sb = in ? a.sbase[p] : kNoSplit;
+  const bool live = fc != 0 && dc != 0;
+  const bool splitp = sb != kNoSplit;
+  const uint32_t chunks = (dc + kJChunk - 1) / kJChunk;
+  const uint32_t nsub = splitp ? (fc + kSubRows - 1) / kSubRows : 1u;
+  const uint32_t cls = size_class(splitp ? kSubRows : fc);
+  uint32_t pos = wave_grouped_add(cur, cls, live ? chunks * nsub : 0u, live);
+  if (!live) return;
+  if (splitp) {
+    for (uint32_t j = 0; j < nsub; ++j, ++pos) {
+      const uint32_t flo = fs + j * kSubRows;
+      const uint32_t fhi = flo + kSubRows < fs + fc ? flo + kSubRows : fs + fc;
+      a.desc[pos] = make_uint4(ds, ds + dc, flo, fhi);
+      a.split[pos] = make_uint2(sb + 1, nsub);
+    }
+  } else {
+    for (uint32_t c = 0; c < chunks; ++c, ++pos) {
+      const uint32_t dlo = ds + c * kJChunk;
+      a.desc[pos] = make_uint4(dlo, dlo + kJChunk < ds + dc ? dlo + kJChunk : ds + dc, fs, fs + fc);
+      a.split[pos] = make_uint2(0, 1);
     }
   }
 }
@@ -710,6 +783,33 @@ __device__ __forceinline__ void load_dkeys(const JoinArgs& a, uint32_t dlo, uint
   }
 }
 
+// The next unit's dim keys and first fact rows, with indices clamped into the
+// unit's (never empty) ranges: the loads carry no branch, so their number is
+// fixed and a later wait for an earlier atomic does not have to wait for them.
+// Lanes past the ranges hold copies that the build and probe skip.
+__device__ __forceinline__ void prefetch_unit(const JoinArgs& a, uint4 u, int32_t (&dk)[kJDK], RowRegs& r) {
+#pragma unroll
+  for (int k = 0; k < kJDK; ++k) {
+    const uint32_t j = u.x + threadIdx.x + k * kJBlock;
+    dk[k] = a.dkey[j < u.y ? j : u.y - 1];
+  }
+#pragma unroll
+  for (int k = 0; k < kJR; ++k) {
+    uint32_t i = u.z + threadIdx.x + k * kJBlock;
+    i = i < u.w ? i : u.w - 1;
+    r.key[k] = a.fkey[i];
+    r.sp[k] = (uint64_t)a.fprice[i];
+    r.qty[k] = a.fqty[i];
+  }
+}
+
+// Output room for `total` groups. Like take_ticket, the address is not provably
+// uniform, so the wave waits for the result only where it is used.
+__device__ __forceinline__ int64_t reserve_nowait(const JoinArgs& a, uint32_t total) {
+  unsigned long long* p = (unsigned long long*)a.d_n + threadIdx.x * a.zero;
+  return (int64_t)__hip_atomic_fetch_add(p, (unsigned long long)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Reserve room for `mine` groups of this thread (block-wide scan, one atomic
 // per call) and return this thread's first output row.
 __device__ __forceinline__ int64_t reserve_out(const JoinArgs& a, uint32_t mine, uint32_t* scr, uint64_t* s_excl) {
@@ -740,21 +840,26 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
   __shared__ uint64_t tsq[kJSlots];
   __shared__ uint16_t tpos[kJSlots];  // the key's position in its chunk (split units)
   __shared__ uint32_t scr[kJBlock / kWave];
+  __shared__ uint32_t s_wk[kJPer][kJBlock / kWave];  // occupied slots per (slot round, wave)
   __shared__ uint64_t s_excl;
   __shared__ uint4 s_desc;
   __shared__ uint2 s_split;
   __shared__ int64_t s_u;
   __shared__ uint32_t s_last;
   const int64_t n_units = *a.n_units;
-  const uint32_t tid = threadIdx.x, lane = lane_id();
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   uint64_t matched = 0;
   // Units come from the largest-first list by ticket (dynamic, so a workgroup
-  // held up by a long unit takes fewer). While a unit probes, thread 0 already
-  // holds the next ticket and reads the next unit's descriptor; after the
-  // probe every thread issues the next unit's dim-key and first fact-row loads,
-  // which then travel during this unit's emission.
+  // held up by a long unit takes fewer). Thread 0 runs two units ahead: at the
+  // start of a unit it asks for the ticket after next and reads the next
+  // unit's descriptor (its ticket arrived during the previous unit), so
+  // neither round trip delays the unit. After the probe every thread issues
+  // the next unit's dim-key and first fact-row loads, which travel during this
+  // unit's emission.
+  int64_t t_ahead = 0;  // thread 0: ticket of the next unit
   if (tid == 0) {
     const int64_t t = take_ticket(a);
+    t_ahead = take_ticket(a);
     s_u = t;
     if (t < n_units) {
       s_desc = a.unit_desc[t];
@@ -773,8 +878,16 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
   }
   while (u < n_units) {
     const uint32_t dlo = d.x, dhi = d.y, flo = d.z, fhi = d.w;
-    int64_t tn = 0;
-    if (tid == 0) tn = take_ticket(a);
+    int64_t t_req = 0;
+    uint4 nd = make_uint4(0, 0, 0, 0);
+    uint2 ns = make_uint2(0, 0);
+    if (tid == 0) {
+      t_req = take_ticket(a);
+      if (t_ahead < n_units) {
+        nd = a.unit_desc[t_ahead];
+        ns = a.unit_split[t_ahead];
+      }
+    }
     for (int s = tid; s < kJSlots; s += kJBlock) {
       tkey[s] = kLdsEmpty;
       tcnt[s] = 0;
@@ -804,12 +917,6 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
       }
     }
     __syncthreads();
-    uint4 nd = make_uint4(0, 0, 0, 0);
-    uint2 ns = make_uint2(0, 0);
-    if (tid == 0 && tn < n_units) {
-      nd = a.unit_desc[tn];
-      ns = a.unit_split[tn];
-    }
     // probe and aggregate in LDS; long units stream further steps through nxt
     const uint32_t nrows = fhi - flo;
     const uint32_t iters = (nrows + kJR * kJBlock - 1) / (kJR * kJBlock);  // uniform over the workgroup
@@ -817,24 +924,33 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
       const uint32_t i0 = flo + it * (kJR * kJBlock) + tid;
       if (it > 0) cur = nxt;
       if (it + 1 < iters) load_rows(a, i0 + kJR * kJBlock, fhi, nxt);
+      // find every row's slot first, then update: the LDS reads of the finds
+      // are not queued behind the previous row's atomics
+      bool fnd[kJR];
+      int slt[kJR];
 #pragma unroll
       for (int k = 0; k < kJR; ++k) {
-        bool found = false;
-        int slot = 0;
+        fnd[k] = false;
+        slt[k] = 0;
         if (i0 + k * kJBlock < fhi) {
           const uint64_t want = (uint64_t)(uint32_t)cur.key[k] | (1ull << 32);
           uint32_t h = slot_hash(cur.key[k]);
           for (int step = 0; step < kJSlots; ++step) {
             const uint64_t c = tkey[h];
             if (c == want) {
-              found = true;
-              slot = (int)h;
+              fnd[k] = true;
+              slt[k] = (int)h;
               break;
             }
             if (c == kLdsEmpty) break;
             h = (h + 1) & (kJSlots - 1);
           }
         }
+      }
+#pragma unroll
+      for (int k = 0; k < kJR; ++k) {
+        bool found = fnd[k];
+        const int slot = slt[k];
         matched += found;
         // Hot keys: when many lanes of the wave hit one slot, pre-sum them so the
         // LDS sees one update instead of a serialised run of same-address atomics.
@@ -862,36 +978,59 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
       }
     }
     if (tid == 0) {
-      s_u = tn;
+      s_u = t_ahead;
       s_desc = nd;
       s_split = ns;
+      t_ahead = t_req;
     }
     __syncthreads();
     const int64_t un = s_u;
     const uint4 dn = s_desc;
     const uint2 sn = s_split;
     int32_t ndkeys[kJDK];
-    if (un < n_units) {
-      load_dkeys(a, dn.x, dn.y, ndkeys);
-      load_rows(a, dn.z + tid, dn.w, nxt);
-    }
+    // past the last unit the loads read the current unit again (discarded)
+    const uint4 pd = un < n_units ? dn : d;
     if (sp.x == 0) {
       // Whole unit: emit its groups. Output room is reserved with one atomic
       // per unit, taken when the unit finishes, so no unit waits on another.
-      uint32_t mine = 0;
-#pragma unroll
-      for (int k = 0; k < kJPer; ++k) mine += tcnt[tid * kJPer + k] != 0;
-      int64_t o = reserve_out(a, mine, scr, &s_excl);
+      // The next unit's loads are issued after the atomic and travel while
+      // thread 0 waits for it. Slots go out in round-major order (round k
+      // holds slots k * kJBlock + thread), so each wave's stores of a round
+      // land on consecutive output rows.
+      uint32_t occ[kJPer];
+      uint64_t bal[kJPer];
 #pragma unroll
       for (int k = 0; k < kJPer; ++k) {
-        const int s = tid * kJPer + k;
-        const uint32_t c = tcnt[s];
-        if (c == 0) continue;
-        put_group(a, o++, (int64_t)(int32_t)(uint32_t)tkey[s], tsp[s], tsq[s], c);
+        occ[k] = tcnt[k * kJBlock + tid];
+        bal[k] = wave_ballot(occ[k] != 0);
+        if (lane == 0) s_wk[k][wave] = (uint32_t)__popcll(bal[k]);
+      }
+      __syncthreads();
+      uint32_t total = 0, base[kJPer];
+#pragma unroll
+      for (int k = 0; k < kJPer; ++k) {
+#pragma unroll
+        for (int w = 0; w < kJBlock / kWave; ++w) {
+          if (w == (int)wave) base[k] = total;
+          total += s_wk[k][w];
+        }
+      }
+      int64_t resv = 0;
+      if (tid == 0 && total) resv = reserve_nowait(a, total);
+      prefetch_unit(a, pd, ndkeys, nxt);
+      if (tid == 0) s_excl = (uint64_t)resv;
+      __syncthreads();
+      const int64_t o0 = (int64_t)s_excl;
+#pragma unroll
+      for (int k = 0; k < kJPer; ++k) {
+        if (occ[k] == 0) continue;
+        const int s = k * kJBlock + tid;
+        put_group(a, o0 + base[k] + mask_rank(bal[k]), (int64_t)(int32_t)(uint32_t)tkey[s], tsp[s], tsq[s], occ[k]);
       }
     } else {
       // Sub-unit of a split chunk: add the partial sums into the chunk's
       // accumulator; the last sub-unit to finish emits and clears it.
+      prefetch_unit(a, pd, ndkeys, nxt);
       SplitAcc* acc = a.split_acc + (size_t)(sp.x - 1) * kJChunk;
 #pragma unroll
       for (int k = 0; k < kJPer; ++k) {
@@ -1042,15 +1181,18 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   TRY(scratch(ctx, SCR_PART_B, fact_bytes, &pb));
   TRY(scratch(ctx, SCR_PART_C, (size_t)(m > 0 ? m : 1) * 16 + 4 * 256, &pc));
   const size_t book = ((size_t)fnt1 * nb1 + (size_t)dnt1 * nb1 + (size_t)fnt2 * nb2 + (size_t)dnt2 * nb2 + 2 * nb1 +
-                       5 * (size_t)nparts) * 4 + (size_t)max_units * (sizeof(uint4) + sizeof(uint2)) + 64 * 256;
+                       5 * (size_t)nparts + ((size_t)nparts / kUBlk + 1) * kClasses) * 4 +
+                      (size_t)max_units * (sizeof(uint4) + sizeof(uint2)) + 64 * 256;
   TRY(scratch(ctx, SCR_PART_D, book, &pd));
   // split-chunk accumulators and their done counters: zero when allocated, and
   // left zero by every call (the last sub-unit of a chunk clears what it emits)
   void* pe;
-  const size_t split_bytes = (size_t)kMaxSplit * kJChunk * sizeof(SplitAcc) + kMaxSplit * sizeof(uint32_t);
+  const size_t split_bytes = (size_t)kMaxSplit * kJChunk * sizeof(SplitAcc) + (kMaxSplit + 1) * sizeof(uint32_t);
   const bool fresh = ctx->scratch[SCR_PART_E].bytes < split_bytes;
   TRY(scratch(ctx, SCR_PART_E, split_bytes, &pe));
   if (fresh) TRY(fill_u32(ctx, pe, split_bytes / 4, 0));
+  uint32_t* split_done = (uint32_t*)((char*)pe + (size_t)kMaxSplit * kJChunk * sizeof(SplitAcc));
+  uint32_t* split_ctr = split_done + kMaxSplit;
 
   PartSide F{};
   F.key = fact->fk;
@@ -1093,6 +1235,8 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   uint4* unit_desc = cd.take<uint4>(max_units);
   uint2* unit_split = cd.take<uint2>(max_units);
   uint32_t* sbase = cd.take<uint32_t>(nparts);
+  const uint32_t unit_wgs = (nparts + kUBlk - 1) / kUBlk;
+  uint32_t* wg_cls = cd.take<uint32_t>((size_t)unit_wgs * kClasses);
   int64_t* n_units = counters + CNT_AUX0;
   int64_t* ticket = counters + CNT_TICKET;
 
@@ -1100,10 +1244,26 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   TRY(partition_side(ctx, F, true, counters + CNT_ROWS_PASSED));
 
   {
+    UnitArgs ua{};
+    ua.dstart = D.pstart;
+    ua.dcount = D.pcount;
+    ua.fstart = F.pstart;
+    ua.fcount = F.pcount;
+    ua.nparts = nparts;
+    ua.rows_passed = counters + CNT_ROWS_PASSED;
+    ua.split_ctr = split_ctr;
+    ua.sbase = sbase;
+    ua.wg_cls = wg_cls;
+    ua.desc = unit_desc;
+    ua.split = unit_split;
+    ua.n_units = n_units;
     {
-      KernelTimer kt(ctx, "make_units");
-      hipLaunchKernelGGL(k_make_units, dim3(1), dim3(1024), 0, ctx->stream, D.pstart, D.pcount, F.pstart, F.pcount,
-                         nparts, unit_desc, unit_split, sbase, n_units);
+      KernelTimer kt(ctx, "unit_count");
+      hipLaunchKernelGGL(k_unit_count, dim3(unit_wgs), dim3(kUBlk), 0, ctx->stream, ua);
+    }
+    {
+      KernelTimer kt(ctx, "unit_emit");
+      hipLaunchKernelGGL(k_unit_emit, dim3(unit_wgs), dim3(kUBlk), 0, ctx->stream, ua);
     }
     REL_LAUNCH_CHECK(ctx, "make_units");
     TRY(fill_u64(ctx, ticket, 1, 0));
@@ -1118,7 +1278,7 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
     a.fprice = F.price2;
     a.fqty = F.qty2;
     a.split_acc = (SplitAcc*)pe;
-    a.split_done = (uint32_t*)((char*)pe + (size_t)kMaxSplit * kJChunk * sizeof(SplitAcc));
+    a.split_done = split_done;
     a.zero = 0;
     a.ticket = ticket;
     a.matched = counters + CNT_JOIN_MATCHES;
