@@ -172,6 +172,32 @@ __device__ __forceinline__ bool join_lookup(const JoinView& t, int32_t key, int3
   return false;
 }
 
+// Split form of join_lookup for several independent probes per thread: the
+// first slot of every probe is loaded together (join_first), then each probe
+// is finished from its loaded slot (join_finish), walking on only when the
+// first slot holds another key.
+__device__ __forceinline__ size_t join_first_index(const JoinView& t, int32_t key) {
+  return key == -1 ? (size_t)t.mask + 1 : (size_t)hash32(key, t.shift);
+}
+
+__device__ __forceinline__ bool join_finish(const JoinView& t, int32_t key, uint64_t s, int32_t* payload) {
+  if (key == -1) {
+    *payload = (int32_t)(uint32_t)s;
+    return s != kJoinEmpty;
+  }
+  uint32_t h = hash32(key, t.shift);
+  for (uint32_t step = 0; step <= t.mask; ++step) {
+    if (s == kJoinEmpty) return false;
+    if ((uint32_t)s == (uint32_t)key) {
+      *payload = (int32_t)(s >> 32);
+      return true;
+    }
+    h = (h + 1) & t.mask;
+    s = t.slots[h];
+  }
+  return false;
+}
+
 // Insert (key, payload) into a join table with one 64-bit CAS per attempted
 // slot; a repeated key sets kDevDupKey, a full table kDevOverflow.
 __device__ __forceinline__ void join_insert(uint64_t* slots, uint32_t mask, uint32_t shift, int32_t key, int32_t pl,

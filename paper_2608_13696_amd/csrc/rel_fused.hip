@@ -22,6 +22,7 @@ enum Mode : int { M_PRIO_FLAG = REL_GROUP_PRIO_FLAG, M_FK = REL_GROUP_FK, M_DIM_
 enum GPlace : int { G_LDS = 0, G_GLOBAL = 1, G_ROWAGG = 2 };
 
 constexpr int kBlock = 256;
+constexpr int kLdsBlock = 1024;  // fused kernel with an LDS group table: one workgroup per CU
 constexpr int kIPT = 4;  // rows per thread per tile: one 16-byte load per int32 column
 constexpr int kLdsSlots = 1024;
 constexpr int kLdsProbe = 32;
@@ -53,62 +54,80 @@ __device__ __forceinline__ int64_t group_key(int32_t payload, int32_t fk, int8_t
   return (int64_t)fk;
 }
 
-template <int MODE, int GP>
-__global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a) {
+// One thread's rows of a tile: kIPT consecutive rows, loaded with 16-byte loads.
+struct FusedRows {
+  int32_t d[kIPT], f[kIPT], q[kIPT];
+  int64_t p[kIPT];
+  uint32_t fl;  // the four flag bytes
+  int nv;       // rows in range
+};
+
+template <int MODE>
+__device__ __forceinline__ void load_fused(const FusedArgs& a, int64_t r0, FusedRows& r) {
+  if (r0 + kIPT <= a.n) {
+    r.nv = kIPT;
+    const int4 dv = *reinterpret_cast<const int4*>(a.day + r0);
+    const int4 fv = *reinterpret_cast<const int4*>(a.fk + r0);
+    const int4 qv = *reinterpret_cast<const int4*>(a.qty + r0);
+    const longlong2 p01 = *reinterpret_cast<const longlong2*>(a.price + r0);
+    const longlong2 p23 = *reinterpret_cast<const longlong2*>(a.price + r0 + 2);
+    r.d[0] = dv.x; r.d[1] = dv.y; r.d[2] = dv.z; r.d[3] = dv.w;
+    r.f[0] = fv.x; r.f[1] = fv.y; r.f[2] = fv.z; r.f[3] = fv.w;
+    r.q[0] = qv.x; r.q[1] = qv.y; r.q[2] = qv.z; r.q[3] = qv.w;
+    r.p[0] = p01.x; r.p[1] = p01.y; r.p[2] = p23.x; r.p[3] = p23.y;
+    r.fl = MODE == M_PRIO_FLAG ? *reinterpret_cast<const uint32_t*>(a.flag + r0) : 0u;
+  } else {
+    r.nv = r0 < a.n ? (int)(a.n - r0) : 0;
+    r.fl = 0;
+#pragma unroll
+    for (int k = 0; k < kIPT; ++k) {
+      const bool ok = k < r.nv;
+      r.d[k] = ok ? a.day[r0 + k] : 0;
+      r.f[k] = ok ? a.fk[r0 + k] : 0;
+      r.q[k] = ok ? a.qty[r0 + k] : 0;
+      r.p[k] = ok ? a.price[r0 + k] : 0;
+      if (MODE == M_PRIO_FLAG && ok) r.fl |= (uint32_t)(uint8_t)a.flag[r0 + k] << (8 * k);
+    }
+  }
+}
+
+// Persistent: each workgroup walks tiles with a grid stride and loads its next
+// tile while it probes and aggregates the current one. With an LDS group
+// table there is one large workgroup per CU, so the table is flushed to device
+// memory once per CU (few groups means few, heavily shared device slots).
+template <int MODE, int GP, int NT>
+__global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
   __shared__ LdsGroups<GP == G_LDS ? kLdsSlots : 1> lds;
   if (GP == G_LDS) {
-    lds.init(threadIdx.x, kBlock);
+    lds.init(threadIdx.x, NT);
     __syncthreads();
   }
   uint64_t passed = 0, matched = 0;
-  constexpr int64_t tile_rows = (int64_t)kBlock * kIPT;
+  constexpr int64_t tile_rows = (int64_t)NT * kIPT;
   const int64_t ntiles = (a.n + tile_rows - 1) / tile_rows;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t r0 = tile * tile_rows + (int64_t)threadIdx.x * kIPT;
-    int32_t d[kIPT], f[kIPT], q[kIPT];
-    int64_t p[kIPT];
-    int8_t fl[kIPT];
-    int nv;
-    if (r0 + kIPT <= a.n) {
-      nv = kIPT;
-      const int4 dv = *reinterpret_cast<const int4*>(a.day + r0);
-      const int4 fv = *reinterpret_cast<const int4*>(a.fk + r0);
-      const int4 qv = *reinterpret_cast<const int4*>(a.qty + r0);
-      const longlong2 p01 = *reinterpret_cast<const longlong2*>(a.price + r0);
-      const longlong2 p23 = *reinterpret_cast<const longlong2*>(a.price + r0 + 2);
-      d[0] = dv.x; d[1] = dv.y; d[2] = dv.z; d[3] = dv.w;
-      f[0] = fv.x; f[1] = fv.y; f[2] = fv.z; f[3] = fv.w;
-      q[0] = qv.x; q[1] = qv.y; q[2] = qv.z; q[3] = qv.w;
-      p[0] = p01.x; p[1] = p01.y; p[2] = p23.x; p[3] = p23.y;
-      if (MODE == M_PRIO_FLAG) {
-        const uint32_t w = *reinterpret_cast<const uint32_t*>(a.flag + r0);
+  int64_t tile = blockIdx.x;
+  FusedRows cur, nxt;
+  if (tile < ntiles) load_fused<MODE>(a, tile * tile_rows + (int64_t)threadIdx.x * kIPT, cur);
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int64_t tn = tile + gridDim.x;
+    if (tn < ntiles) load_fused<MODE>(a, tn * tile_rows + (int64_t)threadIdx.x * kIPT, nxt);
+    // every row's first join slot is loaded before any is examined, so the
+    // tile's random reads overlap instead of following one another
+    bool pass[kIPT];
+    uint64_t first[kIPT];
 #pragma unroll
-        for (int k = 0; k < kIPT; ++k) fl[k] = (int8_t)(w >> (8 * k));
-      } else {
-#pragma unroll
-        for (int k = 0; k < kIPT; ++k) fl[k] = 0;
-      }
-    } else {
-      nv = r0 < a.n ? (int)(a.n - r0) : 0;
-#pragma unroll
-      for (int k = 0; k < kIPT; ++k) {
-        const bool ok = k < nv;
-        d[k] = ok ? a.day[r0 + k] : 0;
-        f[k] = ok ? a.fk[r0 + k] : 0;
-        q[k] = ok ? a.qty[r0 + k] : 0;
-        p[k] = ok ? a.price[r0 + k] : 0;
-        fl[k] = (ok && MODE == M_PRIO_FLAG) ? a.flag[r0 + k] : 0;
-      }
+    for (int k = 0; k < kIPT; ++k) {
+      pass[k] = k < cur.nv && cur.d[k] < a.day_lt;
+      first[k] = pass[k] ? a.join.slots[join_first_index(a.join, cur.f[k])] : kJoinEmpty;
     }
 #pragma unroll
     for (int k = 0; k < kIPT; ++k) {
       // no early exits: the device-memory update below is a wave-wide call
-      const bool pass = k < nv && d[k] < a.day_lt;
-      passed += pass;
+      passed += pass[k];
       int32_t pl = 0;
-      const bool hit = pass && join_lookup(a.join, f[k], &pl);
+      const bool hit = pass[k] && join_finish(a.join, cur.f[k], first[k], &pl);
       matched += hit;
-      const uint64_t sp = (uint64_t)p[k], sq = (uint64_t)(int64_t)q[k];
+      const uint64_t sp = (uint64_t)cur.p[k], sq = (uint64_t)(int64_t)cur.q[k];
       if (GP == G_ROWAGG) {
         if (hit) {
           RowAgg* r = &a.row_agg[pl];
@@ -117,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a) {
           dev_add<uint64_t>(&r->count, 1ull);
         }
       } else {
-        const int64_t key = hit ? group_key<MODE>(pl, f[k], fl[k]) : 0;
+        const int64_t key = hit ? group_key<MODE>(pl, cur.f[k], (int8_t)(cur.fl >> (8 * k))) : 0;
         bool global = hit;
         if (GP == G_LDS && hit) {
           const int s = lds.find(key, a.lds_probe);
@@ -129,10 +148,11 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a) {
         group_add_wave(a.groups, global, key, sp, sq);
       }
     }
+    cur = nxt;
   }
   if (GP == G_LDS) {
     __syncthreads();
-    lds.flush(a.groups, threadIdx.x, kBlock);
+    lds.flush(a.groups, threadIdx.x, NT);
   }
   passed = wave_sum(passed);
   matched = wave_sum(matched);
@@ -308,11 +328,11 @@ template <int MODE>
 rel_status launch_fused(rel_ctx* ctx, int gp, const FusedArgs& a, unsigned grid) {
   relh::KernelTimer kt(ctx, "probe_agg");
   if (gp == G_LDS)
-    hipLaunchKernelGGL((k_fused<MODE, G_LDS>), dim3(grid), dim3(kBlock), 0, ctx->stream, a);
+    hipLaunchKernelGGL((k_fused<MODE, G_LDS, kLdsBlock>), dim3(grid), dim3(kLdsBlock), 0, ctx->stream, a);
   else if (gp == G_GLOBAL)
-    hipLaunchKernelGGL((k_fused<MODE, G_GLOBAL>), dim3(grid), dim3(kBlock), 0, ctx->stream, a);
+    hipLaunchKernelGGL((k_fused<MODE, G_GLOBAL, kBlock>), dim3(grid), dim3(kBlock), 0, ctx->stream, a);
   else
-    hipLaunchKernelGGL((k_fused<MODE, G_ROWAGG>), dim3(grid), dim3(kBlock), 0, ctx->stream, a);
+    hipLaunchKernelGGL((k_fused<MODE, G_ROWAGG, kBlock>), dim3(grid), dim3(kBlock), 0, ctx->stream, a);
   REL_LAUNCH_CHECK(ctx, "fused");
   return REL_OK;
 }
@@ -448,7 +468,7 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
   }
 
   if (n > 0) {
-    const unsigned grid = relh::grid_for(ctx, n, kBlock * kIPT, gp == G_LDS ? 4 : 8);
+    const unsigned grid = gp == G_LDS ? relh::grid_for(ctx, n, kLdsBlock * kIPT, 1) : relh::grid_for(ctx, n, kBlock * kIPT, 8);
     if (gb == REL_GROUP_PRIO_FLAG) TRY(launch_fused<M_PRIO_FLAG>(ctx, gp, a, grid));
     else if (gb == REL_GROUP_FK) TRY(launch_fused<M_FK>(ctx, gp, a, grid));
     else TRY(launch_fused<M_DIM_GRP>(ctx, gp, a, grid));
