@@ -287,14 +287,19 @@ rel_status rel_mlp_adam_step(rel_ctx* ctx, float* d_params, float* d_m, float* d
 
 typedef struct rel_planner rel_planner;
 
-/* A planner from host arrays: params[6914], feature standardisation
- * mean[40] / scale[40] (x' = (x - mean) / scale), and the safety margin in
- * log2 units added to the predicted group count. */
+/* A planner from host arrays: params[6914], standardisation mean[40] /
+ * scale[40] of the network's input, and the safety margin in log2 units added
+ * to the predicted group count. The input is the sketch with its size-dependent
+ * features taken relative to r, the log2 HyperLogLog estimate of the group key
+ * (fk; dim.grp; for (prio, flag) the smaller of the fk estimate and
+ * log2(1 + M)): features 0, 1, 12, 13, 16, 17 and 37 minus r, features 19..36
+ * set to 0, then x' = (x - mean) / scale. The network's outputs are
+ * log2(1 + join rows) - log2(1 + N) and log2(1 + groups) - r. */
 rel_status rel_planner_create(rel_ctx* ctx, const float* params, const float* mean, const float* scale,
                               float margin_log2, rel_planner** out);
 /* Sketch, predict and fill *plan (group capacity and placement, fallback
- * allowed). Synchronises once (two floats come back). pred (host, nullable)
- * receives the raw predictions log2(1 + join rows), log2(1 + groups). */
+ * allowed). Synchronises once (a few floats come back). pred (host, nullable)
+ * receives the predictions log2(1 + join rows), log2(1 + groups). */
 rel_status rel_planner_plan(rel_planner* p, const rel_fact* fact, const rel_dim* dim, const rel_query* q,
                             const int64_t* d_fact_sample, const int64_t* d_dim_sample, int32_t k, rel_plan* plan,
                             float* pred);

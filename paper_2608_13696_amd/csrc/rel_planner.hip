@@ -384,13 +384,40 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
   p[i] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-// Standardise the features in place; keep the raw sampled max frequency
-// (feature 10), which the sizing rule reads as a skew signal.
-__global__ void k_normalize(float* __restrict__ x, const float* __restrict__ mean, const float* __restrict__ scale,
-                            float* __restrict__ raw_maxfreq) {
+// The network's input. Features that grow with the input size enter relative
+// to a reference scale r, the log2 HyperLogLog estimate of the group key
+// (fk; dim.grp; for (prio, flag) the smaller of the fk estimate and
+// log2(1 + M)): log2 N, log2 M, the sampled key ranges and both estimates
+// become differences from r, and the register-level HLL features (their
+// level moves with the size) are left out. The network's group output is
+// likewise log2(1 + groups) - r and its join output log2(1 + join rows) -
+// log2(1 + N). A model trained on small instances then carries over to much
+// larger ones. The result is standardised with the training mean and scale.
+// aux[0] = raw sampled max frequency (feature 10, the sizing rule's skew
+// signal), aux[1] = r, aux[2] = log2(1 + N).
+constexpr int kRelFeat[] = {0, 1, 12, 13, 16, 17, 37};
+
+__global__ void k_prepare_input(float* __restrict__ x, const float* __restrict__ mean, const float* __restrict__ scale,
+                                float* __restrict__ aux) {
+  __shared__ float s_r;
   const int i = threadIdx.x;
-  if (i == 10) *raw_maxfreq = x[i];
-  if (i < kFeat) x[i] = (x[i] - mean[i]) / scale[i];
+  if (i == 0) {
+    const float r = x[4] > 0.5f ? x[17] : x[5] > 0.5f ? x[37] : fminf(x[17], x[1]);
+    s_r = r;
+    aux[0] = x[10];
+    aux[1] = r;
+    aux[2] = x[0];
+  }
+  __syncthreads();
+  if (i < kFeat) {
+    float v = x[i];
+    bool rel = false;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) rel |= i == kRelFeat[j];
+    if (rel) v -= s_r;
+    else if (i >= 19 && i <= 36) v = 0.f;
+    x[i] = (v - mean[i]) / scale[i];
+  }
 }
 
 // A key seen this often among the sampled rows marks a heavy hitter (about
@@ -500,7 +527,7 @@ rel_status rel_planner_create(rel_ctx* ctx, const float* params, const float* me
   rel_planner* p = new rel_planner();
   p->ctx = ctx;
   p->margin = margin_log2;
-  const size_t floats = kParams + 3 * kFeat + 4 + 64;  // params, mean, scale, features, prediction + skew, HLL bytes
+  const size_t floats = kParams + 3 * kFeat + 8 + 64;  // params, mean, scale, features, prediction + aux, HLL bytes
   hipError_t e = hipMalloc(&p->mem, floats * sizeof(float));
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -527,27 +554,28 @@ rel_status rel_planner_plan(rel_planner* p, const rel_fact* fact, const rel_dim*
   float* mean = params + kParams;
   float* scale = mean + kFeat;
   float* feat = scale + kFeat;
-  float* y = feat + kFeat;  // y[0], y[1]: prediction; y[2]: raw sampled max frequency
-  uint8_t* hll = (uint8_t*)(y + 4);
+  float* y = feat + kFeat;  // y[0], y[1]: network outputs; y[2..4]: aux of k_prepare_input
+  uint8_t* hll = (uint8_t*)(y + 8);
   TRY(rel_sketch(ctx, fact, dim, q, d_fact_sample, d_dim_sample, k, feat, hll));
   {
-    relh::KernelTimer kt(ctx, "planner_normalize");
-    hipLaunchKernelGGL(k_normalize, dim3(1), dim3(64), 0, ctx->stream, feat, (const float*)mean, (const float*)scale,
-                       y + 2);
+    relh::KernelTimer kt(ctx, "planner_input");
+    hipLaunchKernelGGL(k_prepare_input, dim3(1), dim3(64), 0, ctx->stream, feat, (const float*)mean,
+                       (const float*)scale, y + 2);
   }
-  REL_LAUNCH_CHECK(ctx, "normalize");
+  REL_LAUNCH_CHECK(ctx, "prepare_input");
   TRY(rel_mlp_forward(ctx, params, feat, 1, y));
-  float hy[3];
+  float hy[5];
   REL_HIP_CHECK(ctx, hipMemcpyAsync(hy, y, sizeof hy, hipMemcpyDeviceToHost, ctx->stream));
   REL_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  const double log2_join = (double)hy[0] + hy[4], log2_groups = (double)hy[1] + hy[3];
   if (pred) {
-    pred[0] = hy[0];
-    pred[1] = hy[1];
+    pred[0] = (float)log2_join;
+    pred[1] = (float)log2_groups;
   }
   // sizing rule: expected groups = 2^(prediction + margin), never above the plain bound
   const int64_t n = fact->n, m = dim->m;
   const int64_t ub = q->group_by == REL_GROUP_PRIO_FLAG ? std::min<int64_t>(n, 65536) : std::min(n, m);
-  double e = std::exp2((double)hy[1] + (double)p->margin);
+  double e = std::exp2(log2_groups + (double)p->margin);
   if (!std::isfinite(e) || e > (double)ub) e = (double)ub;
   int64_t expected = (int64_t)std::ceil(e);
   if (expected < 1) expected = 1;

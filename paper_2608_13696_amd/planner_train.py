@@ -6,10 +6,16 @@ columns all varied). Each run's label is what the plain pipeline reports
 (join output rows, groups); each run's input is the GPU sketch. Training runs
 on the GPU through librel's own MLP kernels (forward, backward, Adam).
 
-Targets: y = (log2(1 + join rows), log2(1 + groups)). Loss: mean squared
-error. The planner's safety margin is the 95th percentile of the validation
-under-prediction of log2(1 + groups), so about one plan in twenty overflows
-and falls back to the plain pipeline.
+Input and targets are scale-free (the same transform the library's planner
+applies before its forward pass, see relative_inputs): size-dependent features
+are taken relative to r, the log2 HyperLogLog estimate of the group key, and
+the targets are y = (log2(1 + join rows) - log2(1 + N), log2(1 + groups) - r).
+Runs of up to 2^17 fact rows then train a model that sizes tables for inputs
+hundreds of times larger. Loss: mean squared error. The planner's safety
+margin is the 95th percentile of the validation under-prediction of the group
+target; a planned group table has twice the expected slots, so a prediction
+must be short by about that factor again before the run overflows and falls
+back to the plain pipeline.
 
 Usage: python -m paper_2608_13696_amd.planner_train --runs 200000 --out <file.npz>
 """
@@ -102,20 +108,46 @@ def build_corpus(ctx, runs: int, seed: int, n_hi: int, chunk: int = 2048):
     return feats, labels
 
 
+REL_FEATURES = (0, 1, 12, 13, 16, 17, 37)  # size-dependent: taken relative to r
+HLL_REGISTER_FEATURES = slice(19, 37)      # register-level HLL features: left out
+
+
+def relative_inputs(feats: np.ndarray):
+    """The network's input before standardisation, and the reference scale r
+    per run (mirrors the library's planner input kernel)."""
+    f = np.asarray(feats, np.float64)
+    r = np.where(f[:, 4] > 0.5, f[:, 17], np.where(f[:, 5] > 0.5, f[:, 37], np.minimum(f[:, 17], f[:, 1])))
+    x = f.copy()
+    for i in REL_FEATURES:
+        x[:, i] -= r
+    x[:, HLL_REGISTER_FEATURES] = 0.0
+    return x, r
+
+
+def targets(feats: np.ndarray, labels: np.ndarray):
+    """Scale-free targets (join relative to log2(1 + N), groups relative to r)."""
+    _, r = relative_inputs(feats)
+    y = np.log2(1.0 + labels.astype(np.float64))
+    y[:, 0] -= np.asarray(feats, np.float64)[:, 0]
+    y[:, 1] -= r
+    return y
+
+
 def train(ctx, feats: np.ndarray, labels: np.ndarray, seed: int, epochs: int, batch: int = 256, lr: float = 1e-3):
     import torch
 
     from . import rel
 
     n = feats.shape[0]
-    y = np.log2(1.0 + labels.astype(np.float64)).astype(np.float32)
+    y = targets(feats, labels).astype(np.float32)
+    xin = relative_inputs(feats)[0].astype(np.float32)
     perm = np.argsort(datagen.unit(n, seed, 901))
     n_val = max(1, n // 10)
     val, tr = perm[:n_val], perm[n_val:]
-    mean = feats[tr].mean(axis=0).astype(np.float32)
-    scale = feats[tr].std(axis=0).astype(np.float32)
+    mean = xin[tr].mean(axis=0).astype(np.float32)
+    scale = xin[tr].std(axis=0).astype(np.float32)
     scale[scale < 1e-6] = 1.0
-    X = torch.from_numpy((feats - mean) / scale).cuda()
+    X = torch.from_numpy((xin - mean) / scale).cuda()
     Y = torch.from_numpy(y).cuda()
     # He-uniform initialisation from seeded unit draws (biases zero)
     u = datagen.unit(N_PARAMS, seed, 902)
@@ -188,7 +220,8 @@ def main():
         if args.corpus:
             np.savez(args.corpus, feats=feats, labels=labels)
     params, mean, scale, margin, metrics = train(ctx, feats, labels, args.seed, args.epochs)
-    meta = dict(metrics, runs=int(feats.shape[0]), n_hi=args.n_hi, seed=args.seed)
+    meta = dict(metrics, runs=int(feats.shape[0]), n_hi=args.n_hi, seed=args.seed,
+                inputs="relative to the group key's log2 HLL estimate")
     save_model(args.out, params, mean, scale, margin, meta)
     log(f"saved {args.out}: margin {margin:.3f}, validation MSE {metrics['val_mse']:.4f}")
     print(json.dumps(meta))

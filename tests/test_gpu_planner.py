@@ -57,15 +57,16 @@ def test_planned_equals_plain_and_oracle(ctx, planner, groups):
 
 
 def test_undersized_plan_falls_back_identically(ctx):
-    # a network that predicts zero groups: the plan is one slot, it overflows
-    # and the plain pipeline reruns
+    # a network whose outputs are -64 whatever the input predicts far below one
+    # group: the plan is one slot, it overflows and the plain pipeline reruns
     z = np.zeros(6914, np.float32)
+    z[-2:] = -64.0  # the output biases
     p = rel.Planner(ctx, z, np.zeros(40, np.float32), np.ones(40, np.float32), 0.0)
     T = datagen.planner_eval(5000, seed=56, n=1_000_000, m=250_000)
     fact, dim = to_dev(T)
     fs, ds = _samples(T)
     plan, pred = p.plan(fact, dim, T.day_lt, T.group_by, fs, ds)
-    assert plan.group_capacity == 1 and pred == (0.0, 0.0)
+    assert plan.group_capacity == 1 and pred[1] < -30
     out, st = ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, plan=plan)
     assert st["fell_back"] == 1 and st["overflowed"] == 1
     assert_groups_equal(gpu_groups(out), oracle.run_tables(T)[0], "fallback")
@@ -73,13 +74,17 @@ def test_undersized_plan_falls_back_identically(ctx):
 
 
 def test_prediction_tracks_group_count(ctx, planner):
-    # not a parity check (the prediction has no oracle): the trained network
-    # should order group counts correctly across three decades
-    preds = []
+    # not a parity check (the prediction has no oracle): on inputs 15x larger
+    # than any training run the trained network should order group counts
+    # correctly across four decades and land within a factor of 4 of each
+    preds, actual = [], []
     for groups in (100, 10_000, 1_000_000):
         T = datagen.planner_eval(groups, seed=57, n=2_000_000, m=500_000)
         fact, dim = to_dev(T)
         fs, ds = _samples(T)
         _, pred = planner.plan(fact, dim, T.day_lt, T.group_by, fs, ds)
+        _, st = ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by)
         preds.append(pred[1])
+        actual.append(np.log2(1.0 + st["groups"]))
     assert preds[0] < preds[1] < preds[2]
+    assert all(abs(p - a) < 2.0 for p, a in zip(preds, actual)), (preds, actual)
