@@ -90,19 +90,21 @@ def kernel_times(ctx) -> dict:
     return {names[i].decode(): (tot[i], cnt[i]) for i in range(min(n.value, 32))}
 
 
-def traffic_for(kernel: str, workload_name: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if the
-    kernel source is unchanged since the counters were taken."""
+VALU_PEAK_G = 256 * 2.4  # G wave64 VALU instructions/s: 256 CUs x one per clock x 2.4 GHz
+
+
+def counters_for(kernel: str, workload_name: str) -> dict:
+    """The committed rocprofv3 counter summary of a kernel (HBM bytes and VALU
+    instructions per launch), if the kernel sources are unchanged since the
+    counters were taken; else {}."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload_name}.json")
     if not os.path.exists(path):
-        return None
+        return {}
     try:
         rec = json.load(open(path))
-        if rec.get("src_sha") != source_sha():
-            return None
-        return rec.get("traffic_bytes_per_launch")
+        return rec if rec.get("src_sha") == source_sha() else {}
     except Exception:
-        return None
+        return {}
 
 
 def source_sha() -> str:
@@ -437,6 +439,13 @@ def main() -> int:
         kms = tot / max(c, 1)
         b, _ = kernel_alg_bytes(k, n, m, r, g, T.group_by)
         per_kernel[k] = {"ms": kms, "alg_gbs": (b / (kms / 1e3) / 1e9) if b else None}
+    ctr = counters_for(dom_name, args.workload)
+    valu = None
+    if ctr.get("valu_insts_per_launch"):
+        gis = ctr["valu_insts_per_launch"] / (dom_ms / 1e3) / 1e9
+        valu = {"insts_per_launch": ctr["valu_insts_per_launch"], "achieved": gis, "peak": VALU_PEAK_G,
+                "unit": "G wave-instr/s", "frac": gis / VALU_PEAK_G,
+                "insts_per_alg_byte": ctr["valu_insts_per_launch"] / alg_bytes if alg_bytes else None}
     per_row = FACT_BYTES[T.group_by]
     pipe_bytes = per_row * n + DIM_BYTES[T.group_by] * m + OUT_BYTES_PER_GROUP * g
     pipe_gbs = pipe_bytes / (ms / 1e3) / 1e9
@@ -459,8 +468,9 @@ def main() -> int:
                    "join_placement": st["join_placement"], "group_placement": st["group_placement"]},
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": traffic_for(dom_name, args.workload), "algorithmic_bytes_per_launch": alg_bytes,
-                     "per_unit": unit_desc, "avg_launch_ms": dom_ms, "launches": dom_cnt},
+                     "traffic": ctr.get("traffic_bytes_per_launch"), "algorithmic_bytes_per_launch": alg_bytes,
+                     "per_unit": unit_desc, "avg_launch_ms": dom_ms, "launches": dom_cnt,
+                     "valu": valu},
         "pipeline": {"compulsory_bytes": pipe_bytes, "achieved_gbs": pipe_gbs, "hbm_frac": pipe_gbs / HBM_PEAK_GBS,
                      "kernels": per_kernel},
     }
