@@ -93,6 +93,23 @@ static hipEvent_t take_event(rel_ctx* ctx) {
   return e;
 }
 
+rel_status aux_fork(rel_ctx* ctx) {
+  if (!ctx->aux) {
+    REL_HIP_CHECK(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    REL_HIP_CHECK(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    REL_HIP_CHECK(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+  }
+  REL_HIP_CHECK(ctx, hipEventRecord(ctx->ev_fork, ctx->stream));
+  REL_HIP_CHECK(ctx, hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0));
+  return REL_OK;
+}
+
+rel_status aux_join(rel_ctx* ctx) {
+  REL_HIP_CHECK(ctx, hipEventRecord(ctx->ev_join, ctx->aux));
+  REL_HIP_CHECK(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
+  return REL_OK;
+}
+
 KernelTimer::KernelTimer(rel_ctx* ctx, const char* name) : ctx_(ctx) {
   if (!ctx || !ctx->timing) return;
   for (size_t i = 0; i < ctx->timings.size(); ++i)
@@ -219,6 +236,12 @@ rel_status rel_ctx_destroy(rel_ctx* ctx) {
       (void)hipEventDestroy(pr.second);
     }
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+    (void)hipEventDestroy(ctx->ev_fork);
+    (void)hipEventDestroy(ctx->ev_join);
+  }
   if (ctx->d_status) (void)hipFree(ctx->d_status);
   delete ctx;
   return REL_OK;

@@ -67,6 +67,10 @@ struct rel_ctx {
   bool timing = false;
   std::vector<KernelTiming> timings;
   std::vector<hipEvent_t> event_pool;
+  // A second stream of the library's own (default priority) for work that can
+  // run beside the caller's stream, with the fork / join events; made on first use.
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 struct rel_join_table {
@@ -108,6 +112,12 @@ rel_status fill_u32(rel_ctx* ctx, void* p, size_t n_u32, uint32_t v);
 
 // Records a start event on construction and a stop event on destruction when
 // the context's timing is enabled; otherwise does nothing.
+// aux_fork orders the auxiliary stream after the work already on ctx->stream
+// (creating it on first use); aux_join makes ctx->stream wait for everything
+// enqueued on the auxiliary stream since.
+rel_status aux_fork(rel_ctx* ctx);
+rel_status aux_join(rel_ctx* ctx);
+
 class KernelTimer {
  public:
   KernelTimer(rel_ctx* ctx, const char* name);

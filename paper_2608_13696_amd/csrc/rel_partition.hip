@@ -1240,8 +1240,18 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   int64_t* n_units = counters + CNT_AUX0;
   int64_t* ticket = counters + CNT_TICKET;
 
-  TRY(partition_side(ctx, D, false, nullptr));
+  // The two sides are independent until the groupjoin: the dim side (small,
+  // latency-bound kernels) runs on the auxiliary stream beside the fact side.
+  TRY(aux_fork(ctx));
+  {
+    hipStream_t main = ctx->stream;
+    ctx->stream = ctx->aux;
+    const rel_status sd = partition_side(ctx, D, false, nullptr);
+    ctx->stream = main;
+    if (sd != REL_OK) return sd;
+  }
   TRY(partition_side(ctx, F, true, counters + CNT_ROWS_PASSED));
+  TRY(aux_join(ctx));
 
   {
     UnitArgs ua{};
