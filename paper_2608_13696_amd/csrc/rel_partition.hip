@@ -26,10 +26,10 @@ using namespace rel;
 
 constexpr int kBlk = 256;         // histogram and scan kernels
 constexpr int kSBlk = 512;        // scatter kernels
-// First level: one 2048-row tile per workgroup (36 KB of LDS, four per CU).
-// Second level: persistent workgroups over 4096-row tiles (two per CU).
+// Both levels: one 2048-row tile per 512-thread workgroup (36 KB of LDS, four
+// workgroups per CU), so one workgroup's loads overlap another's sort and stores.
 constexpr int64_t kTile1 = 2048;
-constexpr int64_t kTile = 4096;
+constexpr int64_t kTile = 2048;
 constexpr int kMaxBins = 256;
 constexpr int kJBlock = 512;
 constexpr int kJSlotBits = 11;
@@ -67,6 +67,8 @@ struct PartSide {
   uint32_t* hist2;   // [max tiles2][nb2]
   uint32_t* pstart;  // [nb1 * nb2]
   uint32_t* pcount;  // [nb1 * nb2]
+  uint4* tdesc2;     // [max tiles2] second-level tile: {first-level partition, row lo, row hi, 0}
+  int64_t* ntiles2;  // number of second-level tiles
   uint32_t b1, b2;
 };
 
@@ -487,6 +489,13 @@ __global__ __launch_bounds__(kBlk) void k_p2_scan(PartSide s) {
     s.pstart[p * nb2 + threadIdx.x] = mp.start[p] + ex;
     s.pcount[p * nb2 + threadIdx.x] = bin_tot;
   }
+  // the scatter's tile table: this partition's tiles, and (once) their total
+  for (uint32_t k = threadIdx.x; k < nt; k += kBlk) {
+    const uint32_t lo = mp.start[p] + k * (uint32_t)kTile;
+    const uint32_t end = mp.start[p] + mp.cnt[p];
+    s.tdesc2[tb + k] = make_uint4(p, lo, lo + (uint32_t)kTile < end ? lo + (uint32_t)kTile : end, 0u);
+  }
+  if (p == 0 && threadIdx.x == 0) *s.ntiles2 = mp.ntiles;
 }
 
 constexpr int kR2 = (int)(kTile / kSBlk);  // rows per thread at the second level
@@ -517,42 +526,29 @@ __device__ __forceinline__ void load_p2(const PartSide& s, const Tile2& x, bool 
   }
 }
 
-// Persistent over the second-level tiles; two workgroups per CU (LDS).
+// One second-level tile per workgroup, from the tile table; the grid is an
+// upper bound and the surplus workgroups leave at once. Workgroup b takes tile
+// xcd_tile(b, tiles), so each XCD holds a contiguous range of tiles.
 template <bool FACT>
-__global__ __launch_bounds__(kSBlk, 4) void k_p2_scatter(PartSide s) {
+__global__ __launch_bounds__(kSBlk) void k_p2_scatter(PartSide s) {
   __shared__ Stage<FACT, (int)kTile> st;
-  __shared__ L2Map mp;
-  for (uint32_t b = threadIdx.x; b < kMaxBins; b += kSBlk) st.lcnt[b] = 0;
-  build_l2map<kSBlk>(s, mp, st.scr);  // ends with a barrier
-  const uint32_t nb1 = 1u << s.b1, nb2 = 1u << s.b2;
+  const int64_t ntiles = *s.ntiles2;
+  if ((int64_t)blockIdx.x >= ntiles) return;
+  const uint32_t t = xcd_tile(blockIdx.x, (uint32_t)ntiles);
+  const uint4 td = s.tdesc2[t];
+  const uint32_t nb2 = 1u << s.b2;
   const BinOf bin_of{32u - s.b1 - s.b2, nb2 - 1};
   const bool pay = !FACT && s.pkind != relh::PAY_NONE;
-  TileWalk w(mp.ntiles);
-  int64_t t = w.take();
-  TileRows<FACT, false, kR2> cur, nxt;
-  uint32_t gcur = 0, gnxt = 0;  // thread b < nb2: the tile's start in bin b
-  auto gstart = [&](const Tile2& x, int64_t tile) {
-    return threadIdx.x < nb2 ? s.pstart[x.p * nb2 + threadIdx.x] + s.hist2[(size_t)tile * nb2 + threadIdx.x] : 0u;
-  };
-  if (t >= 0) {
-    const Tile2 x = find_tile(mp, nb1, t);
-    load_p2<FACT>(s, x, pay, cur);
-    gcur = gstart(x, t);
-  }
-  while (t >= 0) {
-    if (threadIdx.x < nb2) st.gbase[threadIdx.x] = gcur;
-    const int64_t tn = w.take();
-    if (tn >= 0) {
-      const Tile2 x = find_tile(mp, nb1, tn);
-      load_p2<FACT>(s, x, pay, nxt);
-      gnxt = gstart(x, tn);
-    }
-    stage_and_write<FACT, false, kSBlk, (int)kTile>(st, cur, 0, bin_of, nb2, pay, s.key2, s.price2,
-                                                    FACT ? s.qty2 : s.pay2);
-    cur = nxt;
-    gcur = gnxt;
-    t = tn;
-  }
+  Tile2 x;
+  x.p = td.x;
+  x.lo = td.y;
+  x.hi = td.z;
+  TileRows<FACT, false, kR2> r;
+  load_p2<FACT>(s, x, pay, r);
+  if (threadIdx.x < kMaxBins) st.lcnt[threadIdx.x] = 0;
+  if (threadIdx.x < nb2) st.gbase[threadIdx.x] = s.pstart[x.p * nb2 + threadIdx.x] + s.hist2[(size_t)t * nb2 + threadIdx.x];
+  __syncthreads();
+  stage_and_write<FACT, false, kSBlk, (int)kTile>(st, r, 0, bin_of, nb2, pay, s.key2, s.price2, FACT ? s.qty2 : s.pay2);
 }
 
 // ---- work units -----------------------------------------------------------------------------------------------------------
@@ -1126,8 +1122,10 @@ rel_status partition_side(rel_ctx* ctx, PartSide& s, bool fact, int64_t* passed)
   }
   {
     relh::KernelTimer kt(ctx, fact ? "fact_p2_scatter" : "dim_p2_scatter");
-    if (fact) hipLaunchKernelGGL(k_p2_scatter<true>, dim3(gs), sblk, 0, ctx->stream, s);
-    else hipLaunchKernelGGL(k_p2_scatter<false>, dim3(gs), sblk, 0, ctx->stream, s);
+    // upper bound of second-level tiles: sum over partitions of ceil(c_p / kTile)
+    const dim3 g2((unsigned)(s.n / kTile + nb1));
+    if (fact) hipLaunchKernelGGL(k_p2_scatter<true>, g2, sblk, 0, ctx->stream, s);
+    else hipLaunchKernelGGL(k_p2_scatter<false>, g2, sblk, 0, ctx->stream, s);
   }
   REL_LAUNCH_CHECK(ctx, "partition level 2");
   return REL_OK;
@@ -1182,7 +1180,8 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   TRY(scratch(ctx, SCR_PART_C, (size_t)(m > 0 ? m : 1) * 16 + 4 * 256, &pc));
   const size_t book = ((size_t)fnt1 * nb1 + (size_t)dnt1 * nb1 + (size_t)fnt2 * nb2 + (size_t)dnt2 * nb2 + 2 * nb1 +
                        5 * (size_t)nparts + ((size_t)nparts / kUBlk + 1) * kClasses) * 4 +
-                      (size_t)max_units * (sizeof(uint4) + sizeof(uint2)) + 64 * 256;
+                      (size_t)max_units * (sizeof(uint4) + sizeof(uint2)) + (size_t)(fnt2 + dnt2) * sizeof(uint4) +
+                      64 * 256;
   TRY(scratch(ctx, SCR_PART_D, book, &pd));
   // split-chunk accumulators and their done counters: zero when allocated, and
   // left zero by every call (the last sub-unit of a chunk clears what it emits)
@@ -1215,6 +1214,8 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   F.hist2 = cd.take<uint32_t>((size_t)fnt2 * nb2);
   F.pstart = cd.take<uint32_t>(nparts);
   F.pcount = cd.take<uint32_t>(nparts);
+  F.tdesc2 = cd.take<uint4>((size_t)fnt2);
+  F.ntiles2 = cd.take<int64_t>(1);
 
   PartSide D{};
   D.key = dim->pk;
@@ -1231,6 +1232,8 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   D.hist2 = cd.take<uint32_t>((size_t)dnt2 * nb2);
   D.pstart = cd.take<uint32_t>(nparts);
   D.pcount = cd.take<uint32_t>(nparts);
+  D.tdesc2 = cd.take<uint4>((size_t)dnt2);
+  D.ntiles2 = cd.take<int64_t>(1);
 
   uint4* unit_desc = cd.take<uint4>(max_units);
   uint2* unit_split = cd.take<uint2>(max_units);
