@@ -24,6 +24,11 @@ using namespace rel;
 
 constexpr int kBLdsSlots = 1024;
 constexpr int kBLdsProbe = 32;
+// Instances with more groups than the LDS table holds still use it as a
+// cache in front of their device-memory table: the first keys a workgroup
+// meets stay in LDS (one set of device atomics per key and work item instead
+// of one per row), and a short probe budget bounds the cost for the others.
+constexpr int kBLdsCacheProbe = 4;
 constexpr int64_t kFinItemSlots = 8192;
 constexpr uint32_t kHintProbe = 256;
 
@@ -104,10 +109,10 @@ __global__ __launch_bounds__(BLOCK) void k_batch_probe(const BInst* __restrict__
     if (it >= n_items) break;
     const BItem w = items[it];
     const BInst& I = inst[w.inst];
-    const bool use_lds = I.lds != 0;
+    const int lds_probe = I.lds != 0 ? kBLdsProbe : kBLdsCacheProbe;
     const JoinView jv{I.jslots, I.jmask, I.jshift};
     const GroupView gv{I.gslots, I.gmask, I.gshift, status, I.gprobe};
-    if (use_lds) lds.init(threadIdx.x, BLOCK);
+    lds.init(threadIdx.x, BLOCK);
     __syncthreads();
     uint64_t passed = 0, matched = 0;
     for (int64_t r0 = w.lo + threadIdx.x; r0 < w.hi; r0 += (int64_t)BLOCK * IPT) {
@@ -133,15 +138,13 @@ __global__ __launch_bounds__(BLOCK) void k_batch_probe(const BInst* __restrict__
         ++matched;
         const int64_t key = batch_key(I, pl, f[k], fl[k]);
         const uint64_t sp = (uint64_t)p[k], sq = (uint64_t)(int64_t)q[k];
-        const int s = (use_lds && key != kGroupEmpty) ? lds.find(key, kBLdsProbe) : -1;
+        const int s = key != kGroupEmpty ? lds.find(key, lds_probe) : -1;
         if (s >= 0) lds.add(s, sp, sq, 1ull);
         else group_add(gv, key, sp, sq, 1ull);
       }
     }
-    if (use_lds) {
-      __syncthreads();
-      lds.flush(gv, threadIdx.x, BLOCK);
-    }
+    __syncthreads();
+    lds.flush(gv, threadIdx.x, BLOCK);
     passed = wave_sum(passed);
     matched = wave_sum(matched);
     if (lane_id() == 0) {
