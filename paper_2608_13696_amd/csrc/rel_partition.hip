@@ -26,9 +26,11 @@ using namespace rel;
 
 constexpr int kBlk = 256;         // histogram and scan kernels
 constexpr int kSBlk = 512;        // scatter kernels
-// Both levels: one 2048-row tile per 512-thread workgroup (36 KB of LDS, four
-// workgroups per CU), so one workgroup's loads overlap another's sort and stores.
-constexpr int64_t kTile1 = 2048;
+// One tile per 512-thread workgroup at both levels, so one workgroup's loads
+// overlap another's sort and stores: 4096-row tiles at the first level (68 KB
+// of LDS, two workgroups per CU; longer runs per partition, so fewer partly
+// written lines), 2048-row tiles at the second (36 KB, four per CU).
+constexpr int64_t kTile1 = 4096;
 constexpr int64_t kTile = 2048;
 constexpr int kMaxBins = 256;
 constexpr int kJBlock = 512;
@@ -318,8 +320,7 @@ __device__ __forceinline__ void load_p1_row(const PartSide& s, int64_t q, int k,
   }
 }
 
-// One first-level tile per workgroup (tiles of one XCD contiguous, xcd_tile);
-// four workgroups per CU, so one's loads overlap another's sort and stores.
+// One first-level tile per workgroup (tiles of one XCD contiguous, xcd_tile).
 template <bool FACT>
 __global__ __launch_bounds__(kSBlk) void k_p1_scatter(PartSide s) {
   __shared__ Stage<FACT, (int)kTile1> st;
