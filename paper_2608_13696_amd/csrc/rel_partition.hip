@@ -850,9 +850,8 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
   // held up by a long unit takes fewer). Thread 0 runs two units ahead: at the
   // start of a unit it asks for the ticket after next and reads the next
   // unit's descriptor (its ticket arrived during the previous unit), so
-  // neither round trip delays the unit. After the probe every thread issues
-  // the next unit's dim-key and first fact-row loads, which travel during this
-  // unit's emission.
+  // neither round trip delays the unit. Every thread then issues the next
+  // unit's dim-key and first fact-row loads as early as its registers allow.
   int64_t t_ahead = 0;  // thread 0: ticket of the next unit
   if (tid == 0) {
     const int64_t t = take_ticket(a);
@@ -879,11 +878,13 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
     uint4 nd = make_uint4(0, 0, 0, 0);
     uint2 ns = make_uint2(0, 0);
     if (tid == 0) {
-      t_req = take_ticket(a);
+      // the descriptor loads go out before the ticket atomic, so waiting for
+      // them (before the build's barrier) never waits for the atomic as well
       if (t_ahead < n_units) {
         nd = a.unit_desc[t_ahead];
         ns = a.unit_split[t_ahead];
       }
+      t_req = take_ticket(a);
     }
     for (int s = tid; s < kJSlots; s += kJBlock) {
       tkey[s] = kLdsEmpty;
@@ -913,10 +914,26 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
         h = (h + 1) & (kJSlots - 1);
       }
     }
+    if (tid == 0) {  // the next unit, read by everyone after the barrier
+      s_u = t_ahead;
+      s_desc = nd;
+      s_split = ns;
+    }
     __syncthreads();
+    const int64_t un = s_u;
+    const uint4 dn = s_desc;
+    const uint2 sn = s_split;
+    int32_t ndkeys[kJDK];
+    // past the last unit the loads read the current unit again (discarded)
+    const uint4 pd = un < n_units ? dn : d;
     // probe and aggregate in LDS; long units stream further steps through nxt
     const uint32_t nrows = fhi - flo;
     const uint32_t iters = (nrows + kJR * kJBlock - 1) / (kJR * kJBlock);  // uniform over the workgroup
+    // A unit of one step leaves nxt free: the next unit's loads go out now and
+    // travel during this unit's probe and emission. Longer units issue them
+    // after the probe.
+    const bool early = iters <= 1;
+    if (early) prefetch_unit(a, pd, ndkeys, nxt);
     for (uint32_t it = 0; it < iters; ++it) {
       const uint32_t i0 = flo + it * (kJR * kJBlock) + tid;
       if (it > 0) cur = nxt;
@@ -974,19 +991,7 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
         }
       }
     }
-    if (tid == 0) {
-      s_u = t_ahead;
-      s_desc = nd;
-      s_split = ns;
-      t_ahead = t_req;
-    }
     __syncthreads();
-    const int64_t un = s_u;
-    const uint4 dn = s_desc;
-    const uint2 sn = s_split;
-    int32_t ndkeys[kJDK];
-    // past the last unit the loads read the current unit again (discarded)
-    const uint4 pd = un < n_units ? dn : d;
     if (sp.x == 0) {
       // Whole unit: emit its groups. Output room is reserved with one atomic
       // per unit, taken when the unit finishes, so no unit waits on another.
@@ -1014,7 +1019,7 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
       }
       int64_t resv = 0;
       if (tid == 0 && total) resv = reserve_nowait(a, total);
-      prefetch_unit(a, pd, ndkeys, nxt);
+      if (!early) prefetch_unit(a, pd, ndkeys, nxt);
       if (tid == 0) s_excl = (uint64_t)resv;
       __syncthreads();
       const int64_t o0 = (int64_t)s_excl;
@@ -1027,7 +1032,7 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
     } else {
       // Sub-unit of a split chunk: add the partial sums into the chunk's
       // accumulator; the last sub-unit to finish emits and clears it.
-      prefetch_unit(a, pd, ndkeys, nxt);
+      if (!early) prefetch_unit(a, pd, ndkeys, nxt);
       SplitAcc* acc = a.split_acc + (size_t)(sp.x - 1) * kJChunk;
 #pragma unroll
       for (int k = 0; k < kJPer; ++k) {
@@ -1070,6 +1075,7 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
       }
     }
     __syncthreads();  // the table, s_excl and s_last are reused by the next unit
+    t_ahead = t_req;  // (thread 0) the atomic has had the whole unit to return
     u = un;
     d = dn;
     sp = sn;
