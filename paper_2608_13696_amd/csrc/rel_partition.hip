@@ -26,12 +26,12 @@ using namespace rel;
 
 constexpr int kBlk = 256;         // histogram and scan kernels
 constexpr int kSBlk = 512;        // scatter kernels
-// One tile per 512-thread workgroup at both levels, so one workgroup's loads
-// overlap another's sort and stores: 4096-row tiles at the first level (68 KB
-// of LDS, two workgroups per CU; longer runs per partition, so fewer partly
-// written lines), 2048-row tiles at the second (36 KB, four per CU).
+// One 4096-row tile per 512-thread workgroup at both levels (68 KB of LDS, two
+// workgroups per CU), so one workgroup's loads overlap another's sort and
+// stores; tiles this long leave runs per partition long enough that few cache
+// lines are written partly.
 constexpr int64_t kTile1 = 4096;
-constexpr int64_t kTile = 2048;
+constexpr int64_t kTile = 4096;
 constexpr int kMaxBins = 256;
 constexpr int kJBlock = 512;
 constexpr int kJSlotBits = 11;
