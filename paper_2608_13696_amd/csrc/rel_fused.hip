@@ -343,9 +343,12 @@ rel_status launch_fused(rel_ctx* ctx, int gp, const FusedArgs& a, unsigned grid)
     if (s_ != REL_OK) return s_;    \
   } while (0)
 
-// GROUP BY fk inputs at least this large take the radix-partitioned path
-// unless a plan says otherwise.
+// Fact tables at least this large take the radix-partitioned path unless a
+// plan says otherwise ...
 constexpr int64_t kPartitionMinRows = 1 << 20;
+// ... and, grouping by a dim attribute, at least this many dim rows (a plain
+// join table of 2^19 slots or more no longer fits one XCD's L2).
+constexpr int64_t kPartitionMinDim = 1 << 18;
 
 rel_status sync_stats(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, const rel_query* q, const rel_plan* plan,
                       rel_groups_out* out, rel_stats* stats, int64_t* cnt, int64_t join_cap, int64_t group_cap,
@@ -404,23 +407,28 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
   int64_t* cnt = relh::counters(ctx);
   const bool planned = plan && plan->group_capacity > 0;
 
-  // Radix-partitioned groupjoin: asked for, or chosen for large GROUP BY fk inputs.
+  // Radix partitioning of both sides: asked for, or chosen for large inputs
+  // (for a dim-attribute group key only when the dim side is large enough that
+  // its join table would not stay in L2).
   const int jp = plan ? plan->join_placement : REL_PLACE_AUTO;
-  if (jp == REL_PLACE_PARTITIONED && gb != REL_GROUP_FK)
-    return relh::fail(ctx, REL_UNSUPPORTED, "rel_filter_join_agg: the partitioned path groups by fk only");
-  if (gb == REL_GROUP_FK && (jp == REL_PLACE_PARTITIONED || (jp == REL_PLACE_AUTO && n >= kPartitionMinRows))) {
+  const bool part = jp == REL_PLACE_PARTITIONED ||
+                    (jp == REL_PLACE_AUTO && n >= kPartitionMinRows && (gb == REL_GROUP_FK || m >= kPartitionMinDim));
+  if (part && gb == REL_GROUP_FK) {
     TRY(relh::fill_u64(ctx, cnt, 2, 0));
     TRY(relh::partitioned_groupjoin(ctx, fact, dim, q->day_lt, out, cnt));
     return sync_stats(ctx, fact, dim, q, plan, out, stats, cnt, m, m, REL_PLACE_PARTITIONED, REL_PLACE_PARTITIONED);
   }
 
   // Join table: plain sizing (2m rounded up to a power of two), in device memory.
-  const uint32_t jl = relh::join_log2cap(m, nullptr);
-  void* jt;
-  TRY(relh::scratch(ctx, SCR_JOIN_TABLE, ((size_t)8 << jl) + 8, &jt));
-  const void* payload = gb == REL_GROUP_PRIO_FLAG ? (const void*)dim->prio : gb == REL_GROUP_DIM_GRP ? (const void*)dim->grp : nullptr;
-  const int pkind = gb == REL_GROUP_PRIO_FLAG ? relh::PAY_I8 : gb == REL_GROUP_DIM_GRP ? relh::PAY_I32 : relh::PAY_ROW_ID;
-  TRY(relh::join_build_into(ctx, dim->pk, payload, pkind, m, (uint64_t*)jt, jl));
+  uint32_t jl = 0;
+  void* jt = nullptr;
+  if (!part) {
+    jl = relh::join_log2cap(m, nullptr);
+    TRY(relh::scratch(ctx, SCR_JOIN_TABLE, ((size_t)8 << jl) + 8, &jt));
+    const void* payload = gb == REL_GROUP_PRIO_FLAG ? (const void*)dim->prio : gb == REL_GROUP_DIM_GRP ? (const void*)dim->grp : nullptr;
+    const int pkind = gb == REL_GROUP_PRIO_FLAG ? relh::PAY_I8 : gb == REL_GROUP_DIM_GRP ? relh::PAY_I32 : relh::PAY_ROW_ID;
+    TRY(relh::join_build_into(ctx, dim->pk, payload, pkind, m, (uint64_t*)jt, jl));
+  }
   TRY(relh::fill_u64(ctx, cnt, 2, 0));
 
   FusedArgs a{};
@@ -436,6 +444,7 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
 
   int gp;
   int64_t group_cap = 0;
+  uint32_t gl = 0;
   void* gt = nullptr;
   if (gb == REL_GROUP_FK) {
     gp = G_ROWAGG;  // group key == join key: per-dim-row accumulators
@@ -458,13 +467,22 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
     // which under skew are the hot ones); a short probe budget bounds the cost
     // of rows whose key is not cached.
     a.lds_probe = expected <= relh::kLdsGroupCap ? kLdsProbe : kLdsCacheProbe;
-    const uint32_t gl = group_log2cap(expected, 0.5);
+    gl = group_log2cap(expected, 0.5);
     if (gl > 31) return relh::fail(ctx, REL_UNSUPPORTED, "rel_filter_join_agg: group table above 2^31 slots");
     group_cap = 1ll << gl;
     TRY(relh::scratch(ctx, SCR_GROUP_TABLE, (size_t)(group_cap + 1) * sizeof(GroupSlot), &gt));
     TRY(init_groups(ctx, (GroupSlot*)gt, group_cap + 1));
     a.groups = GroupView{(GroupSlot*)gt, (uint32_t)(group_cap - 1), 32u - gl, ctx->d_status,
                          planned ? kPlannedProbe : (uint32_t)group_cap};
+  }
+
+  if (part) {
+    // the same group table behind a per-workgroup LDS table (probe budget 0: none)
+    TRY(relh::partitioned_join_agg(ctx, fact, dim, q->day_lt, gb, gt, gl, a.groups.max_probe,
+                                   gp == G_LDS ? a.lds_probe : 0, cnt));
+    TRY(finalize(ctx, SlotSource{(const GroupSlot*)gt, group_cap}, group_cap + 1, out_args(ctx, out)));
+    return sync_stats(ctx, fact, dim, q, plan, out, stats, cnt, m, group_cap, REL_PLACE_PARTITIONED,
+                      gp == G_LDS ? REL_PLACE_LDS : REL_PLACE_GLOBAL);
   }
 
   if (n > 0) {

@@ -24,5 +24,13 @@ uint32_t join_log2cap(int64_t m, const rel_table_opts* opts);
 // counters[CNT_JOIN_MATCHES]; writes groups and *d_n_groups.
 rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, int32_t day_lt,
                                  rel_groups_out* out, int64_t* counters);
+// GROUP BY (dim.prio, fact.flag) or dim.grp over the same partitioned join:
+// aggregates into the device-memory group table group_slots (2^group_log2cap
+// slots plus the side slot, initialised by the caller; probe walks bounded by
+// max_probe) through per-workgroup LDS tables (probe budget lds_probe). Adds
+// to the same two counters.
+rel_status partitioned_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, int32_t day_lt, int group_by,
+                                void* group_slots, uint32_t group_log2cap, uint32_t max_probe, int32_t lds_probe,
+                                int64_t* counters);
 
 }  // namespace relh

@@ -49,6 +49,7 @@ struct PartSide {
   const int32_t* day;      // fact only
   const int64_t* price;    // fact only
   const int32_t* qty;      // fact only
+  const int8_t* flag;      // fact only, and only when the group key needs it (else null)
   const void* payload;     // dim only (PayloadKind)
   int pkind;
   int32_t day_lt;
@@ -57,11 +58,13 @@ struct PartSide {
   int32_t* key1;
   int64_t* price1;
   int32_t* qty1;
+  int8_t* flag1;
   int32_t* pay1;
   // second-level outputs
   int32_t* key2;
   int64_t* price2;
   int32_t* qty2;
+  int8_t* flag2;
   int32_t* pay2;
   // bookkeeping
   uint32_t* hist1;   // [ntiles1][nb1]
@@ -97,6 +100,57 @@ struct TileWalk {
     return t;
   }
 };
+
+// ---- skew-tolerant LDS counters ------------------------------------------------------------------------------------
+//
+// Under key skew most of a wave's rows can fall in one bin, and atomics of
+// many lanes on one LDS address execute one after another. The lanes that
+// share the first active lane's bin are therefore served by one atomic when
+// there are enough of them; the others use their own.
+constexpr int kBinCombineMin = 4;
+
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t v, int lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+// ctr[bin] += 1 for every active lane. Every lane of the wave must call it.
+__device__ __forceinline__ void lds_count(uint32_t* ctr, uint32_t bin, bool active) {
+  const uint64_t act = wave_ballot(active);
+  if (act == 0) return;
+  const int leader = __ffsll((long long)act) - 1;
+  const uint32_t b0 = readlane_u32(bin, leader);
+  const bool mine = active && bin == b0;
+  const uint64_t same = wave_ballot(mine);
+  const int c = __popcll(same);
+  if (c >= kBinCombineMin) {
+    if ((int)lane_id() == leader) atomicAdd(&ctr[b0], (uint32_t)c);
+    active = active && !mine;
+  }
+  if (active) atomicAdd(&ctr[bin], 1u);
+}
+
+// The same, returning each lane's rank in its bin (the counter's value before
+// the lane's own increment; lanes combined by one atomic rank in lane order).
+__device__ __forceinline__ uint32_t lds_rank(uint32_t* ctr, uint32_t bin, bool active) {
+  const uint64_t act = wave_ballot(active);
+  if (act == 0) return 0;
+  const int leader = __ffsll((long long)act) - 1;
+  const uint32_t b0 = readlane_u32(bin, leader);
+  const bool mine = active && bin == b0;
+  const uint64_t same = wave_ballot(mine);
+  const int c = __popcll(same);
+  uint32_t rank = 0;
+  if (c >= kBinCombineMin) {
+    uint32_t base = 0;
+    if ((int)lane_id() == leader) base = atomicAdd(&ctr[b0], (uint32_t)c);
+    if (active && !mine) rank = atomicAdd(&ctr[bin], 1u);
+    base = readlane_u32(base, leader);
+    if (mine) rank = base + mask_rank(same);
+  } else if (active) {
+    rank = atomicAdd(&ctr[bin], 1u);
+  }
+  return rank;
+}
 
 // ---- first level -------------------------------------------------------------------------------------------------------
 
@@ -143,11 +197,13 @@ __global__ __launch_bounds__(kBlk) void k_p1_hist(PartSide s) {
 }
 
 // Column b of hist1 (one bin over all tiles) -> exclusive prefix in place;
-// tot1[b] = column sum. The column goes through LDS in chunks so that global
+// tot1[b] = column sum; also clears bin b's second-level counters. The column goes through LDS in chunks so that global
 // reads and writes are coalesced while each thread scans a contiguous run.
 constexpr int kColPer = 16;
 __global__ __launch_bounds__(kBlk) void k_p1_colscan(uint32_t* __restrict__ hist1, int64_t ntiles, uint32_t nb1,
-                                                     uint32_t* __restrict__ tot1, int64_t* __restrict__ passed) {
+                                                     uint32_t* __restrict__ tot1, int64_t* __restrict__ passed,
+                                                     uint32_t* __restrict__ pcount, uint32_t nb2) {
+  for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) pcount[blockIdx.x * nb2 + b] = 0;  // for k_p2_hist
   __shared__ uint32_t buf[kBlk * kColPer];
   __shared__ uint32_t scr[kBlk / kWave];
   uint32_t* col = hist1 + (size_t)blockIdx.x * ntiles;
@@ -206,6 +262,7 @@ struct Stage {
   uint32_t scr[kSBlk / kWave];
   int2 kv[TILE];             // {key, qty (fact) or payload (dim)}
   int64_t price[FACT ? TILE : 1];
+  int8_t flag[FACT ? TILE : 1];  // fact flag (when carried)
 };
 
 // The rows one thread holds for one tile. valid: bit k set when row k is in
@@ -218,6 +275,7 @@ struct TileRows {
   int32_t val[R];
   int64_t price[FACT ? R : 1];
   int32_t day[DAY ? R : 1];
+  uint32_t flags[FACT ? (R + 3) / 4 : 1];  // fact flag bytes, four per word (when carried)
   uint32_t valid;
 };
 
@@ -237,7 +295,7 @@ struct BinOf {
 template <bool FACT, bool DAY, int NT, int TILE>
 __device__ __forceinline__ void stage_and_write(Stage<FACT, TILE>& st, TileRows<FACT, DAY, TILE / NT>& r, int32_t day_lt,
                                                 BinOf bin_of, uint32_t nb, bool with_val, int32_t* dkey,
-                                                int64_t* dprice, int32_t* dval) {
+                                                int64_t* dprice, int32_t* dval, int8_t* dflag) {
   constexpr int R = TILE / NT;
   if (DAY) {
 #pragma unroll
@@ -246,7 +304,7 @@ __device__ __forceinline__ void stage_and_write(Stage<FACT, TILE>& st, TileRows<
   }
   uint32_t rank[R];
 #pragma unroll
-  for (int k = 0; k < R; ++k) rank[k] = (r.valid >> k) & 1u ? atomicAdd(&st.lcnt[bin_of(r.key[k])], 1u) : 0u;
+  for (int k = 0; k < R; ++k) rank[k] = lds_rank(st.lcnt, bin_of(r.key[k]), (r.valid >> k) & 1u);
   __syncthreads();
   if (threadIdx.x < kWave) {
     // wave 0: exclusive scan of the counts, four bins per lane (nb <= 256)
@@ -285,6 +343,7 @@ __device__ __forceinline__ void stage_and_write(Stage<FACT, TILE>& st, TileRows<
     const uint32_t slot = st.lbase[bin_of(r.key[k])] + rank[k];
     st.kv[slot] = make_int2(r.key[k], r.val[k]);
     if (FACT) st.price[slot] = r.price[k];
+    if (FACT && dflag) st.flag[slot] = (int8_t)(r.flags[k / 4] >> (8 * (k % 4)));
   }
   __syncthreads();
   const uint32_t total = st.total;
@@ -295,6 +354,7 @@ __device__ __forceinline__ void stage_and_write(Stage<FACT, TILE>& st, TileRows<
     if (FACT) {
       dprice[pos] = st.price[j];
       dval[pos] = kv.y;
+      if (dflag) dflag[pos] = st.flag[j];
     } else if (with_val) {
       dval[pos] = kv.y;
     }
@@ -312,6 +372,7 @@ __device__ __forceinline__ void load_p1_row(const PartSide& s, int64_t q, int k,
     r.val[k] = s.qty[q];
     r.price[k] = s.price[q];
     r.day[k] = s.day[q];
+    if (s.flag) r.flags[k / 4] |= (uint32_t)(uint8_t)s.flag[q] << (8 * (k % 4));
   } else {
     r.val[k] = s.pkind == relh::PAY_ROW_ID ? (int32_t)q
              : s.pkind == relh::PAY_I32    ? ((const int32_t*)s.payload)[q]
@@ -329,6 +390,9 @@ __global__ __launch_bounds__(kSBlk) void k_p1_scatter(PartSide s) {
   const int64_t ntiles = gridDim.x;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   TileRows<FACT, FACT, kR1> r;
+  if (FACT)
+#pragma unroll
+    for (int w = 0; w < (kR1 + 3) / 4; ++w) r.flags[w] = 0;
   const int64_t r0 = (int64_t)tile * kTile1 + threadIdx.x;
   if ((int64_t)tile * kTile1 + kTile1 <= s.n) {  // full tile: unconditional loads, issued back to back
 #pragma unroll
@@ -360,7 +424,7 @@ __global__ __launch_bounds__(kSBlk) void k_p1_scatter(PartSide s) {
   if (threadIdx.x < nb1) st.gbase[threadIdx.x] = pbase + h;
   __syncthreads();
   stage_and_write<FACT, FACT, kSBlk, (int)kTile1>(st, r, s.day_lt, bin_of, nb1, s.pkind != relh::PAY_NONE, s.key1,
-                                                  s.price1, FACT ? s.qty1 : s.pay1);
+                                                  s.price1, FACT ? s.qty1 : s.pay1, FACT ? s.flag1 : nullptr);
 }
 
 // ---- second level ------------------------------------------------------------------------------------------------------
@@ -416,7 +480,17 @@ __device__ __forceinline__ Tile2 find_tile(const L2Map& mp, uint32_t nb1, int64_
 }
 
 // Per second-level tile: histogram of the next b2 hash bits. Persistent.
+//
+// A tile's start inside each bin's run of its partition is the prefix of the
+// counts of the partition's earlier tiles (k_p2_scan). That keeps the runs of
+// neighbouring tiles, which neighbouring workgroups of one XCD scatter at the
+// same time, adjacent in memory, so the cache lines they share are completed
+// in that XCD's L2. A scan over a partition's tiles is sequential, though: for
+// a partition of more than kScanTilesMax tiles (key skew) the tiles instead
+// take their starts with device atomics on the bin counters (pcount, zeroed
+// by k_p1_colscan) in the order they get there.
 constexpr int kHR = (int)(kTile / kBlk);
+constexpr uint32_t kScanTilesMax = 128;
 __global__ __launch_bounds__(kBlk) void k_p2_hist(PartSide s) {
   __shared__ L2Map mp;
   __shared__ uint32_t scr[kBlk / kWave];
@@ -448,10 +522,18 @@ __global__ __launch_bounds__(kBlk) void k_p2_hist(PartSide s) {
     for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) h[b] = 0;
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kHR; ++k)
-      if (tc.lo + threadIdx.x + (int64_t)k * kBlk < tc.hi) atomicAdd(&h[bin_of(cur[k])], 1u);
+    for (int k = 0; k < kHR; ++k) lds_count(h, bin_of(cur[k]), tc.lo + threadIdx.x + (int64_t)k * kBlk < tc.hi);
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) s.hist2[(size_t)t * nb2 + b] = h[b];
+    if ((mp.cnt[tc.p] + kTile - 1) / kTile > kScanTilesMax) {
+      // a long partition: the tile's start inside each bin's run, taken in the
+      // order the counts arrive (rows of a partition need no particular order)
+      for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) {
+        const uint32_t c = h[b];
+        s.hist2[(size_t)t * nb2 + b] = c ? dev_add_ret<uint32_t>(&s.pcount[tc.p * nb2 + b], c) : 0u;
+      }
+    } else {
+      for (uint32_t b = threadIdx.x; b < nb2; b += kBlk) s.hist2[(size_t)t * nb2 + b] = h[b];
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kHR; ++k) cur[k] = nxt[k];
@@ -461,7 +543,8 @@ __global__ __launch_bounds__(kBlk) void k_p2_hist(PartSide s) {
 }
 
 // One workgroup per first-level partition p: per second-level bin, prefix over
-// p's tiles (in place) and the final partition starts/counts.
+// p's tiles (in place; unless k_p2_hist placed them) and the partition
+// starts and counts; then p's entries of the tile table.
 constexpr int kScanBatch = 8;
 __global__ __launch_bounds__(kBlk) void k_p2_scan(PartSide s) {
   __shared__ L2Map mp;
@@ -472,15 +555,19 @@ __global__ __launch_bounds__(kBlk) void k_p2_scan(PartSide s) {
   const uint32_t tb = mp.tbase[p], nt = (uint32_t)((mp.cnt[p] + kTile - 1) / kTile);
   uint32_t bin_tot = 0;
   if (threadIdx.x < nb2) {
-    for (uint32_t k0 = 0; k0 < nt; k0 += kScanBatch) {
-      uint32_t v[kScanBatch];
+    if (nt > kScanTilesMax) {
+      bin_tot = s.pcount[p * nb2 + threadIdx.x];
+    } else {
+      for (uint32_t k0 = 0; k0 < nt; k0 += kScanBatch) {
+        uint32_t v[kScanBatch];
 #pragma unroll
-      for (int k = 0; k < kScanBatch; ++k)
-        v[k] = k0 + k < nt ? s.hist2[(size_t)(tb + k0 + k) * nb2 + threadIdx.x] : 0u;
+        for (int k = 0; k < kScanBatch; ++k)
+          v[k] = k0 + k < nt ? s.hist2[(size_t)(tb + k0 + k) * nb2 + threadIdx.x] : 0u;
 #pragma unroll
-      for (int k = 0; k < kScanBatch; ++k) {
-        if (k0 + k < nt) s.hist2[(size_t)(tb + k0 + k) * nb2 + threadIdx.x] = bin_tot;
-        bin_tot += v[k];
+        for (int k = 0; k < kScanBatch; ++k) {
+          if (k0 + k < nt) s.hist2[(size_t)(tb + k0 + k) * nb2 + threadIdx.x] = bin_tot;
+          bin_tot += v[k];
+        }
       }
     }
   }
@@ -504,6 +591,9 @@ constexpr int kR2 = (int)(kTile / kSBlk);  // rows per thread at the second leve
 template <bool FACT>
 __device__ __forceinline__ void load_p2(const PartSide& s, const Tile2& x, bool pay, TileRows<FACT, false, kR2>& r) {
   const int64_t r0 = x.lo + threadIdx.x;
+  if (FACT)
+#pragma unroll
+    for (int w = 0; w < (kR2 + 3) / 4; ++w) r.flags[w] = 0;
   if (x.lo + kTile <= x.hi) {  // full tile: unconditional loads, issued back to back
 #pragma unroll
     for (int k = 0; k < kR2; ++k) {
@@ -511,6 +601,7 @@ __device__ __forceinline__ void load_p2(const PartSide& s, const Tile2& x, bool 
       r.key[k] = s.key1[q];
       if (FACT) r.price[k] = s.price1[q];
       r.val[k] = FACT ? s.qty1[q] : pay ? s.pay1[q] : 0;
+      if (FACT && s.flag1) r.flags[k / 4] |= (uint32_t)(uint8_t)s.flag1[q] << (8 * (k % 4));
     }
     r.valid = (1u << kR2) - 1;
   } else {
@@ -522,6 +613,7 @@ __device__ __forceinline__ void load_p2(const PartSide& s, const Tile2& x, bool 
       r.key[k] = in ? s.key1[q] : 0;
       if (FACT) r.price[k] = in ? s.price1[q] : 0;
       r.val[k] = !in ? 0 : FACT ? s.qty1[q] : pay ? s.pay1[q] : 0;
+      if (FACT && s.flag1 && in) r.flags[k / 4] |= (uint32_t)(uint8_t)s.flag1[q] << (8 * (k % 4));
       r.valid |= (uint32_t)in << k;
     }
   }
@@ -549,7 +641,8 @@ __global__ __launch_bounds__(kSBlk) void k_p2_scatter(PartSide s) {
   if (threadIdx.x < kMaxBins) st.lcnt[threadIdx.x] = 0;
   if (threadIdx.x < nb2) st.gbase[threadIdx.x] = s.pstart[x.p * nb2 + threadIdx.x] + s.hist2[(size_t)t * nb2 + threadIdx.x];
   __syncthreads();
-  stage_and_write<FACT, false, kSBlk, (int)kTile>(st, r, 0, bin_of, nb2, pay, s.key2, s.price2, FACT ? s.qty2 : s.pay2);
+  stage_and_write<FACT, false, kSBlk, (int)kTile>(st, r, 0, bin_of, nb2, pay, s.key2, s.price2, FACT ? s.qty2 : s.pay2,
+                                                  FACT ? s.flag2 : nullptr);
 }
 
 // ---- work units -----------------------------------------------------------------------------------------------------------
@@ -698,21 +791,26 @@ __global__ __launch_bounds__(kUBlk) void k_unit_emit(UnitArgs a) {
   const uint32_t chunks = (dc + kJChunk - 1) / kJChunk;
   const uint32_t nsub = splitp ? (fc + kSubRows - 1) / kSubRows : 1u;
   const uint32_t cls = size_class(splitp ? kSubRows : fc);
-  uint32_t pos = wave_grouped_add(cur, cls, live ? chunks * nsub : 0u, live);
-  if (!live) return;
-  if (splitp) {
-    for (uint32_t j = 0; j < nsub; ++j, ++pos) {
-      const uint32_t flo = fs + j * kSubRows;
-      const uint32_t fhi = flo + kSubRows < fs + fc ? flo + kSubRows : fs + fc;
-      a.desc[pos] = make_uint4(ds, ds + dc, flo, fhi);
-      a.split[pos] = make_uint2(sb + 1, nsub);
+  const uint32_t pos = wave_grouped_add(cur, cls, live ? chunks * nsub : 0u, live);
+  // A split partition can have hundreds of sub-units: the wave writes each
+  // such partition's list together.
+  const uint32_t lane = lane_id();
+  for (uint64_t todo = wave_ballot(live && splitp); todo != 0; todo &= todo - 1) {
+    const int l = __ffsll((long long)todo) - 1;
+    const uint32_t lfs = readlane_u32(fs, l), lend = lfs + readlane_u32(fc, l);
+    const uint32_t lds = readlane_u32(ds, l), lde = lds + readlane_u32(dc, l);
+    const uint32_t lpos = readlane_u32(pos, l), lns = readlane_u32(nsub, l), lsb = readlane_u32(sb, l);
+    for (uint32_t j = lane; j < lns; j += kWave) {
+      const uint32_t flo = lfs + j * kSubRows;
+      a.desc[lpos + j] = make_uint4(lds, lde, flo, flo + kSubRows < lend ? flo + kSubRows : lend);
+      a.split[lpos + j] = make_uint2(lsb + 1, lns);
     }
-  } else {
-    for (uint32_t c = 0; c < chunks; ++c, ++pos) {
-      const uint32_t dlo = ds + c * kJChunk;
-      a.desc[pos] = make_uint4(dlo, dlo + kJChunk < ds + dc ? dlo + kJChunk : ds + dc, fs, fs + fc);
-      a.split[pos] = make_uint2(0, 1);
-    }
+  }
+  if (!live || splitp) return;
+  for (uint32_t c = 0; c < chunks; ++c) {
+    const uint32_t dlo = ds + c * kJChunk;
+    a.desc[pos + c] = make_uint4(dlo, dlo + kJChunk < ds + dc ? dlo + kJChunk : ds + dc, fs, fs + fc);
+    a.split[pos + c] = make_uint2(0, 1);
   }
 }
 
@@ -1087,6 +1185,230 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
   if (lane == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
 }
 
+// ---- partitioned join + aggregate ------------------------------------------------------------------------------------
+//
+// GROUP BY a dim attribute: each unit's dim keys go into an LDS join table
+// with their payload (dim.grp, or dim.prio), its fact rows probe it, and the
+// matches aggregate into an LDS group table that lives for the whole kernel
+// (units of one workgroup share it) and is flushed into the device-memory
+// table at the end. A key the LDS table cannot place within its probe budget
+// goes to the device-memory table directly. Units need no merging: a fact row
+// matches at most one dim key, hence one unit.
+
+constexpr int kAggSlots = 1024;
+
+struct AggArgs {
+  const uint4* unit_desc;
+  const int64_t* n_units;
+  const int32_t* dkey;
+  const int32_t* dpay;
+  const int32_t* fkey;
+  const int64_t* fprice;
+  const int32_t* fqty;
+  const int8_t* fflag;  // (prio, flag) grouping only
+  int64_t* ticket;
+  int64_t* matched;
+  uint32_t* status;
+  GroupView groups;
+  int32_t lds_probe;
+  uint32_t zero;  // 0 at run time; see take_ticket
+};
+
+__device__ __forceinline__ int64_t take_ticket(const AggArgs& a) {
+  unsigned long long* t = (unsigned long long*)a.ticket + threadIdx.x * a.zero;
+  return (int64_t)__hip_atomic_fetch_add(t, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool FL>
+struct AggRows {
+  int32_t key[kJR];
+  int32_t qty[kJR];
+  uint64_t sp[kJR];
+  uint32_t fl;  // the rows' flag bytes (FL only)
+};
+
+// Fact rows i0 + k * kJBlock of a unit, indices clamped into its (never
+// empty) range so that the number of loads is fixed; the probe skips the
+// copies past the range.
+template <bool FL>
+__device__ __forceinline__ void load_agg_rows(const AggArgs& a, uint32_t i0, uint32_t fhi, AggRows<FL>& r) {
+  r.fl = 0;
+#pragma unroll
+  for (int k = 0; k < kJR; ++k) {
+    uint32_t i = i0 + k * kJBlock;
+    i = i < fhi ? i : fhi - 1;
+    r.key[k] = a.fkey[i];
+    r.sp[k] = (uint64_t)a.fprice[i];
+    r.qty[k] = a.fqty[i];
+    if constexpr (FL) r.fl |= (uint32_t)(uint8_t)a.fflag[i] << (8 * k);
+  }
+}
+
+__device__ __forceinline__ void load_agg_dim(const AggArgs& a, uint4 u, int32_t (&dk)[kJDK], int32_t (&dp)[kJDK]) {
+#pragma unroll
+  for (int k = 0; k < kJDK; ++k) {
+    uint32_t j = u.x + threadIdx.x + k * kJBlock;
+    j = j < u.y ? j : u.y - 1;
+    dk[k] = a.dkey[j];
+    dp[k] = a.dpay[j];
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ int64_t agg_group_key(int32_t pay, uint32_t fl, int k) {
+  if (MODE == REL_GROUP_PRIO_FLAG) return (int64_t)pay * 256 + (int64_t)((fl >> (8 * k)) & 0xffu);
+  return (int64_t)pay;
+}
+
+// Two workgroups per CU (56 KB of LDS each).
+template <int MODE>
+__global__ __launch_bounds__(kJBlock, 4) void k_part_join_agg(AggArgs a) {
+  constexpr bool FL = MODE == REL_GROUP_PRIO_FLAG;
+  __shared__ uint64_t tkey[kJSlots];  // {key, 1} packed; all ones = empty
+  __shared__ int32_t tpay[kJSlots];
+  __shared__ LdsGroups<kAggSlots> grp;
+  __shared__ uint4 s_desc;
+  __shared__ int64_t s_u;
+  const int64_t n_units = *a.n_units;
+  const uint32_t tid = threadIdx.x, lane = lane_id();
+  uint64_t matched = 0;
+  grp.init(tid, kJBlock);
+  // units by ticket from the largest-first list, thread 0 two tickets ahead
+  // (as in k_part_groupjoin)
+  int64_t t_ahead = 0;
+  if (tid == 0) {
+    const int64_t t = take_ticket(a);
+    t_ahead = take_ticket(a);
+    s_u = t;
+    if (t < n_units) s_desc = a.unit_desc[t];
+  }
+  __syncthreads();
+  int64_t u = s_u;
+  uint4 d = s_desc;
+  int32_t dk[kJDK], dp[kJDK];
+  AggRows<FL> cur, nxt;
+  if (u < n_units) {
+    load_agg_dim(a, d, dk, dp);
+    load_agg_rows<FL>(a, d.z + tid, d.w, cur);
+  }
+  while (u < n_units) {
+    const uint32_t dlo = d.x, dhi = d.y, flo = d.z, fhi = d.w;
+    int64_t t_req = 0;
+    uint4 nd = make_uint4(0, 0, 0, 0);
+    if (tid == 0) {
+      if (t_ahead < n_units) nd = a.unit_desc[t_ahead];
+      t_req = take_ticket(a);
+    }
+    for (int s = tid; s < kJSlots; s += kJBlock) tkey[s] = kLdsEmpty;
+    __syncthreads();
+    // build: at most kJChunk unique keys into kJSlots slots, so a free slot always exists
+#pragma unroll
+    for (int k = 0; k < kJDK; ++k) {
+      if (dlo + tid + k * kJBlock >= dhi) continue;
+      const int32_t key = dk[k];
+      const uint64_t want = (uint64_t)(uint32_t)key | (1ull << 32);
+      uint32_t h = slot_hash(key);
+      for (int step = 0; step < kJSlots; ++step) {
+        const uint64_t old = atomicCAS((unsigned long long*)&tkey[h], (unsigned long long)kLdsEmpty, (unsigned long long)want);
+        if (old == kLdsEmpty) {
+          tpay[h] = dp[k];
+          break;
+        }
+        if (old == want) {
+          set_status(a.status, kDevDupKey);
+          break;
+        }
+        h = (h + 1) & (kJSlots - 1);
+      }
+    }
+    if (tid == 0) {
+      s_u = t_ahead;
+      s_desc = nd;
+    }
+    __syncthreads();
+    const int64_t un = s_u;
+    const uint4 dn = s_desc;
+    const uint4 pd = un < n_units ? dn : d;  // past the last unit: reread this one (discarded)
+    int32_t ndk[kJDK], ndp[kJDK];
+    const uint32_t nrows = fhi - flo;
+    const uint32_t iters = (nrows + kJR * kJBlock - 1) / (kJR * kJBlock);
+    const bool early = iters <= 1;
+    if (early) {
+      load_agg_dim(a, pd, ndk, ndp);
+      load_agg_rows<FL>(a, pd.z + tid, pd.w, nxt);
+    }
+    for (uint32_t it = 0; it < iters; ++it) {
+      const uint32_t i0 = flo + it * (kJR * kJBlock) + tid;
+      if (it > 0) cur = nxt;
+      if (it + 1 < iters) load_agg_rows<FL>(a, i0 + kJR * kJBlock, fhi, nxt);
+      bool fnd[kJR];
+      int32_t pay[kJR];
+#pragma unroll
+      for (int k = 0; k < kJR; ++k) {
+        fnd[k] = false;
+        pay[k] = 0;
+        if (i0 + k * kJBlock < fhi) {
+          const uint64_t want = (uint64_t)(uint32_t)cur.key[k] | (1ull << 32);
+          uint32_t h = slot_hash(cur.key[k]);
+          for (int step = 0; step < kJSlots; ++step) {
+            const uint64_t c = tkey[h];
+            if (c == want) {
+              fnd[k] = true;
+              pay[k] = tpay[h];
+              break;
+            }
+            if (c == kLdsEmpty) break;
+            h = (h + 1) & (kJSlots - 1);
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kJR; ++k) {
+        const bool hit = fnd[k];
+        matched += hit;
+        const int64_t key = hit ? agg_group_key<MODE>(pay[k], cur.fl, k) : 0;
+        const uint64_t sp = cur.sp[k], sq = (uint64_t)(int64_t)cur.qty[k];
+        const int s = hit ? grp.find(key, a.lds_probe) : -1;
+        bool add = s >= 0;
+        // hot groups: many lanes of the wave on one slot are pre-summed
+        const uint64_t act = wave_ballot(add);
+        if (act != 0) {
+          const int first = __ffsll((long long)act) - 1;
+          const int s0 = __shfl(s, first, kWave);
+          const bool mine = add && s == s0;
+          const uint64_t same = wave_ballot(mine);
+          if (__popcll(same) >= kCombineMin) {
+            const uint64_t tp = wave_sum_u64(mine ? sp : 0);
+            const uint64_t tq = wave_sum_u64(mine ? sq : 0);
+            if ((int)lane == first) grp.add(s0, tp, tq, (uint64_t)__popcll(same));
+            add = add && !mine;
+          }
+        }
+        if (add) grp.add(s, sp, sq, 1ull);
+        group_add_wave(a.groups, hit && s < 0, key, sp, sq);
+      }
+    }
+    if (!early) {
+      load_agg_dim(a, pd, ndk, ndp);
+      load_agg_rows<FL>(a, pd.z + tid, pd.w, nxt);
+    }
+    __syncthreads();  // the join table and s_u / s_desc are reused by the next unit
+    t_ahead = t_req;
+    u = un;
+    d = dn;
+#pragma unroll
+    for (int k = 0; k < kJDK; ++k) {
+      dk[k] = ndk[k];
+      dp[k] = ndp[k];
+    }
+    cur = nxt;
+  }
+  __syncthreads();
+  grp.flush(a.groups, tid, kJBlock);
+  matched = wave_sum_u64(matched);
+  if (lane == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
+}
+
 #define TRY(x)                   \
   do {                           \
     rel_status s_ = (x);         \
@@ -1108,7 +1430,8 @@ rel_status partition_side(rel_ctx* ctx, PartSide& s, bool fact, int64_t* passed)
     }
     {
       relh::KernelTimer kt(ctx, fact ? "fact_p1_colscan" : "dim_p1_colscan");
-      hipLaunchKernelGGL(k_p1_colscan, dim3(nb1), blk, 0, ctx->stream, s.hist1, ntiles1, nb1, s.tot1, passed);
+      hipLaunchKernelGGL(k_p1_colscan, dim3(nb1), blk, 0, ctx->stream, s.hist1, ntiles1, nb1, s.tot1, passed,
+                         s.pcount, 1u << s.b2);
     }
     {
       relh::KernelTimer kt(ctx, fact ? "fact_p1_scatter" : "dim_p1_scatter");
@@ -1117,6 +1440,7 @@ rel_status partition_side(rel_ctx* ctx, PartSide& s, bool fact, int64_t* passed)
     }
   } else {
     TRY(relh::fill_u32(ctx, s.tot1, nb1, 0));
+    TRY(relh::fill_u32(ctx, s.pcount, (size_t)nb1 << s.b2, 0));
   }
   REL_LAUNCH_CHECK(ctx, "partition level 1");
   {
@@ -1166,9 +1490,21 @@ namespace relh {
 
 bool partitioned_supported(int64_t n, int64_t m) { return n < (1ll << 31) && m < (1ll << 30); }
 
-// GROUP BY fk over fact JOIN dim ON fk = pk, WHERE day < day_lt, radix-partitioned.
-rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, int32_t day_lt,
-                                 rel_groups_out* out, int64_t* counters) {
+// Both sides of fact JOIN dim ON fk = pk (fact rows filtered by day < day_lt)
+// radix-partitioned into 2^(b1 + b2) partitions, and the work units listed.
+struct Partitioned {
+  PartSide F, D;
+  uint32_t b1, b2, nparts;
+  uint4* unit_desc;
+  uint2* unit_split;
+  int64_t* n_units;
+  int64_t* ticket;
+  void* split_scratch;
+  uint32_t* split_done;
+};
+
+rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, int32_t day_lt, int pkind,
+                          const void* payload, bool with_flag, int64_t* counters, Partitioned* P) {
   const int64_t n = fact->n, m = dim->m;
   uint32_t b1, b2;
   split_bits(m, &b1, &b2);
@@ -1181,7 +1517,7 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
 
   // scratch: partitioned columns (A: fact level 1, B: fact level 2, C: dim both levels), bookkeeping (D)
   void *pa, *pb, *pc, *pd;
-  const size_t fact_bytes = (size_t)(n > 0 ? n : 1) * 16 + 4 * 256;
+  const size_t fact_bytes = (size_t)(n > 0 ? n : 1) * 17 + 4 * 256;  // fk, qty, price, flag
   TRY(scratch(ctx, SCR_PART_A, fact_bytes, &pa));
   TRY(scratch(ctx, SCR_PART_B, fact_bytes, &pb));
   TRY(scratch(ctx, SCR_PART_C, (size_t)(m > 0 ? m : 1) * 16 + 4 * 256, &pc));
@@ -1205,6 +1541,7 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   F.day = fact->day;
   F.price = fact->price_cents;
   F.qty = fact->qty;
+  F.flag = with_flag ? fact->flag : nullptr;
   F.day_lt = day_lt;
   F.n = n;
   F.b1 = b1;
@@ -1213,9 +1550,11 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   F.key1 = ca.take<int32_t>(n);
   F.qty1 = ca.take<int32_t>(n);
   F.price1 = ca.take<int64_t>(n);
+  F.flag1 = with_flag ? ca.take<int8_t>(n) : nullptr;
   F.key2 = cb.take<int32_t>(n);
   F.qty2 = cb.take<int32_t>(n);
   F.price2 = cb.take<int64_t>(n);
+  F.flag2 = with_flag ? cb.take<int8_t>(n) : nullptr;
   F.hist1 = cd.take<uint32_t>((size_t)fnt1 * nb1);
   F.tot1 = cd.take<uint32_t>(nb1);
   F.hist2 = cd.take<uint32_t>((size_t)fnt2 * nb2);
@@ -1226,7 +1565,8 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
 
   PartSide D{};
   D.key = dim->pk;
-  D.pkind = PAY_NONE;  // the group key is the join key: no dim payload travels
+  D.pkind = pkind;
+  D.payload = payload;
   D.n = m;
   D.b1 = b1;
   D.b2 = b2;
@@ -1247,10 +1587,8 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   uint32_t* sbase = cd.take<uint32_t>(nparts);
   const uint32_t unit_wgs = (nparts + kUBlk - 1) / kUBlk;
   uint32_t* wg_cls = cd.take<uint32_t>((size_t)unit_wgs * kClasses);
-  int64_t* n_units = counters + CNT_AUX0;
-  int64_t* ticket = counters + CNT_TICKET;
 
-  // The two sides are independent until the groupjoin: the dim side (small,
+  // The two sides are independent until the join: the dim side (small,
   // latency-bound kernels) runs on the auxiliary stream beside the fact side.
   TRY(aux_fork(ctx));
   {
@@ -1263,56 +1601,110 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   TRY(partition_side(ctx, F, true, counters + CNT_ROWS_PASSED));
   TRY(aux_join(ctx));
 
+  UnitArgs ua{};
+  ua.dstart = D.pstart;
+  ua.dcount = D.pcount;
+  ua.fstart = F.pstart;
+  ua.fcount = F.pcount;
+  ua.nparts = nparts;
+  ua.rows_passed = counters + CNT_ROWS_PASSED;
+  ua.split_ctr = split_ctr;
+  ua.sbase = sbase;
+  ua.wg_cls = wg_cls;
+  ua.desc = unit_desc;
+  ua.split = unit_split;
+  ua.n_units = counters + CNT_AUX0;
   {
-    UnitArgs ua{};
-    ua.dstart = D.pstart;
-    ua.dcount = D.pcount;
-    ua.fstart = F.pstart;
-    ua.fcount = F.pcount;
-    ua.nparts = nparts;
-    ua.rows_passed = counters + CNT_ROWS_PASSED;
-    ua.split_ctr = split_ctr;
-    ua.sbase = sbase;
-    ua.wg_cls = wg_cls;
-    ua.desc = unit_desc;
-    ua.split = unit_split;
-    ua.n_units = n_units;
-    {
-      KernelTimer kt(ctx, "unit_count");
-      hipLaunchKernelGGL(k_unit_count, dim3(unit_wgs), dim3(kUBlk), 0, ctx->stream, ua);
-    }
-    {
-      KernelTimer kt(ctx, "unit_emit");
-      hipLaunchKernelGGL(k_unit_emit, dim3(unit_wgs), dim3(kUBlk), 0, ctx->stream, ua);
-    }
-    REL_LAUNCH_CHECK(ctx, "make_units");
-    TRY(fill_u64(ctx, ticket, 1, 0));
-    TRY(fill_u64(ctx, out->d_n_groups, 1, 0));
-    KernelTimer kt(ctx, "part_groupjoin");
-    JoinArgs a{};
-    a.unit_desc = unit_desc;
-    a.unit_split = unit_split;
-    a.n_units = n_units;
-    a.dkey = D.key2;
-    a.fkey = F.key2;
-    a.fprice = F.price2;
-    a.fqty = F.qty2;
-    a.split_acc = (SplitAcc*)pe;
-    a.split_done = split_done;
-    a.zero = 0;
-    a.ticket = ticket;
-    a.matched = counters + CNT_JOIN_MATCHES;
-    a.status = ctx->d_status;
-    a.out_key = out->key;
-    a.out_sp = out->sum_price;
-    a.out_sq = out->sum_qty;
-    a.out_cnt = out->count;
-    a.out_cap = out->cap;
-    a.d_n = out->d_n_groups;
-    const unsigned grid = (unsigned)ctx->num_cus * 2;  // 60 KB of LDS each: two per CU
-    hipLaunchKernelGGL(k_part_groupjoin, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
-    REL_LAUNCH_CHECK(ctx, "part_groupjoin");
+    KernelTimer kt(ctx, "unit_count");
+    hipLaunchKernelGGL(k_unit_count, dim3(unit_wgs), dim3(kUBlk), 0, ctx->stream, ua);
   }
+  {
+    KernelTimer kt(ctx, "unit_emit");
+    hipLaunchKernelGGL(k_unit_emit, dim3(unit_wgs), dim3(kUBlk), 0, ctx->stream, ua);
+  }
+  REL_LAUNCH_CHECK(ctx, "make_units");
+  TRY(fill_u64(ctx, counters + CNT_TICKET, 1, 0));
+
+  P->F = F;
+  P->D = D;
+  P->b1 = b1;
+  P->b2 = b2;
+  P->nparts = nparts;
+  P->unit_desc = unit_desc;
+  P->unit_split = unit_split;
+  P->n_units = counters + CNT_AUX0;
+  P->ticket = counters + CNT_TICKET;
+  P->split_scratch = pe;
+  P->split_done = split_done;
+  return REL_OK;
+}
+
+// GROUP BY fk over fact JOIN dim ON fk = pk, WHERE day < day_lt, radix-partitioned.
+rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, int32_t day_lt,
+                                 rel_groups_out* out, int64_t* counters) {
+  Partitioned P;
+  // the group key is the join key: no dim payload travels
+  TRY(partition_both(ctx, fact, dim, day_lt, PAY_NONE, nullptr, false, counters, &P));
+  TRY(fill_u64(ctx, out->d_n_groups, 1, 0));
+  KernelTimer kt(ctx, "part_groupjoin");
+  JoinArgs a{};
+  a.unit_desc = P.unit_desc;
+  a.unit_split = P.unit_split;
+  a.n_units = P.n_units;
+  a.dkey = P.D.key2;
+  a.fkey = P.F.key2;
+  a.fprice = P.F.price2;
+  a.fqty = P.F.qty2;
+  a.split_acc = (SplitAcc*)P.split_scratch;
+  a.split_done = P.split_done;
+  a.zero = 0;
+  a.ticket = P.ticket;
+  a.matched = counters + CNT_JOIN_MATCHES;
+  a.status = ctx->d_status;
+  a.out_key = out->key;
+  a.out_sp = out->sum_price;
+  a.out_sq = out->sum_qty;
+  a.out_cnt = out->count;
+  a.out_cap = out->cap;
+  a.d_n = out->d_n_groups;
+  const unsigned grid = (unsigned)ctx->num_cus * 2;  // 60 KB of LDS each: two per CU
+  hipLaunchKernelGGL(k_part_groupjoin, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
+  REL_LAUNCH_CHECK(ctx, "part_groupjoin");
+  return REL_OK;
+}
+
+// GROUP BY a dim attribute (dim.grp, or (dim.prio, fact.flag)) over the
+// partitioned join: the dim payload travels with the keys (and the fact flag
+// with the rows when the key needs it), and k_part_join_agg aggregates into
+// the device-memory group table g with an LDS table in front of it.
+rel_status partitioned_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, int32_t day_lt, int group_by,
+                                void* group_slots, uint32_t group_log2cap, uint32_t max_probe, int32_t lds_probe,
+                                int64_t* counters) {
+  Partitioned P;
+  const bool prio_flag = group_by == REL_GROUP_PRIO_FLAG;
+  TRY(partition_both(ctx, fact, dim, day_lt, prio_flag ? PAY_I8 : PAY_I32,
+                     prio_flag ? (const void*)dim->prio : (const void*)dim->grp, prio_flag, counters, &P));
+  KernelTimer kt(ctx, "part_join_agg");
+  AggArgs a{};
+  a.unit_desc = P.unit_desc;
+  a.n_units = P.n_units;
+  a.dkey = P.D.key2;
+  a.dpay = P.D.pay2;
+  a.fkey = P.F.key2;
+  a.fprice = P.F.price2;
+  a.fqty = P.F.qty2;
+  a.fflag = P.F.flag2;
+  a.ticket = P.ticket;
+  a.matched = counters + CNT_JOIN_MATCHES;
+  a.status = ctx->d_status;
+  a.groups = GroupView{(GroupSlot*)group_slots, (uint32_t)((1ull << group_log2cap) - 1), 32u - group_log2cap,
+                       ctx->d_status, max_probe};
+  a.lds_probe = lds_probe;
+  a.zero = 0;
+  const unsigned grid = (unsigned)ctx->num_cus * 2;
+  if (prio_flag) hipLaunchKernelGGL(k_part_join_agg<REL_GROUP_PRIO_FLAG>, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
+  else hipLaunchKernelGGL(k_part_join_agg<REL_GROUP_DIM_GRP>, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
+  REL_LAUNCH_CHECK(ctx, "part_join_agg");
   return REL_OK;
 }
 

@@ -62,7 +62,7 @@ def test_small_workload(ctx):
 
 def test_medium_workload(ctx):
     st = run_both(ctx, datagen.medium(), repeats=3)
-    assert st["groups"] == 15
+    assert st["groups"] == 15 and st["join_placement"] == "partitioned"
 
 
 @pytest.mark.parametrize("group_by", ["fk", "dim_grp", "prio_flag"])
@@ -287,3 +287,85 @@ def test_auto_picks_partitioned_for_large_fk_grouping(ctx):
     T = datagen.large(seed=34, n=2_000_000, m=500_000)
     st = run_both(ctx, T)
     assert st["join_placement"] == "partitioned"
+
+
+# -- radix-partitioned join with a dim-attribute group key -----------------------------------------------------------------
+
+@pytest.mark.parametrize("group_by,grp_card", [("prio_flag", None), ("dim_grp", 7), ("dim_grp", 300), ("dim_grp", 20_000),
+                                               ("dim_grp", 3_000_000)])
+@pytest.mark.parametrize("n,m,zipf", [(1, 1, 0.0), (1000, 17, 0.0), (100_003, 25_001, 0.0), (2_000_000, 500_000, 1.2)])
+def test_partitioned_join_agg(ctx, group_by, grp_card, n, m, zipf):
+    T = datagen.make_tables(n, m, 900 + n, day_lt=1200, group_by=group_by, fk_zipf=zipf, fk_domain=m + m // 5,
+                            grp_card=grp_card)
+    st = run_both(ctx, T, plan=_partitioned(), repeats=2)
+    assert st["join_placement"] == "partitioned"
+
+
+@pytest.mark.parametrize("placement", ["lds", "global"])
+def test_partitioned_join_agg_group_placement(ctx, placement):
+    # the LDS tables in front of the device table (lds), or none at all (global)
+    T = datagen.make_tables(300_000, 75_000, 12, day_lt=1500, group_by="dim_grp", fk_zipf=1.1, fk_domain=80_000,
+                            grp_card=3000)
+    plan = rel.Plan(group_capacity=4000, group_placement=rel.PLACE[placement],
+                    join_placement=rel.PLACE["partitioned"], allow_fallback=0)
+    st = run_both(ctx, T, plan=plan, repeats=2)
+    assert st["group_placement"] == placement and st["join_placement"] == "partitioned"
+
+
+@pytest.mark.parametrize("group_by", ["prio_flag", "dim_grp"])
+def test_partitioned_join_agg_chunked_and_split(ctx, group_by):
+    # one partition of 3000 keys (several chunks) and a Zipf(1.5) head (split
+    # partitions): every fact row still matches in exactly one unit
+    hot = _same_partition_keys(3000, 0x0abc)
+    rest = datagen.permutation(400_000, 2_000_000, 13, 1)
+    pk = np.concatenate([hot, rest]).astype(np.int32)
+    T = datagen.make_tables(2_000_000, pk.shape[0], 13, day_lt=1800, group_by=group_by, grp_card=5000)
+    T.pk = pk
+    T.fk = pk[datagen.zipf(T.n, pk.shape[0], 1.5, 13, 77)]
+    T.fk[: T.n // 3] = hot[datagen.uniform(T.n // 3, 0, 2999, np.int64, 13, 78)]
+    T.fk[::11] = -5  # not a dim key
+    run_both(ctx, T, plan=_partitioned(), repeats=2)
+
+
+@pytest.mark.parametrize("case", ["empty_fact", "empty_dim", "all_filtered", "no_match", "extreme_keys"])
+def test_partitioned_join_agg_degenerate(ctx, case):
+    n, m = (0 if case == "empty_fact" else 50_000), (0 if case == "empty_dim" else 9_000)
+    T = datagen.make_tables(n, m, 14, day_lt=0 if case == "all_filtered" else 1800, group_by="dim_grp", grp_card=50)
+    if case == "no_match":
+        T.fk = T.fk + 100_000
+    elif case == "extreme_keys":
+        ext = np.array([-(2 ** 31), 2 ** 31 - 1, -1, -2, -1_000_000], np.int32)
+        T.pk[:5] = ext
+        T.fk[:200] = np.resize(ext, 200)
+        T.grp[:5] = np.array([-1, -(2 ** 31), 2 ** 31 - 1, 5, -7], np.int32)
+    run_both(ctx, T, plan=_partitioned())
+    T.group_by = "prio_flag"
+    if case == "extreme_keys":
+        T.prio = datagen.uniform(T.m, -128, 127, np.int8, 14, 100)
+        T.flag = datagen.uniform(T.n, -128, 127, np.int8, 14, 101)
+    run_both(ctx, T, plan=_partitioned())
+
+
+def test_partitioned_join_agg_duplicate_pk_reported(ctx):
+    T = datagen.make_tables(10_000, 1000, 15, group_by="dim_grp", grp_card=40)
+    T.pk[7] = T.pk[8]
+    fact, dim = to_dev(T)
+    with pytest.raises(rel.RelError) as e:
+        ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, plan=_partitioned())
+    assert e.value.status == rel.DUPLICATE_KEY
+
+
+@pytest.mark.parametrize("placement", ["lds", "global"])
+def test_partitioned_planned_overflow_falls_back(ctx, placement):
+    T = datagen.make_tables(1_500_000, 400_000, 16, day_lt=1800, group_by="dim_grp", grp_card=5000)
+    plan = rel.Plan(group_capacity=16, group_placement=rel.PLACE[placement], join_placement=rel.PLACE["partitioned"],
+                    allow_fallback=1)
+    fact, dim = to_dev(T)
+    ora, _ = oracle.run_tables(T)
+    out, st = ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, plan=plan)
+    assert st["fell_back"] == 1 and st["overflowed"] == 1
+    assert_groups_equal(gpu_groups(out), ora, "partitioned fallback")
+    plan.allow_fallback = 0
+    with pytest.raises(rel.RelError) as e:
+        ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, plan=plan)
+    assert e.value.status == rel.OVERFLOW
