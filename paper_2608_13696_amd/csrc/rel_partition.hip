@@ -848,8 +848,18 @@ constexpr int kJPer = kJSlots / kJBlock;                 // LDS slots per thread
 // rewritten into a wave-wide one whose result is broadcast at once, stalling
 // the wave on the round trip; this way the wave waits only where the ticket
 // is used, after the current unit's build.
+// The offset is rebuilt at each call (the empty asm keeps the compiler from
+// hoisting it out of the unit loop): a loop-invariant address would hold two
+// registers for the whole loop, and when spilled its reload waits for every
+// memory operation in flight.
+__device__ __forceinline__ uint32_t unhoisted_zero_offset(uint32_t zero) {
+  uint32_t z = threadIdx.x * zero;
+  asm volatile("" : "+v"(z));
+  return z;
+}
+
 __device__ __forceinline__ int64_t take_ticket(const JoinArgs& a) {
-  unsigned long long* t = (unsigned long long*)a.ticket + threadIdx.x * a.zero;
+  unsigned long long* t = (unsigned long long*)a.ticket + unhoisted_zero_offset(a.zero);
   return (int64_t)__hip_atomic_fetch_add(t, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -878,10 +888,12 @@ __device__ __forceinline__ void load_dkeys(const JoinArgs& a, uint32_t dlo, uint
   }
 }
 
-// The next unit's dim keys and first fact rows, with indices clamped into the
-// unit's (never empty) ranges: the loads carry no branch, so their number is
-// fixed and a later wait for an earlier atomic does not have to wait for them.
-// Lanes past the ranges hold copies that the build and probe skip.
+// The next unit's dim keys and the keys of its first fact rows, with indices
+// clamped into the unit's (never empty) ranges: the loads carry no branch, so
+// their number is fixed and a later wait for an earlier atomic does not have to
+// wait for them. Lanes past the ranges hold copies that the build and probe
+// skip. The rows' prices and quantities follow at the start of the unit
+// (load_payload), so they do not hold registers through this unit.
 __device__ __forceinline__ void prefetch_unit(const JoinArgs& a, uint4 u, int32_t (&dk)[kJDK], RowRegs& r) {
 #pragma unroll
   for (int k = 0; k < kJDK; ++k) {
@@ -891,8 +903,15 @@ __device__ __forceinline__ void prefetch_unit(const JoinArgs& a, uint4 u, int32_
 #pragma unroll
   for (int k = 0; k < kJR; ++k) {
     uint32_t i = u.z + threadIdx.x + k * kJBlock;
-    i = i < u.w ? i : u.w - 1;
-    r.key[k] = a.fkey[i];
+    r.key[k] = a.fkey[i < u.w ? i : u.w - 1];
+  }
+}
+
+__device__ __forceinline__ void load_payload(const JoinArgs& a, uint32_t i0, uint32_t fhi, RowRegs& r) {
+#pragma unroll
+  for (int k = 0; k < kJR; ++k) {
+    uint32_t i = i0 + k * kJBlock;
+    i = i < fhi ? i : fhi - 1;
     r.sp[k] = (uint64_t)a.fprice[i];
     r.qty[k] = a.fqty[i];
   }
@@ -901,7 +920,7 @@ __device__ __forceinline__ void prefetch_unit(const JoinArgs& a, uint4 u, int32_
 // Output room for `total` groups. Like take_ticket, the address is not provably
 // uniform, so the wave waits for the result only where it is used.
 __device__ __forceinline__ int64_t reserve_nowait(const JoinArgs& a, uint32_t total) {
-  unsigned long long* p = (unsigned long long*)a.d_n + threadIdx.x * a.zero;
+  unsigned long long* p = (unsigned long long*)a.d_n + unhoisted_zero_offset(a.zero);
   return (int64_t)__hip_atomic_fetch_add(p, (unsigned long long)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -966,12 +985,10 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
   uint2 sp = s_split;
   int32_t dkeys[kJDK];
   RowRegs cur, nxt;
-  if (u < n_units) {
-    load_dkeys(a, d.x, d.y, dkeys);
-    load_rows(a, d.z + tid, d.w, cur);
-  }
+  if (u < n_units) prefetch_unit(a, d, dkeys, cur);
   while (u < n_units) {
     const uint32_t dlo = d.x, dhi = d.y, flo = d.z, fhi = d.w;
+    load_payload(a, flo + tid, fhi, cur);
     int64_t t_req = 0;
     uint4 nd = make_uint4(0, 0, 0, 0);
     uint2 ns = make_uint2(0, 0);
@@ -1215,7 +1232,7 @@ struct AggArgs {
 };
 
 __device__ __forceinline__ int64_t take_ticket(const AggArgs& a) {
-  unsigned long long* t = (unsigned long long*)a.ticket + threadIdx.x * a.zero;
+  unsigned long long* t = (unsigned long long*)a.ticket + unhoisted_zero_offset(a.zero);
   return (int64_t)__hip_atomic_fetch_add(t, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
