@@ -46,22 +46,27 @@ def kernel_alg_bytes(kernel: str, n: int, m: int, r: int, g: int, group_by: str)
     re-read traffic). n fact rows, m dim rows, r rows passing the predicate,
     g groups. Returns (bytes, description) or (None, None)."""
     fb, db = FACT_BYTES[group_by], DIM_BYTES[group_by]
+    # partitioned rows: fact 16 B (+1 flag byte when the key needs it); dim key
+    # 4 B (+4 B payload when the group key comes from the dim side)
+    pf = PART_ROW_BYTES + (1 if group_by == "prio_flag" else 0)
+    pd = 4 if group_by == "fk" else 8
     table = {
         # plain (device-memory table) pipeline
         "probe_agg": (fb * n, f"{fb} B per fact row (day, fk, price_cents, qty)"),
         "join_build": (db * m, f"{db} B per dim row"),
         "finalize": (OUT_BYTES_PER_GROUP * g, "32 B per output group"),
-        # radix-partitioned groupjoin
+        # radix-partitioned pipeline
         "fact_p1_hist": (8 * n, "8 B per fact row (day, fk)"),
-        "fact_p1_scatter": (20 * n + PART_ROW_BYTES * r, "20 B per fact row read + 16 B per passing row written"),
+        "fact_p1_scatter": (fb * n + pf * r, f"{fb} B per fact row read + {pf} B per passing row written"),
         "fact_p2_hist": (4 * r, "4 B per passing row (fk)"),
-        "fact_p2_scatter": (2 * PART_ROW_BYTES * r, "16 B per passing row read + 16 B written"),
+        "fact_p2_scatter": (2 * pf * r, f"{pf} B per passing row read + {pf} B written"),
         "dim_p1_hist": (4 * m, "4 B per dim row"),
-        "dim_p1_scatter": (8 * m, "4 B per dim row read + 4 B written"),
+        "dim_p1_scatter": ((db + pd) * m, f"{db} B per dim row read + {pd} B written"),
         "dim_p2_hist": (4 * m, "4 B per dim row"),
-        "dim_p2_scatter": (8 * m, "4 B per dim row read + 4 B written"),
+        "dim_p2_scatter": (2 * pd * m, f"{pd} B per dim row read + {pd} B written"),
         "part_groupjoin": (PART_ROW_BYTES * r + 4 * m + OUT_BYTES_PER_GROUP * g,
                            "16 B per passing row + 4 B per dim key + 32 B per group"),
+        "part_join_agg": (pf * r + pd * m, f"{pf} B per passing row + {pd} B per dim row (key, payload)"),
     }
     return table.get(kernel, (None, None))
 
