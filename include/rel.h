@@ -298,8 +298,13 @@ typedef struct rel_planner rel_planner;
 rel_status rel_planner_create(rel_ctx* ctx, const float* params, const float* mean, const float* scale,
                               float margin_log2, rel_planner** out);
 /* Sketch, predict and fill *plan (group capacity and placement, fallback
- * allowed). Synchronises once (a few floats come back). pred (host, nullable)
- * receives the predictions log2(1 + join rows), log2(1 + groups). */
+ * allowed). Group capacity = 2^(predicted log2 groups + margin), capped at the
+ * plain bound; group placement LDS when that is at most 512 or a key is hot
+ * (sampled max frequency >= 4/256), else device memory; join placement plain
+ * (device memory) when a key is hot, the group key is a dim attribute and the
+ * capacity is at most 2048, else left to the library. Synchronises once (a
+ * few floats come back). pred (host, nullable) receives the predictions
+ * log2(1 + join rows), log2(1 + groups). */
 rel_status rel_planner_plan(rel_planner* p, const rel_fact* fact, const rel_dim* dim, const rel_query* q,
                             const int64_t* d_fact_sample, const int64_t* d_dim_sample, int32_t k, rel_plan* plan,
                             float* pred);

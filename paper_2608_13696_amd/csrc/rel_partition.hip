@@ -979,6 +979,13 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
       s_split = a.unit_split[t];
     }
   }
+  // The table starts empty once; after that each unit's emission leaves the
+  // slots it read empty again, and an insert zeroes its slot's sums, so no
+  // unit spends a phase and a barrier clearing it.
+  for (int s = tid; s < kJSlots; s += kJBlock) {
+    tkey[s] = kLdsEmpty;
+    tcnt[s] = 0;
+  }
   __syncthreads();
   int64_t u = s_u;
   uint4 d = s_desc;
@@ -1001,13 +1008,6 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
       }
       t_req = take_ticket(a);
     }
-    for (int s = tid; s < kJSlots; s += kJBlock) {
-      tkey[s] = kLdsEmpty;
-      tcnt[s] = 0;
-      tsp[s] = 0;
-      tsq[s] = 0;
-    }
-    __syncthreads();
     // build: at most kJChunk unique keys into kJSlots slots, so a free slot always exists
 #pragma unroll
     for (int k = 0; k < kJDK; ++k) {
@@ -1020,6 +1020,8 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
         const uint64_t old = atomicCAS((unsigned long long*)&tkey[h], (unsigned long long)kLdsEmpty, (unsigned long long)want);
         if (old == kLdsEmpty) {
           tpos[h] = (uint16_t)pos;
+          tsp[h] = 0;
+          tsq[h] = 0;
           break;
         }
         if (old == want) {
@@ -1140,9 +1142,12 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
       const int64_t o0 = (int64_t)s_excl;
 #pragma unroll
       for (int k = 0; k < kJPer; ++k) {
-        if (occ[k] == 0) continue;
         const int s = k * kJBlock + tid;
-        put_group(a, o0 + base[k] + mask_rank(bal[k]), (int64_t)(int32_t)(uint32_t)tkey[s], tsp[s], tsq[s], occ[k]);
+        if (occ[k] != 0) {
+          put_group(a, o0 + base[k] + mask_rank(bal[k]), (int64_t)(int32_t)(uint32_t)tkey[s], tsp[s], tsq[s], occ[k]);
+          tcnt[s] = 0;
+        }
+        tkey[s] = kLdsEmpty;
       }
     } else {
       // Sub-unit of a split chunk: add the partial sums into the chunk's
@@ -1153,7 +1158,9 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
       for (int k = 0; k < kJPer; ++k) {
         const int s = tid * kJPer + k;
         const uint32_t c = tcnt[s];
+        tkey[s] = kLdsEmpty;
         if (c == 0) continue;
+        tcnt[s] = 0;
         SplitAcc* e = acc + tpos[s];
         dev_add<uint64_t>(&e->sp, tsp[s]);
         dev_add<uint64_t>(&e->sq, tsq[s]);
