@@ -703,8 +703,9 @@ __device__ __forceinline__ uint32_t wave_grouped_add(uint32_t* ctr, uint32_t key
 // decides the splits and counts units per size class in each workgroup.
 // k_unit_emit: every workgroup derives its own start in each class from
 // those counts (classes in descending order, workgroups in order) and writes
-// its units. desc[u] = {dlo, dhi, flo, fhi}; split[u] = {split id + 1 (0: not
-// split), sub-units of the chunk}.
+// its units. desc[u] = {dlo, dhi, flo, fhi}; split[u] = {split id + 1,
+// sub-units of the chunk} for a sub-unit of a split chunk, {0, end of the
+// partition's dim keys} for a whole chunk.
 constexpr int kUBlk = 256;
 constexpr int kClasses = 33;
 constexpr int kMaxUnitWgs = (1 << 16) / kUBlk;  // partitions never exceed 2^16
@@ -810,7 +811,7 @@ __global__ __launch_bounds__(kUBlk) void k_unit_emit(UnitArgs a) {
   for (uint32_t c = 0; c < chunks; ++c) {
     const uint32_t dlo = ds + c * kJChunk;
     a.desc[pos + c] = make_uint4(dlo, dlo + kJChunk < ds + dc ? dlo + kJChunk : ds + dc, fs, fs + fc);
-    a.split[pos + c] = make_uint2(0, 1);
+    a.split[pos + c] = make_uint2(0, ds + dc);
   }
 }
 
@@ -853,9 +854,9 @@ constexpr int kJPer = kJSlots / kJBlock;                 // LDS slots per thread
 // registers for the whole loop, and when spilled its reload waits for every
 // memory operation in flight.
 __device__ __forceinline__ uint32_t unhoisted_zero_offset(uint32_t zero) {
-  uint32_t z = threadIdx.x * zero;
+  uint32_t z = zero;
   asm volatile("" : "+v"(z));
-  return z;
+  return threadIdx.x * z;
 }
 
 __device__ __forceinline__ int64_t take_ticket(const JoinArgs& a) {
@@ -943,6 +944,28 @@ __device__ __forceinline__ void put_group(const JoinArgs& a, int64_t o, int64_t 
     a.out_cnt[o] = (int64_t)c;
   } else {
     set_status(a.status, kDevOverflow);
+  }
+}
+
+// A partition of more than kJChunk dim keys is processed as several chunk
+// units, and a key repeated in two chunks would meet no other copy in either
+// unit's table. Each chunk unit therefore also looks up the keys of the
+// partition's later chunks, [from, to), in its own table.
+__device__ __forceinline__ void check_later_chunks(const uint64_t* tkey, const int32_t* dkey, uint32_t from, uint32_t to,
+                                                   uint32_t* status) {
+  for (uint32_t j = from + threadIdx.x; j < to; j += kJBlock) {
+    const int32_t key = dkey[j];
+    const uint64_t want = (uint64_t)(uint32_t)key | (1ull << 32);
+    uint32_t h = slot_hash(key);
+    for (int step = 0; step < kJSlots; ++step) {
+      const uint64_t c = tkey[h];
+      if (c == want) {
+        set_status(status, kDevDupKey);
+        break;
+      }
+      if (c == kLdsEmpty) break;
+      h = (h + 1) & (kJSlots - 1);
+    }
   }
 }
 
@@ -1040,6 +1063,7 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
     const int64_t un = s_u;
     const uint4 dn = s_desc;
     const uint2 sn = s_split;
+    if (sp.x == 0 && sp.y > dhi) check_later_chunks(tkey, a.dkey, dhi, sp.y, a.status);
     int32_t ndkeys[kJDK];
     // past the last unit the loads read the current unit again (discarded)
     const uint4 pd = un < n_units ? dn : d;
@@ -1223,6 +1247,7 @@ constexpr int kAggSlots = 1024;
 
 struct AggArgs {
   const uint4* unit_desc;
+  const uint2* unit_split;  // {0, partition's dim end} for whole chunks
   const int64_t* n_units;
   const int32_t* dkey;
   const int32_t* dpay;
@@ -1292,6 +1317,7 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_join_agg(AggArgs a) {
   __shared__ int32_t tpay[kJSlots];
   __shared__ LdsGroups<kAggSlots> grp;
   __shared__ uint4 s_desc;
+  __shared__ uint2 s_split;
   __shared__ int64_t s_u;
   const int64_t n_units = *a.n_units;
   const uint32_t tid = threadIdx.x, lane = lane_id();
@@ -1304,11 +1330,15 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_join_agg(AggArgs a) {
     const int64_t t = take_ticket(a);
     t_ahead = take_ticket(a);
     s_u = t;
-    if (t < n_units) s_desc = a.unit_desc[t];
+    if (t < n_units) {
+      s_desc = a.unit_desc[t];
+      s_split = a.unit_split[t];
+    }
   }
   __syncthreads();
   int64_t u = s_u;
   uint4 d = s_desc;
+  uint2 usplit = s_split;
   int32_t dk[kJDK], dp[kJDK];
   AggRows<FL> cur, nxt;
   if (u < n_units) {
@@ -1319,8 +1349,12 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_join_agg(AggArgs a) {
     const uint32_t dlo = d.x, dhi = d.y, flo = d.z, fhi = d.w;
     int64_t t_req = 0;
     uint4 nd = make_uint4(0, 0, 0, 0);
+    uint2 ns = make_uint2(0, 0);
     if (tid == 0) {
-      if (t_ahead < n_units) nd = a.unit_desc[t_ahead];
+      if (t_ahead < n_units) {
+        nd = a.unit_desc[t_ahead];
+        ns = a.unit_split[t_ahead];
+      }
       t_req = take_ticket(a);
     }
     for (int s = tid; s < kJSlots; s += kJBlock) tkey[s] = kLdsEmpty;
@@ -1348,10 +1382,13 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_join_agg(AggArgs a) {
     if (tid == 0) {
       s_u = t_ahead;
       s_desc = nd;
+      s_split = ns;
     }
     __syncthreads();
     const int64_t un = s_u;
     const uint4 dn = s_desc;
+    const uint2 sn = s_split;
+    if (usplit.x == 0 && usplit.y > dhi) check_later_chunks(tkey, a.dkey, dhi, usplit.y, a.status);
     const uint4 pd = un < n_units ? dn : d;  // past the last unit: reread this one (discarded)
     int32_t ndk[kJDK], ndp[kJDK];
     const uint32_t nrows = fhi - flo;
@@ -1420,6 +1457,7 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_join_agg(AggArgs a) {
     t_ahead = t_req;
     u = un;
     d = dn;
+    usplit = sn;
 #pragma unroll
     for (int k = 0; k < kJDK; ++k) {
       dk[k] = ndk[k];
@@ -1711,6 +1749,7 @@ rel_status partitioned_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_di
   KernelTimer kt(ctx, "part_join_agg");
   AggArgs a{};
   a.unit_desc = P.unit_desc;
+  a.unit_split = P.unit_split;
   a.n_units = P.n_units;
   a.dkey = P.D.key2;
   a.dpay = P.D.pay2;

@@ -369,3 +369,21 @@ def test_partitioned_planned_overflow_falls_back(ctx, placement):
     with pytest.raises(rel.RelError) as e:
         ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, plan=plan)
     assert e.value.status == rel.OVERFLOW
+
+
+@pytest.mark.parametrize("group_by", ["fk", "dim_grp"])
+@pytest.mark.parametrize("pair", [(0, 2999), (1, 1500), (700, 2100)])
+def test_partitioned_duplicate_across_chunks_reported(ctx, group_by, pair):
+    # 3000 keys in one partition are processed as three chunk units; a key
+    # repeated far apart in the partition usually lands in two of them, where
+    # each unit's own table cannot see the other copy.
+    hot = _same_partition_keys(3000, 0x2468)
+    rest = datagen.permutation(2000, 1_000_000, 17, 1)
+    pk = np.concatenate([hot, rest]).astype(np.int32)
+    pk[pair[1]] = pk[pair[0]]
+    T = datagen.make_tables(50_000, pk.shape[0], 17, day_lt=1800, group_by=group_by, grp_card=40)
+    T.pk = pk
+    fact, dim = to_dev(T)
+    with pytest.raises(rel.RelError) as e:
+        ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, plan=_partitioned())
+    assert e.value.status == rel.DUPLICATE_KEY
