@@ -33,7 +33,7 @@ constexpr int kSBlk = 512;        // scatter kernels
 constexpr int64_t kTile1 = 4096;
 constexpr int64_t kTile = 4096;
 constexpr int kMaxBins = 256;
-constexpr int kJBlock = 512;
+constexpr int kJBlock = 256;
 constexpr int kJSlotBits = 11;
 constexpr int kJSlots = 1 << kJSlotBits;
 constexpr int kJChunk = 1400;  // dim keys per unit: LDS load factor <= 0.69
@@ -951,31 +951,35 @@ __device__ __forceinline__ void put_group(const JoinArgs& a, int64_t o, int64_t 
 // units, and a key repeated in two chunks would meet no other copy in either
 // unit's table. Each chunk unit therefore also looks up the keys of the
 // partition's later chunks, [from, to), in its own table.
+template <int NT>
 __device__ __forceinline__ void check_later_chunks(const uint64_t* tkey, const int32_t* dkey, uint32_t from, uint32_t to,
                                                    uint32_t* status) {
-  for (uint32_t j = from + threadIdx.x; j < to; j += kJBlock) {
+  for (uint32_t j = from + threadIdx.x; j < to; j += NT) {
     const int32_t key = dkey[j];
-    const uint64_t want = (uint64_t)(uint32_t)key | (1ull << 32);
     uint32_t h = slot_hash(key);
     for (int step = 0; step < kJSlots; ++step) {
       const uint64_t c = tkey[h];
-      if (c == want) {
+      if (c == kLdsEmpty) break;
+      if ((uint32_t)c == (uint32_t)key) {
         set_status(status, kDevDupKey);
         break;
       }
-      if (c == kLdsEmpty) break;
       h = (h + 1) & (kJSlots - 1);
     }
   }
 }
 
-// Two workgroups per CU (LDS), so at most 128 VGPRs (four waves per SIMD).
-__global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
-  __shared__ uint64_t tkey[kJSlots];  // {key, 1} packed; all ones = empty
-  __shared__ uint32_t tcnt[kJSlots];
+// A slot is one 64-bit word {key, count}: the key in the low half, the rows
+// matched so far in the high half (for a sub-unit of a split chunk, the key's
+// position in its chunk sits above bit kPosShift of that half: sub-units have
+// at most kSubRows rows); all ones = empty. 48 KB of LDS per workgroup, so
+// three 256-thread workgroups fit on a CU.
+constexpr uint32_t kPosShift = 20;
+
+__global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
+  __shared__ uint64_t tkc[kJSlots];
   __shared__ uint64_t tsp[kJSlots];
   __shared__ uint64_t tsq[kJSlots];
-  __shared__ uint16_t tpos[kJSlots];  // the key's position in its chunk (split units)
   __shared__ uint32_t scr[kJBlock / kWave];
   __shared__ uint32_t s_wk[kJPer][kJBlock / kWave];  // occupied slots per (slot round, wave)
   __shared__ uint64_t s_excl;
@@ -1005,10 +1009,7 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
   // The table starts empty once; after that each unit's emission leaves the
   // slots it read empty again, and an insert zeroes its slot's sums, so no
   // unit spends a phase and a barrier clearing it.
-  for (int s = tid; s < kJSlots; s += kJBlock) {
-    tkey[s] = kLdsEmpty;
-    tcnt[s] = 0;
-  }
+  for (int s = tid; s < kJSlots; s += kJBlock) tkc[s] = kLdsEmpty;
   __syncthreads();
   int64_t u = s_u;
   uint4 d = s_desc;
@@ -1037,17 +1038,16 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
       const uint32_t pos = tid + k * kJBlock;
       if (dlo + pos >= dhi) continue;
       const int32_t key = dkeys[k];
-      const uint64_t want = (uint64_t)(uint32_t)key | (1ull << 32);
+      const uint64_t want = (uint64_t)(uint32_t)key | (sp.x != 0 ? (uint64_t)pos << (32 + kPosShift) : 0ull);
       uint32_t h = slot_hash(key);
       for (int step = 0; step < kJSlots; ++step) {
-        const uint64_t old = atomicCAS((unsigned long long*)&tkey[h], (unsigned long long)kLdsEmpty, (unsigned long long)want);
+        const uint64_t old = atomicCAS((unsigned long long*)&tkc[h], (unsigned long long)kLdsEmpty, (unsigned long long)want);
         if (old == kLdsEmpty) {
-          tpos[h] = (uint16_t)pos;
           tsp[h] = 0;
           tsq[h] = 0;
           break;
         }
-        if (old == want) {
+        if ((uint32_t)old == (uint32_t)key) {
           set_status(a.status, kDevDupKey);
           break;
         }
@@ -1063,7 +1063,7 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
     const int64_t un = s_u;
     const uint4 dn = s_desc;
     const uint2 sn = s_split;
-    if (sp.x == 0 && sp.y > dhi) check_later_chunks(tkey, a.dkey, dhi, sp.y, a.status);
+    if (sp.x == 0 && sp.y > dhi) check_later_chunks<kJBlock>(tkc, a.dkey, dhi, sp.y, a.status);
     int32_t ndkeys[kJDK];
     // past the last unit the loads read the current unit again (discarded)
     const uint4 pd = un < n_units ? dn : d;
@@ -1088,16 +1088,15 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
         fnd[k] = false;
         slt[k] = 0;
         if (i0 + k * kJBlock < fhi) {
-          const uint64_t want = (uint64_t)(uint32_t)cur.key[k] | (1ull << 32);
           uint32_t h = slot_hash(cur.key[k]);
           for (int step = 0; step < kJSlots; ++step) {
-            const uint64_t c = tkey[h];
-            if (c == want) {
+            const uint64_t c = tkc[h];
+            if (c == kLdsEmpty) break;
+            if ((uint32_t)c == (uint32_t)cur.key[k]) {
               fnd[k] = true;
               slt[k] = (int)h;
               break;
             }
-            if (c == kLdsEmpty) break;
             h = (h + 1) & (kJSlots - 1);
           }
         }
@@ -1121,14 +1120,14 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
           if ((int)lane == first) {
             atomicAdd((unsigned long long*)&tsp[s0], (unsigned long long)tsum_p);
             atomicAdd((unsigned long long*)&tsq[s0], (unsigned long long)tsum_q);
-            atomicAdd(&tcnt[s0], (uint32_t)__popcll(same));
+            atomicAdd((unsigned long long*)&tkc[s0], (unsigned long long)__popcll(same) << 32);
           }
           found = found && !mine;
         }
         if (found) {
           atomicAdd((unsigned long long*)&tsp[slot], (unsigned long long)cur.sp[k]);
           atomicAdd((unsigned long long*)&tsq[slot], (unsigned long long)(int64_t)cur.qty[k]);
-          atomicAdd(&tcnt[slot], 1u);
+          atomicAdd((unsigned long long*)&tkc[slot], 1ull << 32);
         }
       }
     }
@@ -1144,7 +1143,8 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
       uint64_t bal[kJPer];
 #pragma unroll
       for (int k = 0; k < kJPer; ++k) {
-        occ[k] = tcnt[k * kJBlock + tid];
+        const uint64_t c = tkc[k * kJBlock + tid];
+        occ[k] = c == kLdsEmpty ? 0u : (uint32_t)(c >> 32);
         bal[k] = wave_ballot(occ[k] != 0);
         if (lane == 0) s_wk[k][wave] = (uint32_t)__popcll(bal[k]);
       }
@@ -1167,11 +1167,9 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
 #pragma unroll
       for (int k = 0; k < kJPer; ++k) {
         const int s = k * kJBlock + tid;
-        if (occ[k] != 0) {
-          put_group(a, o0 + base[k] + mask_rank(bal[k]), (int64_t)(int32_t)(uint32_t)tkey[s], tsp[s], tsq[s], occ[k]);
-          tcnt[s] = 0;
-        }
-        tkey[s] = kLdsEmpty;
+        if (occ[k] != 0)
+          put_group(a, o0 + base[k] + mask_rank(bal[k]), (int64_t)(int32_t)(uint32_t)tkc[s], tsp[s], tsq[s], occ[k]);
+        tkc[s] = kLdsEmpty;
       }
     } else {
       // Sub-unit of a split chunk: add the partial sums into the chunk's
@@ -1181,11 +1179,12 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
 #pragma unroll
       for (int k = 0; k < kJPer; ++k) {
         const int s = tid * kJPer + k;
-        const uint32_t c = tcnt[s];
-        tkey[s] = kLdsEmpty;
+        const uint64_t w = tkc[s];
+        tkc[s] = kLdsEmpty;
+        if (w == kLdsEmpty) continue;
+        const uint32_t c = (uint32_t)(w >> 32) & ((1u << kPosShift) - 1);
         if (c == 0) continue;
-        tcnt[s] = 0;
-        SplitAcc* e = acc + tpos[s];
+        SplitAcc* e = acc + (uint32_t)(w >> (32 + kPosShift));
         dev_add<uint64_t>(&e->sp, tsp[s]);
         dev_add<uint64_t>(&e->sq, tsq[s]);
         dev_add<uint64_t>(&e->cnt, (uint64_t)c);
@@ -1244,6 +1243,8 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_groupjoin(JoinArgs a) {
 // matches at most one dim key, hence one unit.
 
 constexpr int kAggSlots = 1024;
+constexpr int kABlock = 512;                              // two workgroups per CU (56 KB of LDS each)
+constexpr int kADK = (kJChunk + kABlock - 1) / kABlock;  // dim keys per thread
 
 struct AggArgs {
   const uint4* unit_desc;
@@ -1276,7 +1277,7 @@ struct AggRows {
   uint32_t fl;  // the rows' flag bytes (FL only)
 };
 
-// Fact rows i0 + k * kJBlock of a unit, indices clamped into its (never
+// Fact rows i0 + k * kABlock of a unit, indices clamped into its (never
 // empty) range so that the number of loads is fixed; the probe skips the
 // copies past the range.
 template <bool FL>
@@ -1284,7 +1285,7 @@ __device__ __forceinline__ void load_agg_rows(const AggArgs& a, uint32_t i0, uin
   r.fl = 0;
 #pragma unroll
   for (int k = 0; k < kJR; ++k) {
-    uint32_t i = i0 + k * kJBlock;
+    uint32_t i = i0 + k * kABlock;
     i = i < fhi ? i : fhi - 1;
     r.key[k] = a.fkey[i];
     r.sp[k] = (uint64_t)a.fprice[i];
@@ -1293,10 +1294,10 @@ __device__ __forceinline__ void load_agg_rows(const AggArgs& a, uint32_t i0, uin
   }
 }
 
-__device__ __forceinline__ void load_agg_dim(const AggArgs& a, uint4 u, int32_t (&dk)[kJDK], int32_t (&dp)[kJDK]) {
+__device__ __forceinline__ void load_agg_dim(const AggArgs& a, uint4 u, int32_t (&dk)[kADK], int32_t (&dp)[kADK]) {
 #pragma unroll
-  for (int k = 0; k < kJDK; ++k) {
-    uint32_t j = u.x + threadIdx.x + k * kJBlock;
+  for (int k = 0; k < kADK; ++k) {
+    uint32_t j = u.x + threadIdx.x + k * kABlock;
     j = j < u.y ? j : u.y - 1;
     dk[k] = a.dkey[j];
     dp[k] = a.dpay[j];
@@ -1311,7 +1312,7 @@ __device__ __forceinline__ int64_t agg_group_key(int32_t pay, uint32_t fl, int k
 
 // Two workgroups per CU (56 KB of LDS each).
 template <int MODE>
-__global__ __launch_bounds__(kJBlock, 4) void k_part_join_agg(AggArgs a) {
+__global__ __launch_bounds__(kABlock, 4) void k_part_join_agg(AggArgs a) {
   constexpr bool FL = MODE == REL_GROUP_PRIO_FLAG;
   __shared__ uint64_t tkey[kJSlots];  // {key, 1} packed; all ones = empty
   __shared__ int32_t tpay[kJSlots];
@@ -1322,7 +1323,7 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_join_agg(AggArgs a) {
   const int64_t n_units = *a.n_units;
   const uint32_t tid = threadIdx.x, lane = lane_id();
   uint64_t matched = 0;
-  grp.init(tid, kJBlock);
+  grp.init(tid, kABlock);
   // units by ticket from the largest-first list, thread 0 two tickets ahead
   // (as in k_part_groupjoin)
   int64_t t_ahead = 0;
@@ -1339,7 +1340,7 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_join_agg(AggArgs a) {
   int64_t u = s_u;
   uint4 d = s_desc;
   uint2 usplit = s_split;
-  int32_t dk[kJDK], dp[kJDK];
+  int32_t dk[kADK], dp[kADK];
   AggRows<FL> cur, nxt;
   if (u < n_units) {
     load_agg_dim(a, d, dk, dp);
@@ -1357,12 +1358,12 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_join_agg(AggArgs a) {
       }
       t_req = take_ticket(a);
     }
-    for (int s = tid; s < kJSlots; s += kJBlock) tkey[s] = kLdsEmpty;
+    for (int s = tid; s < kJSlots; s += kABlock) tkey[s] = kLdsEmpty;
     __syncthreads();
     // build: at most kJChunk unique keys into kJSlots slots, so a free slot always exists
 #pragma unroll
-    for (int k = 0; k < kJDK; ++k) {
-      if (dlo + tid + k * kJBlock >= dhi) continue;
+    for (int k = 0; k < kADK; ++k) {
+      if (dlo + tid + k * kABlock >= dhi) continue;
       const int32_t key = dk[k];
       const uint64_t want = (uint64_t)(uint32_t)key | (1ull << 32);
       uint32_t h = slot_hash(key);
@@ -1388,27 +1389,27 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_join_agg(AggArgs a) {
     const int64_t un = s_u;
     const uint4 dn = s_desc;
     const uint2 sn = s_split;
-    if (usplit.x == 0 && usplit.y > dhi) check_later_chunks(tkey, a.dkey, dhi, usplit.y, a.status);
+    if (usplit.x == 0 && usplit.y > dhi) check_later_chunks<kABlock>(tkey, a.dkey, dhi, usplit.y, a.status);
     const uint4 pd = un < n_units ? dn : d;  // past the last unit: reread this one (discarded)
-    int32_t ndk[kJDK], ndp[kJDK];
+    int32_t ndk[kADK], ndp[kADK];
     const uint32_t nrows = fhi - flo;
-    const uint32_t iters = (nrows + kJR * kJBlock - 1) / (kJR * kJBlock);
+    const uint32_t iters = (nrows + kJR * kABlock - 1) / (kJR * kABlock);
     const bool early = iters <= 1;
     if (early) {
       load_agg_dim(a, pd, ndk, ndp);
       load_agg_rows<FL>(a, pd.z + tid, pd.w, nxt);
     }
     for (uint32_t it = 0; it < iters; ++it) {
-      const uint32_t i0 = flo + it * (kJR * kJBlock) + tid;
+      const uint32_t i0 = flo + it * (kJR * kABlock) + tid;
       if (it > 0) cur = nxt;
-      if (it + 1 < iters) load_agg_rows<FL>(a, i0 + kJR * kJBlock, fhi, nxt);
+      if (it + 1 < iters) load_agg_rows<FL>(a, i0 + kJR * kABlock, fhi, nxt);
       bool fnd[kJR];
       int32_t pay[kJR];
 #pragma unroll
       for (int k = 0; k < kJR; ++k) {
         fnd[k] = false;
         pay[k] = 0;
-        if (i0 + k * kJBlock < fhi) {
+        if (i0 + k * kABlock < fhi) {
           const uint64_t want = (uint64_t)(uint32_t)cur.key[k] | (1ull << 32);
           uint32_t h = slot_hash(cur.key[k]);
           for (int step = 0; step < kJSlots; ++step) {
@@ -1459,14 +1460,14 @@ __global__ __launch_bounds__(kJBlock, 4) void k_part_join_agg(AggArgs a) {
     d = dn;
     usplit = sn;
 #pragma unroll
-    for (int k = 0; k < kJDK; ++k) {
+    for (int k = 0; k < kADK; ++k) {
       dk[k] = ndk[k];
       dp[k] = ndp[k];
     }
     cur = nxt;
   }
   __syncthreads();
-  grp.flush(a.groups, tid, kJBlock);
+  grp.flush(a.groups, tid, kABlock);
   matched = wave_sum_u64(matched);
   if (lane == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
 }
@@ -1729,7 +1730,7 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   a.out_cnt = out->count;
   a.out_cap = out->cap;
   a.d_n = out->d_n_groups;
-  const unsigned grid = (unsigned)ctx->num_cus * 2;  // 60 KB of LDS each: two per CU
+  const unsigned grid = (unsigned)ctx->num_cus * 3;  // 48 KB of LDS each: three per CU
   hipLaunchKernelGGL(k_part_groupjoin, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
   REL_LAUNCH_CHECK(ctx, "part_groupjoin");
   return REL_OK;
@@ -1765,8 +1766,8 @@ rel_status partitioned_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_di
   a.lds_probe = lds_probe;
   a.zero = 0;
   const unsigned grid = (unsigned)ctx->num_cus * 2;
-  if (prio_flag) hipLaunchKernelGGL(k_part_join_agg<REL_GROUP_PRIO_FLAG>, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
-  else hipLaunchKernelGGL(k_part_join_agg<REL_GROUP_DIM_GRP>, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
+  if (prio_flag) hipLaunchKernelGGL(k_part_join_agg<REL_GROUP_PRIO_FLAG>, dim3(grid), dim3(kABlock), 0, ctx->stream, a);
+  else hipLaunchKernelGGL(k_part_join_agg<REL_GROUP_DIM_GRP>, dim3(grid), dim3(kABlock), 0, ctx->stream, a);
   REL_LAUNCH_CHECK(ctx, "part_join_agg");
   return REL_OK;
 }
