@@ -130,6 +130,34 @@ rel_status rel_join_probe(rel_ctx* ctx, const rel_join_table* table, const int32
                           int32_t* out_fact_idx, int32_t* out_payload, int64_t out_cap, int64_t* d_out_count);
 
 /* ------------------------------------------------------------------------------------------------------------------
+ * Join-output materialisation: the gather out[i] = in[map[i]] that Section 7
+ * finds behind the transform kernel, here with vectorised index loads and
+ * output stores (the paper's advice for that kernel).
+ */
+typedef enum rel_side { REL_SIDE_FACT = 0, REL_SIDE_DIM = 1 } rel_side;
+
+typedef struct rel_gather_col {
+  const void* src;    /* device column of src_rows elements (aligned to elem_bytes) */
+  void* dst;          /* device output of at least max_pairs elements, 16-byte aligned */
+  int64_t src_rows;   /* rows of src; a row index outside [0, src_rows) is a device-side error */
+  int32_t elem_bytes; /* 1, 2, 4 or 8 (any fixed-width type: the bytes are copied) */
+  int32_t side;       /* rel_side: REL_SIDE_FACT indexes by fact_idx, REL_SIDE_DIM by dim_idx */
+} rel_gather_col;
+
+/* For i in [0, *d_n_pairs) (a device count, e.g. rel_join_probe's, at most
+ * max_pairs) and each of the n_cols columns (1..8): dst[i] = src[fact_idx[i]]
+ * (REL_SIDE_FACT) or src[dim_idx[i]] (REL_SIDE_DIM), where fact_idx / dim_idx
+ * are a probe's out_fact_idx / out_payload (the dim row id when the table was
+ * built without a payload). Index arrays: device, 16-byte aligned, needed only
+ * for the sides some column uses. An index out of range of its column, or a
+ * count above max_pairs, sets REL_DEV_BADARG (the element is written as 0, the
+ * count is clamped). Host-side errors: REL_INVALID_ARG (null or misaligned
+ * pointer, bad elem_bytes or side, n_cols outside 1..8), REL_UNSUPPORTED
+ * (max_pairs >= 2^31). Stream-ordered, no synchronisation. */
+rel_status rel_join_gather(rel_ctx* ctx, const int32_t* fact_idx, const int32_t* dim_idx, const int64_t* d_n_pairs,
+                           int64_t max_pairs, const rel_gather_col* cols, int32_t n_cols);
+
+/* ------------------------------------------------------------------------------------------------------------------
  * Group-by (cuDF's single_pass_shmem_aggs_kernel of Section 7: per-workgroup
  * aggregation in LDS, one device-memory update per group and workgroup).
  */

@@ -55,6 +55,8 @@ def lib():
         L.or_filter_compact.restype = i64
         L.or_join_probe.argtypes = [i64, vp, vp, i64, vp, vp, vp, vp, i64]
         L.or_join_probe.restype = i64
+        L.or_join_gather.argtypes = [i64, vp, vp, i64, i32, vp]
+        L.or_join_gather.restype = i64
         L.or_groupby_agg.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, i64]
         L.or_groupby_agg.restype = i64
         L.or_hll_registers.argtypes = [i64, vp, vp]
@@ -123,6 +125,16 @@ def join_probe(fk, sel, pk, payload=None):
     op = np.empty(max(n, 1), np.int32)
     c = _check(lib().or_join_probe(n, _p(fk), _p(sel), pk.shape[0], _p(pk), _p(payload), _p(oi), _p(op), oi.shape[0]))
     return oi[:c].copy(), op[:c].copy()
+
+
+def join_gather(idx, src) -> np.ndarray:
+    """dst[i] = src[idx[i]] (join-output materialisation, Section 7's gather),
+    element by element in plain C++; any fixed-width numpy dtype."""
+    idx = _c(idx, np.int32)
+    src = np.ascontiguousarray(src)
+    dst = np.empty(idx.shape[0], src.dtype)
+    _check(lib().or_join_gather(idx.shape[0], _p(idx), _p(src), src.shape[0], src.dtype.itemsize, _p(dst)))
+    return dst
 
 
 def groupby_agg(key, price, qty, sel=None):

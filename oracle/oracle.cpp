@@ -24,6 +24,9 @@
 // std::sort. A second, independent brute-force implementation (nested loop
 // over fact x dim, linear-scan group list) pins the first on tiny inputs.
 //
+// Join output can also be materialised: the gather out[i] = in[map[i]] of
+// selected fact and dim columns through the probe's row pairs.
+//
 // The planner's sketch (HyperLogLog registers of Flajolet, Fusy, Gandouet and
 // Meunier, AofA 2007, and the 40 sample statistics) is also here, so the GPU
 // sketch can be compared register by register.
@@ -207,6 +210,24 @@ int64_t or_join_probe(int64_t n, const int32_t* fk, const int32_t* sel, int64_t 
     ++c;
   }
   return c;
+}
+
+// Materialisation of join output (the gather out[i] = in[map[i]] of the
+// transform kernel, Section 7): dst[i] = src[idx[i]] for i in [0, n), elements
+// of elem_bytes bytes copied as bytes. An index outside [0, src_rows) is an
+// error (ERR_INVALID), as is an element size other than 1, 2, 4 or 8.
+int64_t or_join_gather(int64_t n, const int32_t* idx, const void* src, int64_t src_rows, int32_t elem_bytes,
+                       void* dst) {
+  if (n < 0 || src_rows < 0 || (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8))
+    return ERR_INVALID;
+  const unsigned char* s = static_cast<const unsigned char*>(src);
+  unsigned char* d = static_cast<unsigned char*>(dst);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t row = idx[i];
+    if (row < 0 || row >= src_rows) return ERR_INVALID;
+    std::memcpy(d + i * elem_bytes, s + row * elem_bytes, (size_t)elem_bytes);
+  }
+  return n;
 }
 
 // Hash group-by over the rows sel[0..n) (or 0..n-1): key, SUM(price), SUM(qty), COUNT.

@@ -46,6 +46,13 @@ class Fact(ctypes.Structure):
     _fields_ = [("fk", _vp), ("price_cents", _vp), ("qty", _vp), ("day", _vp), ("flag", _vp), ("n", _i64)]
 
 
+class GatherCol(ctypes.Structure):
+    _fields_ = [("src", _vp), ("dst", _vp), ("src_rows", _i64), ("elem_bytes", _i32), ("side", _i32)]
+
+
+SIDE = {"fact": 0, "dim": 1}
+
+
 class Dim(ctypes.Structure):
     _fields_ = [("pk", _vp), ("prio", _vp), ("grp", _vp), ("m", _i64)]
 
@@ -106,6 +113,7 @@ def lib():
         L.rel_join_build.argtypes = [_vp, _vp, _vp, _i64, P(TableOpts), P(_vp)]
         L.rel_join_table_destroy.argtypes = [_vp]
         L.rel_join_probe.argtypes = [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp]
+        L.rel_join_gather.argtypes = [_vp, _vp, _vp, _vp, _i64, P(GatherCol), _i32]
         L.rel_groupby_agg.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, P(TableOpts), P(GroupsOut)]
         L.rel_filter_join_agg.argtypes = [_vp, P(Fact), P(Dim), P(Query), P(Plan), P(GroupsOut), P(Stats)]
         L.rel_ctx_enable_timing.argtypes = [_vp, ctypes.c_int]
@@ -123,7 +131,7 @@ def lib():
         L.rel_planner_plan.argtypes = [_vp, P(Fact), P(Dim), P(Query), _vp, _vp, _i32, P(Plan), _vp]
         L.rel_planner_destroy.argtypes = [_vp]
         for name in ("rel_ctx_create", "rel_ctx_destroy", "rel_ctx_set_stream", "rel_ctx_sync", "rel_filter_compact",
-                     "rel_join_build", "rel_join_table_destroy", "rel_join_probe", "rel_groupby_agg",
+                     "rel_join_build", "rel_join_table_destroy", "rel_join_probe", "rel_join_gather", "rel_groupby_agg",
                      "rel_filter_join_agg", "rel_ctx_enable_timing", "rel_ctx_kernel_times", "rel_batch_create",
                      "rel_batch_run", "rel_batch_sync", "rel_batch_destroy", "rel_sketch", "rel_mlp_forward",
                      "rel_mlp_backward", "rel_mlp_adam_step", "rel_planner_create", "rel_planner_plan",
@@ -206,6 +214,29 @@ class Context:
         h = ctypes.c_void_p()
         self.check(lib().rel_join_build(self.h, _ptr(pk), _ptr(payload), pk.numel(), ctypes.byref(opts), ctypes.byref(h)))
         return JoinTable(self, h, pk, payload)
+
+    def join_gather(self, fact_idx: torch.Tensor | None, dim_idx: torch.Tensor | None, d_count: torch.Tensor,
+                    columns: list, max_pairs: int | None = None) -> list:
+        """Materialise joined rows: for each (src, side) in columns ("fact" or
+        "dim"), dst[i] = src[fact_idx[i]] or src[dim_idx[i]] for i < d_count
+        (a device int64, e.g. a probe's count). Returns the dst tensors
+        (max_pairs rows each; rows past the count are left unwritten)."""
+        _dev_check(fact_idx, torch.int32, "fact_idx")
+        _dev_check(dim_idx, torch.int32, "dim_idx")
+        _dev_check(d_count, torch.int64, "d_count")
+        if max_pairs is None:
+            max_pairs = max(t.numel() for t in (fact_idx, dim_idx) if t is not None)
+        cols = (GatherCol * len(columns))()
+        outs = []
+        for c, (src, side) in enumerate(columns):
+            if not src.is_cuda or not src.is_contiguous():
+                raise ValueError("gather sources must be contiguous device tensors")
+            dst = torch.empty(max(max_pairs, 1), dtype=src.dtype, device=src.device)
+            cols[c] = GatherCol(_ptr(src), _ptr(dst), src.numel(), src.element_size(), SIDE[side])
+            outs.append(dst)
+        self.check(lib().rel_join_gather(self.h, _ptr(fact_idx), _ptr(dim_idx), _ptr(d_count), int(max_pairs), cols,
+                                         len(columns)))
+        return outs
 
     def groupby_agg(self, key: torch.Tensor, price: torch.Tensor, qty: torch.Tensor, sel: torch.Tensor | None = None,
                     capacity_hint: int = 0, placement: str = "auto", out_cap: int | None = None):
@@ -380,8 +411,10 @@ class JoinTable:
         self.ctx, self.h = ctx, h
         self._keep = (pk, payload)
 
-    def probe(self, fk: torch.Tensor, sel: torch.Tensor | None = None):
-        """(fact_idx, payload) pairs of matching probe rows, unordered. Returns (fact_idx, payload, count)."""
+    def probe(self, fk: torch.Tensor, sel: torch.Tensor | None = None, sync: bool = True):
+        """(fact_idx, payload) pairs of matching probe rows, unordered. Returns
+        (fact_idx, payload, count); with sync=False the full-size buffers and
+        the device count tensor instead (no host synchronisation)."""
         _dev_check(fk, torch.int32, "fk")
         _dev_check(sel, torch.int32, "sel")
         n = sel.numel() if sel is not None else fk.numel()
@@ -390,6 +423,8 @@ class JoinTable:
         cnt = torch.empty(1, dtype=torch.int64, device=fk.device)
         self.ctx.check(lib().rel_join_probe(self.ctx.h, self.h, _ptr(fk), _ptr(sel), n, _ptr(oi), _ptr(op), oi.numel(),
                                             _ptr(cnt)))
+        if not sync:
+            return oi, op, cnt
         c = int(cnt.item())
         return oi[:c], op[:c], c
 

@@ -190,3 +190,39 @@ def test_groupby_agg_matches_numpy():
     np.add.at(sq, inv, qty[sel].astype(np.int64))
     assert g["sum_qty"].tolist() == sq.tolist()
     assert g["count"].tolist() == np.bincount(inv).tolist()
+
+
+# -- join-output materialisation (gather) ---------------------------------------------------------------------------------
+
+def test_join_gather_hand_example():
+    # worked by hand: rows 3, 0, 0, 2 of [10, 20, 30, 40]
+    src = np.array([10, 20, 30, 40], np.int64)
+    assert oracle.join_gather(np.array([3, 0, 0, 2], np.int32), src).tolist() == [40, 10, 10, 30]
+    assert oracle.join_gather(np.array([1, 1, 0], np.int32), np.array([7, -3], np.int8)).tolist() == [-3, -3, 7]
+    assert oracle.join_gather(np.zeros(0, np.int32), src).shape == (0,)
+
+
+@pytest.mark.parametrize("dtype", [np.int8, np.int16, np.int32, np.int64, np.float64])
+def test_join_gather_equals_numpy_take(dtype):
+    rng = np.random.default_rng(5)
+    src = rng.integers(-100, 100, size=1001).astype(dtype)
+    idx = rng.integers(0, 1001, size=5000).astype(np.int32)
+    assert np.array_equal(oracle.join_gather(idx, src), np.take(src, idx))
+
+
+def test_join_gather_identity_and_join_keys():
+    rng = np.random.default_rng(6)
+    src = rng.integers(-(2 ** 31), 2 ** 31 - 1, size=777).astype(np.int32)
+    assert np.array_equal(oracle.join_gather(np.arange(777, dtype=np.int32), src), src)
+    # through a probe: the fact side's fk and the dim side's pk agree pair by pair
+    pk = datagen.permutation(2000, 0, 7, 1)
+    fk = rng.integers(-500, 2500, size=9000).astype(np.int32)
+    fi, di = oracle.join_probe(fk, None, pk)
+    assert np.array_equal(oracle.join_gather(fi, fk), oracle.join_gather(di, pk))
+
+
+def test_join_gather_rejects_out_of_range_rows():
+    src = np.arange(10, dtype=np.int32)
+    for bad in (10, -1):
+        with pytest.raises(oracle.OracleError):
+            oracle.join_gather(np.array([0, bad], np.int32), src)
