@@ -95,6 +95,55 @@ rel_status rel_filter_compact(rel_ctx* ctx, const int32_t* col, int64_t n, rel_c
                               int32_t* out_idx, int64_t out_cap, int64_t* d_out_count);
 
 /* ------------------------------------------------------------------------------------------------------------------
+ * General selection predicates (the compute-column step widened): a
+ * conjunction of up to 8 terms over typed columns. Section 7 finds cuDF's
+ * expression interpreter (compute_column_kernel) spending so many
+ * instructions that a kernel with sequential accesses turns instruction-bound
+ * on the high-bandwidth GPU. Here a predicate is either compiled, as a kernel
+ * generated for it and built at run time with hipRTC (literals and column
+ * types fixed in the code, each column read with 16-byte loads), or
+ * interpreted by one fixed kernel that walks the term list for every row. Both
+ * produce the stable selection vector of rel_filter_compact.
+ */
+typedef enum rel_dtype {
+  REL_DT_I8 = 0, REL_DT_I16 = 1, REL_DT_I32 = 2, REL_DT_I64 = 3, REL_DT_F32 = 4, REL_DT_F64 = 5
+} rel_dtype;
+typedef enum rel_pred_op {
+  REL_OP_LT = 0, REL_OP_LE = 1, REL_OP_GT = 2, REL_OP_GE = 3, REL_OP_EQ = 4, REL_OP_NE = 5,
+  REL_OP_BETWEEN = 6, /* lo <= x <= hi */
+  REL_OP_IN = 7       /* x equals one of the values */
+} rel_pred_op;
+typedef enum rel_pred_mode { REL_PRED_COMPILED = 0, REL_PRED_INTERPRETED = 1 } rel_pred_mode;
+#define REL_PRED_MAX_TERMS 8
+#define REL_PRED_MAX_VALUES 16
+
+typedef struct rel_pred_term {
+  int32_t column;   /* index into the columns array given to rel_pred_filter */
+  int32_t dtype;    /* rel_dtype of that column */
+  int32_t op;       /* rel_pred_op */
+  int32_t n_values; /* 1 for the comparisons, 2 for BETWEEN (lo, hi), 1..16 for IN */
+  int64_t ivalues[REL_PRED_MAX_VALUES]; /* literals for integer columns (the value is compared as int64) */
+  double fvalues[REL_PRED_MAX_VALUES];  /* literals for f32/f64 columns (compared as double; NaN fails every op but NE) */
+} rel_pred_term;
+
+typedef struct rel_pred rel_pred;
+
+/* Validate the terms and prepare the predicate: mode COMPILED generates and
+ * compiles a kernel for it (a few hundred milliseconds; the device's own
+ * architecture), INTERPRETED prepares the interpreter. The predicate is owned
+ * by the caller through *out. Errors: REL_INVALID_ARG (no terms or more than
+ * 8, bad column index, dtype, op or value count), REL_HIP (compilation or
+ * module load failed; rel_last_error has the compiler log). */
+rel_status rel_pred_create(rel_ctx* ctx, const rel_pred_term* terms, int32_t n_terms, int32_t mode, rel_pred** out);
+/* Stable ascending indices of the rows i in [0, n) for which every term holds:
+ * columns is a host array of n_columns device pointers (each 16-byte aligned,
+ * at least n elements of its term's dtype; columns no term uses may be NULL).
+ * *d_out_count (device) = number selected; out_cap >= n (else REL_CAPACITY). */
+rel_status rel_pred_filter(rel_pred* pred, const void* const* columns, int32_t n_columns, int64_t n, int32_t* out_idx,
+                           int64_t out_cap, int64_t* d_out_count);
+rel_status rel_pred_destroy(rel_pred* pred);
+
+/* ------------------------------------------------------------------------------------------------------------------
  * Hash join (cuDF's insert_if_n build and count/retrieve probe kernels of
  * Section 7). Open addressing with linear probing over a power-of-two table of
  * packed 64-bit slots {key, payload}.

@@ -55,6 +55,8 @@ def lib():
         L.or_filter_compact.restype = i64
         L.or_join_probe.argtypes = [i64, vp, vp, i64, vp, vp, vp, vp, i64]
         L.or_join_probe.restype = i64
+        L.or_pred_filter.argtypes = [i64, vp, i32, vp, i32, vp, i64]
+        L.or_pred_filter.restype = i64
         L.or_join_gather.argtypes = [i64, vp, vp, i64, i32, vp]
         L.or_join_gather.restype = i64
         L.or_groupby_agg.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, i64]
@@ -125,6 +127,36 @@ def join_probe(fk, sel, pk, payload=None):
     op = np.empty(max(n, 1), np.int32)
     c = _check(lib().or_join_probe(n, _p(fk), _p(sel), pk.shape[0], _p(pk), _p(payload), _p(oi), _p(op), oi.shape[0]))
     return oi[:c].copy(), op[:c].copy()
+
+
+PRED_OPS = {"lt": 0, "le": 1, "gt": 2, "ge": 3, "eq": 4, "ne": 5, "between": 6, "in": 7}
+_PRED_DT = {np.dtype(np.int8): 0, np.dtype(np.int16): 1, np.dtype(np.int32): 2, np.dtype(np.int64): 3,
+            np.dtype(np.float32): 4, np.dtype(np.float64): 5}
+_TERM = np.dtype([("column", "<i4"), ("dtype", "<i4"), ("op", "<i4"), ("n_values", "<i4"), ("iv", "<i8", 16),
+                  ("fv", "<f8", 16)])
+
+
+def pred_filter(columns, terms) -> np.ndarray:
+    """Ascending rows where every term holds. columns: list of numpy arrays (one
+    length n; None for unused slots); terms: dicts column / op / values, the
+    column's dtype decides integer (int64) or floating (double) comparison."""
+    cols = [None if c is None else np.ascontiguousarray(c) for c in columns]
+    n = next(c.shape[0] for c in cols if c is not None)
+    t = np.zeros(len(terms), _TERM)
+    for i, d in enumerate(terms):
+        col = cols[d["column"]]
+        fp = col.dtype.kind == "f"
+        t[i]["column"], t[i]["dtype"], t[i]["op"] = d["column"], _PRED_DT[col.dtype], PRED_OPS[d["op"]]
+        t[i]["n_values"] = len(d["values"])
+        for j, v in enumerate(d["values"]):
+            if fp:
+                t[i]["fv"][j] = v
+            else:
+                t[i]["iv"][j] = v
+    ptrs = (ctypes.c_void_p * len(cols))(*[None if c is None else c.ctypes.data for c in cols])
+    out = np.empty(max(n, 1), np.int32)
+    c = _check(lib().or_pred_filter(n, ptrs, len(cols), t.ctypes.data, len(terms), _p(out), out.shape[0]))
+    return out[:c].copy()
 
 
 def join_gather(idx, src) -> np.ndarray:

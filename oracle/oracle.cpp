@@ -212,6 +212,66 @@ int64_t or_join_probe(int64_t n, const int32_t* fk, const int32_t* sel, int64_t 
   return c;
 }
 
+// General selection predicate: row i passes when every term holds for it. A
+// term compares its column's value (integers widened to int64, floating point
+// to double) with its literals: <, <=, >, >=, ==, != against one literal,
+// BETWEEN lo and hi (both inclusive), or IN a list of up to 16 values (the
+// selection of the compute-column step, Section 7, over typed columns).
+struct OrPredTerm {
+  int32_t column, dtype, op, n_values;  // dtype: i8 i16 i32 i64 f32 f64; op: lt le gt ge eq ne between in
+  int64_t iv[16];
+  double fv[16];
+};
+
+static bool or_term_holds(const OrPredTerm& t, const void* col, int64_t r) {
+  bool fp = false;
+  int64_t x = 0;
+  double y = 0.0;
+  switch (t.dtype) {
+    case 0: x = static_cast<const int8_t*>(col)[r]; break;
+    case 1: x = static_cast<const int16_t*>(col)[r]; break;
+    case 2: x = static_cast<const int32_t*>(col)[r]; break;
+    case 3: x = static_cast<const int64_t*>(col)[r]; break;
+    case 4: fp = true; y = static_cast<const float*>(col)[r]; break;
+    default: fp = true; y = static_cast<const double*>(col)[r]; break;
+  }
+  auto cmp = [&](int op, int j) {
+    switch (op) {
+      case 0: return fp ? y < t.fv[j] : x < t.iv[j];
+      case 1: return fp ? y <= t.fv[j] : x <= t.iv[j];
+      case 2: return fp ? y > t.fv[j] : x > t.iv[j];
+      case 3: return fp ? y >= t.fv[j] : x >= t.iv[j];
+      case 4: return fp ? y == t.fv[j] : x == t.iv[j];
+      default: return fp ? y != t.fv[j] : x != t.iv[j];
+    }
+  };
+  if (t.op <= 5) return cmp(t.op, 0);
+  if (t.op == 6) return cmp(3, 0) && cmp(1, 1);
+  for (int j = 0; j < t.n_values; ++j)
+    if (cmp(4, j)) return true;
+  return false;
+}
+
+int64_t or_pred_filter(int64_t n, const void* const* cols, int32_t ncols, const OrPredTerm* terms, int32_t nterms,
+                       int32_t* out, int64_t out_cap) {
+  if (n < 0 || nterms < 1) return ERR_INVALID;
+  for (int32_t i = 0; i < nterms; ++i) {
+    const OrPredTerm& t = terms[i];
+    if (t.column < 0 || t.column >= ncols || !cols[t.column] || t.dtype < 0 || t.dtype > 5 || t.op < 0 || t.op > 7 ||
+        t.n_values < 1 || t.n_values > 16)
+      return ERR_INVALID;
+  }
+  int64_t c = 0;
+  for (int64_t r = 0; r < n; ++r) {
+    bool ok = true;
+    for (int32_t i = 0; i < nterms && ok; ++i) ok = or_term_holds(terms[i], cols[terms[i].column], r);
+    if (!ok) continue;
+    if (c >= out_cap) return ERR_CAPACITY;
+    out[c++] = (int32_t)r;
+  }
+  return c;
+}
+
 // Materialisation of join output (the gather out[i] = in[map[i]] of the
 // transform kernel, Section 7): dst[i] = src[idx[i]] for i in [0, n), elements
 // of elem_bytes bytes copied as bytes. An index outside [0, src_rows) is an

@@ -1,0 +1,348 @@
+// General selection predicates: a conjunction of typed terms, compiled or
+// interpreted (declared in rel.h).
+//
+// Both modes are one program text built with hipRTC for the device it runs
+// on: a single-pass stable compaction (Merrill and Garland's decoupled
+// look-back, tiles taken by ticket so every awaited tile belongs to a running
+// workgroup, as in rel_filter.hip) around a function that yields, for one
+// thread's 16 consecutive rows, the bit mask of the rows that pass.
+//   * compiled: the mask function is generated for the predicate. Each term
+//     reads its column's 16 elements with 16-byte loads and compares them
+//     against literals written into the code; no branch depends on the term
+//     list.
+//   * interpreted: the mask function walks a term list in device memory for
+//     every row, dispatching on the column type and the operator (the
+//     expression-interpretation scheme Section 7 measures in cuDF).
+#include <hip/hiprtc.h>
+
+#include <cinttypes>
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "rel_host.h"
+
+namespace {
+
+// The compaction around the mask function; `tile_bits` is defined before it.
+const char* kSkeleton = R"SKEL(
+typedef struct {
+  int column, dtype, op, n_values;
+  long long iv[16];
+  double fv[16];
+} Term;
+typedef struct { const void* c[8]; } Cols;
+
+#define BLOCK 256
+#define IPT 16
+#define TILE (BLOCK * IPT)
+#define FLAG_AGG (1ull << 62)
+#define FLAG_INCL (2ull << 62)
+#define VAL_MASK ((1ull << 62) - 1)
+
+// 16 consecutive elements of T from a 16-byte aligned address.
+template <class T>
+__device__ __forceinline__ void load16(const T* p, T (&v)[16]) {
+  const uint4* q = reinterpret_cast<const uint4*>(p);
+  uint4 w[sizeof(T)];
+#pragma unroll
+  for (int j = 0; j < (int)sizeof(T); ++j) w[j] = q[j];
+  __builtin_memcpy(v, w, sizeof(w));
+}
+
+__device__ __forceinline__ unsigned tile_bits(const Cols& cols, long long r0, long long n, const Term* terms, int nterms);
+
+extern "C" __global__ __launch_bounds__(BLOCK) void k_pred_filter(Cols cols, long long n, int* out,
+                                                                  unsigned long long* state, long long* ticket,
+                                                                  long long* d_count, long long ntiles,
+                                                                  const Term* terms, int nterms) {
+  __shared__ long long s_tile;
+  __shared__ long long s_excl;
+  __shared__ unsigned s_wave[BLOCK / 64];
+  if (threadIdx.x == 0) s_tile = (long long)atomicAdd((unsigned long long*)ticket, 1ull);
+  __syncthreads();
+  const long long tile = s_tile;
+  const long long r0 = tile * TILE + (long long)threadIdx.x * IPT;
+  const unsigned bits = r0 < n ? tile_bits(cols, r0, n, terms, nterms) : 0u;
+  const unsigned c = __popc(bits);
+  const unsigned lane = __lane_id(), wave = threadIdx.x / 64;
+  unsigned incl = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned t = __shfl_up(incl, o, 64);
+    if (lane >= (unsigned)o) incl += t;
+  }
+  if (lane == 63) s_wave[wave] = incl;
+  __syncthreads();
+  unsigned wave_off = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < BLOCK / 64; ++w) {
+    const unsigned t = s_wave[w];
+    wave_off += (unsigned)w < wave ? t : 0u;
+    total += t;
+  }
+  if (threadIdx.x == 0) {
+    if (tile == 0) {
+      __hip_atomic_store(&state[0], FLAG_INCL | (unsigned long long)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_excl = 0;
+    } else {
+      __hip_atomic_store(&state[tile], FLAG_AGG | (unsigned long long)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned long long acc = 0;
+      long long p = tile - 1;
+      for (;;) {
+        const unsigned long long st = __hip_atomic_load(&state[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long flag = st & ~VAL_MASK;
+        if (flag == 0) {
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        acc += st & VAL_MASK;
+        if (flag == FLAG_INCL) break;
+        --p;
+      }
+      __hip_atomic_store(&state[tile], FLAG_INCL | (acc + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_excl = (long long)acc;
+    }
+    if (tile == ntiles - 1) *d_count = s_excl + total;
+  }
+  __syncthreads();
+  long long o = s_excl + wave_off + incl - c;
+  for (int k = 0; k < IPT; ++k)
+    if (bits & (1u << k)) out[o++] = (int)(r0 + k);
+}
+)SKEL";
+
+// The interpreter's mask function: one row at a time, the term list walked per row.
+const char* kInterpreter = R"INTERP(
+__device__ __forceinline__ bool interp_term(const Term& t, const Cols& cols, long long r) {
+  long long iv = 0;
+  double fv = 0.0;
+  const bool fp = t.dtype >= 4;
+  switch (t.dtype) {
+    case 0: iv = ((const signed char*)cols.c[t.column])[r]; break;
+    case 1: iv = ((const short*)cols.c[t.column])[r]; break;
+    case 2: iv = ((const int*)cols.c[t.column])[r]; break;
+    case 3: iv = ((const long long*)cols.c[t.column])[r]; break;
+    case 4: fv = (double)((const float*)cols.c[t.column])[r]; break;
+    default: fv = ((const double*)cols.c[t.column])[r]; break;
+  }
+  switch (t.op) {
+    case 0: return fp ? fv < t.fv[0] : iv < t.iv[0];
+    case 1: return fp ? fv <= t.fv[0] : iv <= t.iv[0];
+    case 2: return fp ? fv > t.fv[0] : iv > t.iv[0];
+    case 3: return fp ? fv >= t.fv[0] : iv >= t.iv[0];
+    case 4: return fp ? fv == t.fv[0] : iv == t.iv[0];
+    case 5: return fp ? fv != t.fv[0] : iv != t.iv[0];
+    case 6: return fp ? (fv >= t.fv[0] && fv <= t.fv[1]) : (iv >= t.iv[0] && iv <= t.iv[1]);
+    default:
+      for (int j = 0; j < t.n_values; ++j)
+        if (fp ? fv == t.fv[j] : iv == t.iv[j]) return true;
+      return false;
+  }
+}
+
+__device__ __forceinline__ unsigned tile_bits(const Cols& cols, long long r0, long long n, const Term* terms, int nterms) {
+  unsigned bits = 0;
+  for (int k = 0; k < IPT; ++k) {
+    const long long r = r0 + k;
+    if (r >= n) break;
+    bool ok = true;
+    for (int t = 0; t < nterms && ok; ++t) ok = interp_term(terms[t], cols, r);
+    bits |= (unsigned)ok << k;
+  }
+  return bits;
+}
+)INTERP";
+
+const char* kTypeName[6] = {"signed char", "short", "int", "long long", "float", "double"};
+
+std::string int_literal(int64_t v) {
+  if (v == INT64_MIN) return "(-9223372036854775807LL - 1)";
+  char b[32];
+  std::snprintf(b, sizeof b, "%" PRId64 "LL", v);
+  return b;
+}
+
+std::string fp_literal(double v) {
+  if (std::isnan(v)) return "__builtin_nan(\"\")";
+  if (std::isinf(v)) return v > 0 ? "__builtin_inf()" : "(-__builtin_inf())";
+  char b[64];
+  std::snprintf(b, sizeof b, "%a", v);  // hexadecimal: the exact double
+  return b;
+}
+
+// The comparison of element expression `x` (already converted to long long or
+// double) for one term.
+std::string term_expr(const rel_pred_term& t, const std::string& x) {
+  const bool fp = t.dtype >= REL_DT_F32;
+  auto lit = [&](int j) { return fp ? fp_literal(t.fvalues[j]) : int_literal(t.ivalues[j]); };
+  static const char* cmp[6] = {"<", "<=", ">", ">=", "==", "!="};
+  if (t.op <= REL_OP_NE) return "(" + x + " " + cmp[t.op] + " " + lit(0) + ")";
+  if (t.op == REL_OP_BETWEEN) return "(" + x + " >= " + lit(0) + " && " + x + " <= " + lit(1) + ")";
+  std::string e = "(";
+  for (int j = 0; j < t.n_values; ++j) e += (j ? " || " : "") + x + " == " + lit(j);
+  return e + ")";
+}
+
+std::string compiled_mask(const rel_pred_term* terms, int32_t n_terms) {
+  std::string s =
+      "__device__ __forceinline__ unsigned tile_bits(const Cols& cols, long long r0, long long n, const Term*, int) {\n"
+      "  unsigned bits = 0xffffu;\n"
+      "  const bool full = r0 + IPT <= n;\n";
+  for (int32_t i = 0; i < n_terms; ++i) {
+    const rel_pred_term& t = terms[i];
+    const std::string T = kTypeName[t.dtype];
+    const std::string conv = t.dtype >= REL_DT_F32 ? "(double)" : "(long long)";
+    s += "  {\n    const " + T + "* p = (const " + T + "*)cols.c[" + std::to_string(t.column) + "];\n";
+    s += "    unsigned m = 0;\n";
+    s += "    if (full) {\n      " + T + " v[16];\n      load16<" + T + ">(p + r0, v);\n";
+    s += "#pragma unroll\n      for (int k = 0; k < 16; ++k) m |= (unsigned)" + term_expr(t, conv + "v[k]") + " << k;\n";
+    s += "    } else {\n      for (int k = 0; k < 16; ++k)\n";
+    s += "        if (r0 + k < n) m |= (unsigned)" + term_expr(t, conv + "p[r0 + k]") + " << k;\n    }\n";
+    s += "    bits &= m;\n  }\n";
+  }
+  s += "  if (r0 + IPT > n) bits &= (1u << (unsigned)(n - r0)) - 1u;\n  return bits;\n}\n";
+  return s;
+}
+
+}  // namespace
+
+struct rel_pred {
+  rel_ctx* ctx = nullptr;
+  int mode = 0;
+  int n_terms = 0;
+  int max_column = -1;
+  std::vector<int> col_dtype;  // dtype each used column must have (-1: unused)
+  hipModule_t module = nullptr;
+  hipFunction_t fn = nullptr;
+  void* d_terms = nullptr;  // the term list, for the interpreter
+};
+
+namespace {
+
+void free_pred(rel_pred* p) {
+  if (!p) return;
+  if (p->module) (void)hipModuleUnload(p->module);
+  if (p->d_terms) (void)hipFree(p->d_terms);
+  delete p;
+}
+
+rel_status compile(rel_ctx* ctx, const std::string& src, hipModule_t* mod, hipFunction_t* fn) {
+  hipDeviceProp_t prop;
+  REL_HIP_CHECK(ctx, hipGetDeviceProperties(&prop, ctx->device));
+  const std::string arch = std::string("--offload-arch=") + prop.gcnArchName;
+  const char* opts[] = {arch.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.c_str(), "rel_pred.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+    return relh::fail(ctx, REL_HIP, "rel_pred_create: hiprtcCreateProgram failed");
+  const hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+  if (r != HIPRTC_SUCCESS) {
+    size_t n = 0;
+    hiprtcGetProgramLogSize(prog, &n);
+    std::string log(n, '\0');
+    if (n) hiprtcGetProgramLog(prog, &log[0]);
+    hiprtcDestroyProgram(&prog);
+    return relh::fail(ctx, REL_HIP, "rel_pred_create: compilation failed: %.900s", log.c_str());
+  }
+  size_t size = 0;
+  hiprtcGetCodeSize(prog, &size);
+  std::vector<char> code(size);
+  hiprtcGetCode(prog, code.data());
+  hiprtcDestroyProgram(&prog);
+  REL_HIP_CHECK(ctx, hipModuleLoadData(mod, code.data()));
+  REL_HIP_CHECK(ctx, hipModuleGetFunction(fn, *mod, "k_pred_filter"));
+  return REL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rel_status rel_pred_create(rel_ctx* ctx, const rel_pred_term* terms, int32_t n_terms, int32_t mode, rel_pred** out) {
+  if (!ctx || !terms || !out || n_terms < 1 || n_terms > REL_PRED_MAX_TERMS ||
+      (mode != REL_PRED_COMPILED && mode != REL_PRED_INTERPRETED))
+    return relh::fail(ctx, REL_INVALID_ARG, "rel_pred_create: bad argument");
+  std::vector<int> col_dtype;
+  for (int32_t i = 0; i < n_terms; ++i) {
+    const rel_pred_term& t = terms[i];
+    const bool ok_n = t.op <= REL_OP_NE ? t.n_values == 1 : t.op == REL_OP_BETWEEN ? t.n_values == 2
+                                                                                 : t.n_values >= 1 && t.n_values <= REL_PRED_MAX_VALUES;
+    if (t.column < 0 || t.column >= 8 || t.dtype < REL_DT_I8 || t.dtype > REL_DT_F64 || t.op < REL_OP_LT ||
+        t.op > REL_OP_IN || !ok_n)
+      return relh::fail(ctx, REL_INVALID_ARG, "rel_pred_create: term %d invalid", i);
+    if ((int)col_dtype.size() <= t.column) col_dtype.resize(t.column + 1, -1);
+    if (col_dtype[t.column] != -1 && col_dtype[t.column] != t.dtype)
+      return relh::fail(ctx, REL_INVALID_ARG, "rel_pred_create: column %d given two types", t.column);
+    col_dtype[t.column] = t.dtype;
+  }
+  rel_pred* p = new rel_pred();
+  p->ctx = ctx;
+  p->mode = mode;
+  p->n_terms = n_terms;
+  p->col_dtype = col_dtype;
+  p->max_column = (int)col_dtype.size() - 1;
+  const std::string src =
+      std::string(kSkeleton) + (mode == REL_PRED_COMPILED ? compiled_mask(terms, n_terms) : std::string(kInterpreter));
+  rel_status s = compile(ctx, src, &p->module, &p->fn);
+  if (s == REL_OK && mode == REL_PRED_INTERPRETED) {
+    hipError_t e = hipMalloc(&p->d_terms, sizeof(rel_pred_term) * n_terms);
+    if (e == hipSuccess) e = hipMemcpy(p->d_terms, terms, sizeof(rel_pred_term) * n_terms, hipMemcpyHostToDevice);
+    if (e != hipSuccess) s = relh::hip_fail(ctx, e, "rel_pred_create: term list");
+  }
+  if (s != REL_OK) {
+    free_pred(p);
+    return s;
+  }
+  *out = p;
+  return REL_OK;
+}
+
+rel_status rel_pred_filter(rel_pred* p, const void* const* columns, int32_t n_columns, int64_t n, int32_t* out_idx,
+                           int64_t out_cap, int64_t* d_out_count) {
+  if (!p) return REL_INVALID_ARG;
+  rel_ctx* ctx = p->ctx;
+  if (!columns || n < 0 || !d_out_count || (n > 0 && !out_idx) || n_columns <= p->max_column || n_columns > 8)
+    return relh::fail(ctx, REL_INVALID_ARG, "rel_pred_filter: bad argument");
+  if (n >= (1ll << 31)) return relh::fail(ctx, REL_UNSUPPORTED, "rel_pred_filter: n >= 2^31");
+  if (out_cap < n) return relh::fail(ctx, REL_CAPACITY, "rel_pred_filter: out_cap < n");
+  struct {
+    const void* c[8];
+  } cols{};
+  for (int c = 0; c < n_columns; ++c) {
+    const bool used = c < (int)p->col_dtype.size() && p->col_dtype[c] >= 0;
+    if (used && n > 0 && (!columns[c] || !relh::aligned16(columns[c])))
+      return relh::fail(ctx, REL_INVALID_ARG, "rel_pred_filter: column %d null or not 16-byte aligned", c);
+    cols.c[c] = columns[c];
+  }
+  rel_status s = relh::ensure_counters(ctx);
+  if (s != REL_OK) return s;
+  if (n == 0) return relh::fill_u64(ctx, d_out_count, 1, 0);
+  constexpr int64_t kTileRows = 256 * 16;
+  long long ntiles = (n + kTileRows - 1) / kTileRows;
+  void* st;
+  if ((s = relh::scratch(ctx, SCR_SCAN_STATE, (size_t)ntiles * 8, &st)) != REL_OK) return s;
+  int64_t* ticket = relh::counters(ctx) + CNT_TICKET;
+  if ((s = relh::fill_u64(ctx, st, (size_t)ntiles, 0)) != REL_OK) return s;
+  if ((s = relh::fill_u64(ctx, ticket, 1, 0)) != REL_OK) return s;
+  long long nn = n;
+  int* out = out_idx;
+  unsigned long long* state = (unsigned long long*)st;
+  long long* tk = (long long*)ticket;
+  long long* dc = (long long*)d_out_count;
+  const void* terms = p->d_terms;
+  int nterms = p->n_terms;
+  void* args[] = {&cols, &nn, &out, &state, &tk, &dc, &ntiles, &terms, &nterms};
+  relh::KernelTimer kt(ctx, p->mode == REL_PRED_COMPILED ? "pred_compiled" : "pred_interpreted");
+  REL_HIP_CHECK(ctx, hipModuleLaunchKernel(p->fn, (unsigned)ntiles, 1, 1, 256, 1, 1, 0, ctx->stream, args, nullptr));
+  return REL_OK;
+}
+
+rel_status rel_pred_destroy(rel_pred* p) {
+  if (!p) return REL_INVALID_ARG;
+  (void)hipStreamSynchronize(p->ctx->stream);
+  free_pred(p);
+  return REL_OK;
+}
+
+}  // extern "C"

@@ -46,6 +46,16 @@ class Fact(ctypes.Structure):
     _fields_ = [("fk", _vp), ("price_cents", _vp), ("qty", _vp), ("day", _vp), ("flag", _vp), ("n", _i64)]
 
 
+class PredTerm(ctypes.Structure):
+    _fields_ = [("column", _i32), ("dtype", _i32), ("op", _i32), ("n_values", _i32), ("ivalues", _i64 * 16),
+                ("fvalues", ctypes.c_double * 16)]
+
+
+PRED_OP = {"lt": 0, "le": 1, "gt": 2, "ge": 3, "eq": 4, "ne": 5, "between": 6, "in": 7}
+PRED_MODE = {"compiled": 0, "interpreted": 1}
+PRED_DTYPE = {torch.int8: 0, torch.int16: 1, torch.int32: 2, torch.int64: 3, torch.float32: 4, torch.float64: 5}
+
+
 class GatherCol(ctypes.Structure):
     _fields_ = [("src", _vp), ("dst", _vp), ("src_rows", _i64), ("elem_bytes", _i32), ("side", _i32)]
 
@@ -114,6 +124,9 @@ def lib():
         L.rel_join_table_destroy.argtypes = [_vp]
         L.rel_join_probe.argtypes = [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp]
         L.rel_join_gather.argtypes = [_vp, _vp, _vp, _vp, _i64, P(GatherCol), _i32]
+        L.rel_pred_create.argtypes = [_vp, P(PredTerm), _i32, _i32, P(_vp)]
+        L.rel_pred_filter.argtypes = [_vp, P(_vp), _i32, _i64, _vp, _i64, _vp]
+        L.rel_pred_destroy.argtypes = [_vp]
         L.rel_groupby_agg.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, P(TableOpts), P(GroupsOut)]
         L.rel_filter_join_agg.argtypes = [_vp, P(Fact), P(Dim), P(Query), P(Plan), P(GroupsOut), P(Stats)]
         L.rel_ctx_enable_timing.argtypes = [_vp, ctypes.c_int]
@@ -131,7 +144,7 @@ def lib():
         L.rel_planner_plan.argtypes = [_vp, P(Fact), P(Dim), P(Query), _vp, _vp, _i32, P(Plan), _vp]
         L.rel_planner_destroy.argtypes = [_vp]
         for name in ("rel_ctx_create", "rel_ctx_destroy", "rel_ctx_set_stream", "rel_ctx_sync", "rel_filter_compact",
-                     "rel_join_build", "rel_join_table_destroy", "rel_join_probe", "rel_join_gather", "rel_groupby_agg",
+                     "rel_join_build", "rel_join_table_destroy", "rel_join_probe", "rel_join_gather", "rel_pred_create", "rel_pred_filter", "rel_pred_destroy", "rel_groupby_agg",
                      "rel_filter_join_agg", "rel_ctx_enable_timing", "rel_ctx_kernel_times", "rel_batch_create",
                      "rel_batch_run", "rel_batch_sync", "rel_batch_destroy", "rel_sketch", "rel_mlp_forward",
                      "rel_mlp_backward", "rel_mlp_adam_step", "rel_planner_create", "rel_planner_plan",
@@ -431,6 +444,59 @@ class JoinTable:
     def close(self):
         if self.h:
             lib().rel_join_table_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Predicate:
+    """A conjunction of terms over typed columns: each term a dict with column
+    (index into the columns given to filter), op (lt le gt ge eq ne between in)
+    and values; dtypes: the column dtypes by index (torch int8/16/32/64,
+    float32/64). mode "compiled" builds a kernel for it at run time, mode
+    "interpreted" walks the terms per row."""
+
+    def __init__(self, ctx: Context, terms: list, dtypes: list, mode: str = "compiled"):
+        self.ctx, self.h = ctx, None
+        arr = (PredTerm * len(terms))()
+        for i, d in enumerate(terms):
+            dt = dtypes[d["column"]]
+            fp = dt in (torch.float32, torch.float64)
+            vals = list(d["values"])
+            arr[i].column, arr[i].dtype, arr[i].op, arr[i].n_values = d["column"], PRED_DTYPE[dt], PRED_OP[d["op"]], len(vals)
+            for j, v in enumerate(vals[:16]):
+                if fp:
+                    arr[i].fvalues[j] = float(v)
+                else:
+                    arr[i].ivalues[j] = int(v)
+        h = ctypes.c_void_p()
+        ctx.check(lib().rel_pred_create(ctx.h, arr, len(terms), PRED_MODE[mode], ctypes.byref(h)))
+        self.h = h
+
+    def filter(self, columns: list, sync: bool = True):
+        """Stable selection vector of the rows passing every term. Returns
+        (idx[:count], count), or with sync=False the full buffer and the device count."""
+        n = next(c.numel() for c in columns if c is not None)
+        for c in columns:
+            if c is not None and (not c.is_cuda or not c.is_contiguous() or c.numel() < n):
+                raise ValueError("predicate columns must be contiguous device tensors of at least n rows")
+        ptrs = (_vp * len(columns))(*[None if c is None else c.data_ptr() for c in columns])
+        dev = next(c.device for c in columns if c is not None)
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        cnt = torch.empty(1, dtype=torch.int64, device=dev)
+        self.ctx.check(lib().rel_pred_filter(self.h, ptrs, len(columns), n, _ptr(out), out.numel(), _ptr(cnt)))
+        if not sync:
+            return out, cnt
+        c = int(cnt.item())
+        return out[:c], c
+
+    def close(self):
+        if self.h:
+            lib().rel_pred_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -226,3 +226,53 @@ def test_join_gather_rejects_out_of_range_rows():
     for bad in (10, -1):
         with pytest.raises(oracle.OracleError):
             oracle.join_gather(np.array([0, bad], np.int32), src)
+
+
+# -- general predicates ---------------------------------------------------------------------------------------------------
+
+def _np_term(col, op, values):
+    x = col.astype(np.float64) if col.dtype.kind == "f" else col.astype(np.int64)
+    if op == "between":
+        return (x >= values[0]) & (x <= values[1])
+    if op == "in":
+        m = np.zeros(x.shape[0], bool)
+        for v in values:
+            m |= x == v
+        return m
+    return {"lt": x < values[0], "le": x <= values[0], "gt": x > values[0], "ge": x >= values[0],
+            "eq": x == values[0], "ne": x != values[0]}[op]
+
+
+def test_pred_filter_hand_example():
+    a = np.array([5, 1, 7, 3, 9], np.int32)
+    b = np.array([1.0, np.nan, 2.5, -1.0, 0.0])
+    assert oracle.pred_filter([a, b], [dict(column=0, op="between", values=[2, 8])]).tolist() == [0, 2, 3]
+    assert oracle.pred_filter([a, b], [dict(column=0, op="in", values=[1, 9, 4]),
+                                       dict(column=1, op="ne", values=[5.0])]).tolist() == [1, 4]
+    assert oracle.pred_filter([a, b], [dict(column=1, op="lt", values=[1.0])]).tolist() == [3, 4]
+
+
+@pytest.mark.parametrize("dtype", [np.int8, np.int16, np.int32, np.int64, np.float32, np.float64])
+@pytest.mark.parametrize("op", ["lt", "le", "gt", "ge", "eq", "ne", "between", "in"])
+def test_pred_filter_single_terms_equal_numpy(dtype, op):
+    rng = np.random.default_rng(hash((str(dtype), op)) % 2 ** 32)
+    col = rng.integers(-60, 60, size=3001).astype(dtype)
+    if col.dtype.kind == "f":
+        col[::97] = np.nan
+    values = {"between": [-20, 35], "in": [-7, 0, 3, 59, 100]}.get(op, [5])
+    got = oracle.pred_filter([col], [dict(column=0, op=op, values=values)])
+    assert np.array_equal(got, np.flatnonzero(_np_term(col, op, values)))
+
+
+def test_pred_filter_conjunction_is_intersection():
+    rng = np.random.default_rng(12)
+    cols = [rng.integers(0, 100, size=5000).astype(np.int32), rng.normal(size=5000), rng.integers(-5, 5, size=5000).astype(np.int8)]
+    terms = [dict(column=0, op="ge", values=[30]), dict(column=1, op="between", values=[-0.5, 1.0]),
+             dict(column=2, op="in", values=[-5, 0, 4]), dict(column=0, op="ne", values=[50])]
+    expect = np.arange(5000)
+    for t in terms:
+        expect = np.intersect1d(expect, oracle.pred_filter(cols, [t]))
+    assert np.array_equal(oracle.pred_filter(cols, terms), expect)
+    # one lt term over int32 is the plain compaction
+    assert np.array_equal(oracle.pred_filter(cols, [dict(column=0, op="lt", values=[42])]),
+                          oracle.filter_compact(cols[0], "lt", 42))
