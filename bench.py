@@ -146,7 +146,56 @@ def cpu_baseline(sample_rows: int, wl: str) -> dict:
     times.sort()
     med = times[len(times) // 2]
     return {"value": T.n / med, "unit": "rows/s", "cores": 1, "kind": "oracle",
-            "sample": f"{desc}; median of {len(times)} runs, {med:.2f} s each, generation excluded"}
+            "sample": f"{desc}; median of {len(times)} runs, {med:.2f} s each, generation excluded",
+            "host": host_info()}
+
+
+def host_info() -> dict:
+    """CPU model, hardware threads and memory of the machine the baseline ran on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    mem_gb = None
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal:"):
+                mem_gb = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    return {"cpu": model, "threads": os.cpu_count(), "mem_gib": mem_gb}
+
+
+def achievable_hbm() -> dict:
+    """A plain device copy (1 GiB read + 1 GiB written) and a read-only sum over
+    2 GiB, timed here: what this GPU's HBM delivers to simple streams, beside
+    the 8 TB/s peak the roofline fractions use."""
+    import torch
+
+    a = torch.ones(1 << 27, dtype=torch.int64, device="cuda:0")
+    b = torch.empty_like(a)
+    r = torch.ones(1 << 28, dtype=torch.int64, device="cuda:0")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def rate(fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return nbytes / (e0.elapsed_time(e1) / 5 / 1e3) / 1e9
+
+    out = {"copy_gbs": rate(lambda: b.copy_(a), 16 * a.numel()), "read_gbs": rate(lambda: r.sum(), 8 * r.numel())}
+    del a, b, r
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_batch(args) -> int:
@@ -313,8 +362,16 @@ def run_planner(args) -> int:
             times[name] = e0.elapsed_time(e1) / args.steps
         tot_plain += times["plain"]
         tot_plan += times["planned"]
-        row = {"groups_param": G, "groups": st0["groups"], "pred_log2_groups": pred[1],
+        # the planning step's own kernels (HyperLogLog pass, sample features, network), timed once
+        ctx.check(rel.lib().rel_ctx_enable_timing(ctx.h, 1))
+        planner.plan(fact, dim, T.day_lt, "dim_grp", fs, ds)
+        torch.cuda.synchronize()
+        kt = kernel_times(ctx)
+        ctx.check(rel.lib().rel_ctx_enable_timing(ctx.h, 0))
+        plan_kernels = {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items()}
+        row = {"groups_param": G, "groups": st0["groups"], "pred_log2_groups": pred[1], "plan_kernels_ms": plan_kernels,
                "plan_capacity": plan.group_capacity, "plan_placement": rel.PLACE_NAME[plan.group_placement],
+               "plan_join_placement": rel.PLACE_NAME[plan.join_placement],
                "fell_back": st1["fell_back"], "plain_ms": times["plain"], "planned_ms": times["planned"],
                "speedup": times["plain"] / times["planned"]}
         rows.append(row)
@@ -586,6 +643,8 @@ def main() -> int:
     for k, (tot, c) in sorted(kt.items(), key=lambda kv: -kv[1][0]):
         log(f"  kernel {k:18s} {tot / max(c, 1):9.3f} ms avg over {c} launches")
 
+    achievable = achievable_hbm()
+    log(f"achievable HBM here: copy {achievable['copy_gbs']:.0f} GB/s, read {achievable['read_gbs']:.0f} GB/s")
     n, m = T.n, T.m
     rows_per_s = n / (ms / 1e3)
     dom = max(kt.items(), key=lambda kv: kv[1][0])
@@ -624,10 +683,12 @@ def main() -> int:
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": desc, "fact_rows": n, "dim_rows": m, "day_lt": T.day_lt, "group_by": T.group_by,
+                   "cache": ("warm: the inputs fit the 256 MB last-level cache and are not flushed between steps"
+                             if 21 * n + 9 * m < 256 * 2 ** 20 else "inputs exceed the last-level cache"),
                    "rows_passed": st["rows_passed"], "join_matches": st["join_matches"], "groups": st["groups"],
                    "join_placement": st["join_placement"], "group_placement": st["group_placement"]},
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "achievable": achievable,
                      "traffic": ctr.get("traffic_bytes_per_launch"), "algorithmic_bytes_per_launch": alg_bytes,
                      "per_unit": unit_desc, "avg_launch_ms": dom_ms, "launches": dom_cnt,
                      "valu": valu},
