@@ -537,6 +537,27 @@ def run_pred(args) -> int:
         log(f"{mode}: {ms:.3f} ms per filter of {n:,} rows ({sel:,} selected), kernel {k_ms:.3f} ms, "
             f"{res[mode]['achieved_gbs']:.0f} GB/s algorithmic; created in {t_create:.2f} s")
         p.close()
+    # One term, day < 1200: the fixed-function compaction (rel_filter_compact)
+    # beside the same predicate compiled. 4 B per row read + 4 B per selected row.
+    one = {}
+    p1 = rel.Predicate(ctx, [dict(column=0, op="lt", values=[int(T.day_lt)])], [torch.int32], "compiled")
+    runs = {"filter_compact": lambda: ctx.filter_compact(cols[0], "lt", T.day_lt, sync=False),
+            "pred_compiled": lambda: p1.filter(cols[:1], sync=False)}
+    sel1 = ctx.filter_compact(cols[0], "lt", T.day_lt)[1]
+    for name, fn in runs.items():
+        for _ in range(args.warmup):
+            fn()
+        ctx.check(rel.lib().rel_ctx_enable_timing(ctx.h, 1))
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        k_tot, k_cnt = kernel_times(ctx)[name]
+        ctx.check(rel.lib().rel_ctx_enable_timing(ctx.h, 0))
+        k_ms = k_tot / max(k_cnt, 1)
+        one[name] = {"kernel_ms": k_ms, "achieved_gbs": (4 * n + 4 * sel1) / (k_ms / 1e3) / 1e9}
+        log(f"day < {T.day_lt} via {name}: kernel {k_ms:.3f} ms ({sel1:,} selected), "
+            f"{one[name]['achieved_gbs']:.0f} GB/s algorithmic")
+    p1.close()
     c, i = res["compiled"], res["interpreted"]
     ctr = counters_for("pred_compiled", "pred")
     result = {
@@ -554,6 +575,7 @@ def run_pred(args) -> int:
                         "kernel_ms": i["kernel_ms"], "achieved_gbs": i["achieved_gbs"],
                         "frac": i["achieved_gbs"] / HBM_PEAK_GBS},
         "compiled_over_interpreted": i["ms"] / c["ms"],
+        "one_term_day_lt": {"selected": sel1, **one},
         "create_s": {"compiled": c["create_s"], "interpreted": i["create_s"]},
     }
     print(json.dumps(result), flush=True)

@@ -5,6 +5,11 @@
 // Tiles are handed out by an atomic ticket, not by blockIdx, so every tile a
 // workgroup waits on belongs to a workgroup that is already running and that
 // publishes its own count before it looks back: the wait always ends.
+//
+// A thread tests 32 consecutive rows (eight 16-byte loads); the tile's
+// selected row numbers are staged in LDS in output order and written out by
+// consecutive lanes, so the stores are contiguous rather than one 4-byte
+// store per selected row scattered across a thread's output run.
 #include "rel_device.h"
 #include "rel_host.h"
 
@@ -13,7 +18,7 @@ namespace {
 using namespace rel;
 
 constexpr int kBlock = 256;
-constexpr int kIPT = 16;  // rows per thread: four 16-byte loads
+constexpr int kIPT = 32;  // rows per thread: eight 16-byte loads
 constexpr int64_t kTile = (int64_t)kBlock * kIPT;
 constexpr uint64_t kFlagAgg = 1ull << 62;   // tile's own count is published
 constexpr uint64_t kFlagIncl = 2ull << 62;  // tile's inclusive prefix is published
@@ -37,6 +42,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_compact(const int32_t* __rest
   __shared__ int64_t s_tile;
   __shared__ int64_t s_excl;
   __shared__ uint32_t s_wave[kBlock / kWave];
+  __shared__ int32_t s_rows[kTile];
   if (threadIdx.x == 0) s_tile = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)ticket, 1ull);
   __syncthreads();
   const int64_t tile = s_tile;
@@ -103,10 +109,12 @@ __global__ __launch_bounds__(kBlock) void k_filter_compact(const int32_t* __rest
     }
     if (tile == ntiles - 1) *d_count = s_excl + total;
   }
-  __syncthreads();
-  int64_t o = s_excl + my_off;
+  uint32_t o = my_off;
   for (int k = 0; k < kIPT; ++k)
-    if (bits & (1u << k)) out[o++] = (int32_t)(r0 + k);
+    if (bits & (1u << k)) s_rows[o++] = (int32_t)(r0 + k);
+  __syncthreads();
+  int32_t* dst = out + s_excl;
+  for (uint32_t j = threadIdx.x; j < total; j += kBlock) dst[j] = s_rows[j];
 }
 
 template <int OP>

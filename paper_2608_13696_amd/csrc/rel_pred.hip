@@ -5,9 +5,12 @@
 // on: a single-pass stable compaction (Merrill and Garland's decoupled
 // look-back, tiles taken by ticket so every awaited tile belongs to a running
 // workgroup, as in rel_filter.hip) around a function that yields, for one
-// thread's 16 consecutive rows, the bit mask of the rows that pass.
+// thread's run of consecutive rows (32 compiled, 16 interpreted), the bit mask
+// of the rows that pass. The
+// selected row numbers of a tile are staged in LDS and written out by
+// consecutive lanes.
 //   * compiled: the mask function is generated for the predicate. Each term
-//     reads its column's 16 elements with 16-byte loads and compares them
+//     reads its column's elements, 16 at a time, with 16-byte loads and compares them
 //     against literals written into the code; no branch depends on the term
 //     list.
 //   * interpreted: the mask function walks a term list in device memory for
@@ -26,6 +29,11 @@
 namespace {
 
 // The compaction around the mask function; `tile_bits` is defined before it.
+// Rows per thread, written in front of the program text: 32 for generated
+// masks (two groups of 16-byte loads per column), 16 for the interpreter,
+// whose rows are evaluated one after another.
+int rows_per_thread(int32_t mode) { return mode == REL_PRED_COMPILED ? 32 : 16; }
+
 const char* kSkeleton = R"SKEL(
 typedef struct {
   int column, dtype, op, n_values;
@@ -35,7 +43,6 @@ typedef struct {
 typedef struct { const void* c[8]; } Cols;
 
 #define BLOCK 256
-#define IPT 16
 #define TILE (BLOCK * IPT)
 #define FLAG_AGG (1ull << 62)
 #define FLAG_INCL (2ull << 62)
@@ -60,6 +67,7 @@ extern "C" __global__ __launch_bounds__(BLOCK) void k_pred_filter(Cols cols, lon
   __shared__ long long s_tile;
   __shared__ long long s_excl;
   __shared__ unsigned s_wave[BLOCK / 64];
+  __shared__ int s_rows[TILE];
   if (threadIdx.x == 0) s_tile = (long long)atomicAdd((unsigned long long*)ticket, 1ull);
   __syncthreads();
   const long long tile = s_tile;
@@ -107,9 +115,15 @@ extern "C" __global__ __launch_bounds__(BLOCK) void k_pred_filter(Cols cols, lon
     if (tile == ntiles - 1) *d_count = s_excl + total;
   }
   __syncthreads();
-  long long o = s_excl + wave_off + incl - c;
-  for (int k = 0; k < IPT; ++k)
-    if (bits & (1u << k)) out[o++] = (int)(r0 + k);
+  // selected rows go through LDS so that the workgroup writes them with consecutive lanes
+  {
+    unsigned o = wave_off + incl - c;
+    for (int k = 0; k < IPT; ++k)
+      if (bits & (1u << k)) s_rows[o++] = (int)(r0 + k);
+  }
+  __syncthreads();
+  const long long base = s_excl;
+  for (unsigned j = threadIdx.x; j < total; j += BLOCK) out[base + j] = s_rows[j];
 }
 )SKEL";
 
@@ -188,7 +202,7 @@ std::string term_expr(const rel_pred_term& t, const std::string& x) {
 std::string compiled_mask(const rel_pred_term* terms, int32_t n_terms) {
   std::string s =
       "__device__ __forceinline__ unsigned tile_bits(const Cols& cols, long long r0, long long n, const Term*, int) {\n"
-      "  unsigned bits = 0xffffu;\n"
+      "  unsigned bits = 0xffffffffu;\n"
       "  const bool full = r0 + IPT <= n;\n";
   for (int32_t i = 0; i < n_terms; ++i) {
     const rel_pred_term& t = terms[i];
@@ -196,9 +210,10 @@ std::string compiled_mask(const rel_pred_term* terms, int32_t n_terms) {
     const std::string conv = t.dtype >= REL_DT_F32 ? "(double)" : "(long long)";
     s += "  {\n    const " + T + "* p = (const " + T + "*)cols.c[" + std::to_string(t.column) + "];\n";
     s += "    unsigned m = 0;\n";
-    s += "    if (full) {\n      " + T + " v[16];\n      load16<" + T + ">(p + r0, v);\n";
-    s += "#pragma unroll\n      for (int k = 0; k < 16; ++k) m |= (unsigned)" + term_expr(t, conv + "v[k]") + " << k;\n";
-    s += "    } else {\n      for (int k = 0; k < 16; ++k)\n";
+    s += "    if (full) {\n#pragma unroll\n      for (int g = 0; g < IPT / 16; ++g) {\n        " + T + " v[16];\n";
+    s += "        load16<" + T + ">(p + r0 + 16 * g, v);\n";
+    s += "#pragma unroll\n        for (int k = 0; k < 16; ++k) m |= (unsigned)" + term_expr(t, conv + "v[k]") + " << (16 * g + k);\n      }\n";
+    s += "    } else {\n      for (int k = 0; k < IPT; ++k)\n";
     s += "        if (r0 + k < n) m |= (unsigned)" + term_expr(t, conv + "p[r0 + k]") + " << k;\n    }\n";
     s += "    bits &= m;\n  }\n";
   }
@@ -282,8 +297,8 @@ rel_status rel_pred_create(rel_ctx* ctx, const rel_pred_term* terms, int32_t n_t
   p->n_terms = n_terms;
   p->col_dtype = col_dtype;
   p->max_column = (int)col_dtype.size() - 1;
-  const std::string src =
-      std::string(kSkeleton) + (mode == REL_PRED_COMPILED ? compiled_mask(terms, n_terms) : std::string(kInterpreter));
+  const std::string src = "#define IPT " + std::to_string(rows_per_thread(mode)) + "\n" + kSkeleton +
+                          (mode == REL_PRED_COMPILED ? compiled_mask(terms, n_terms) : std::string(kInterpreter));
   rel_status s = compile(ctx, src, &p->module, &p->fn);
   if (s == REL_OK && mode == REL_PRED_INTERPRETED) {
     hipError_t e = hipMalloc(&p->d_terms, sizeof(rel_pred_term) * n_terms);
@@ -318,8 +333,8 @@ rel_status rel_pred_filter(rel_pred* p, const void* const* columns, int32_t n_co
   rel_status s = relh::ensure_counters(ctx);
   if (s != REL_OK) return s;
   if (n == 0) return relh::fill_u64(ctx, d_out_count, 1, 0);
-  constexpr int64_t kTileRows = 256 * 16;
-  long long ntiles = (n + kTileRows - 1) / kTileRows;
+  const int64_t tile_rows = 256 * rows_per_thread(p->mode);
+  long long ntiles = (n + tile_rows - 1) / tile_rows;
   void* st;
   if ((s = relh::scratch(ctx, SCR_SCAN_STATE, (size_t)ntiles * 8, &st)) != REL_OK) return s;
   int64_t* ticket = relh::counters(ctx) + CNT_TICKET;

@@ -209,13 +209,16 @@ class Context:
 
     # -- operators ------------------------------------------------------------------------------------------------
 
-    def filter_compact(self, col: torch.Tensor, op: str, literal: int):
-        """Stable selection vector of rows with col <op> literal. Returns (idx[:count] view, count)."""
+    def filter_compact(self, col: torch.Tensor, op: str, literal: int, sync: bool = True):
+        """Stable selection vector of rows with col <op> literal. Returns (idx[:count] view, count), or with
+        sync=False the full buffer and the device count (no host synchronisation)."""
         _dev_check(col, torch.int32, "col")
         n = col.numel()
         out = torch.empty(max(n, 1), dtype=torch.int32, device=col.device)
         cnt = torch.empty(1, dtype=torch.int64, device=col.device)
         self.check(lib().rel_filter_compact(self.h, _ptr(col), n, CMP[op], int(literal), _ptr(out), out.numel(), _ptr(cnt)))
+        if not sync:
+            return out, cnt
         c = int(cnt.item())
         return out[:c], c
 

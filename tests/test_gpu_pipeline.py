@@ -143,7 +143,7 @@ def test_planned_right_size_is_identical(ctx):
 
 # -- standalone operators -------------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n", [0, 1, 15, 4096, 4097, 1_000_003])
+@pytest.mark.parametrize("n", [0, 1, 15, 31, 33, 4096, 4097, 8191, 8192, 8193, 1_000_003])
 @pytest.mark.parametrize("op", ["lt", "le", "gt", "ge", "eq", "ne"])
 def test_filter_compact(ctx, n, op):
     col = datagen.uniform(n, -20, 20, np.int32, n + 7, 3)

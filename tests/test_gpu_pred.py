@@ -88,7 +88,8 @@ def _random_case(seed, n):
 
 @pytest.mark.parametrize("mode", ["compiled", "interpreted"])
 @pytest.mark.parametrize("seed,n", [(1, 1), (2, 15), (3, 16), (4, 17), (5, 4095), (6, 4096), (7, 4097), (8, 100_003),
-                                    (9, 1_000_000), (10, 65_537)])
+                                    (9, 1_000_000), (10, 65_537), (11, 31), (12, 33), (13, 8191), (14, 8192),
+                                    (15, 8193)])
 def test_random_predicates_match_oracle(ctx, mode, seed, n):
     cols, terms = _random_case(seed, n)
     exp = oracle.pred_filter(cols, terms)
