@@ -34,6 +34,9 @@ namespace {
 // whose rows are evaluated one after another.
 int rows_per_thread(int32_t mode) { return mode == REL_PRED_COMPILED ? 32 : 16; }
 
+// The kernel's name in each mode (profiles tell the two apart by it).
+const char* kernel_name(int32_t mode) { return mode == REL_PRED_COMPILED ? "k_pred_compiled" : "k_pred_interpreted"; }
+
 const char* kSkeleton = R"SKEL(
 typedef struct {
   int column, dtype, op, n_values;
@@ -60,7 +63,7 @@ __device__ __forceinline__ void load16(const T* p, T (&v)[16]) {
 
 __device__ __forceinline__ unsigned tile_bits(const Cols& cols, long long r0, long long n, const Term* terms, int nterms);
 
-extern "C" __global__ __launch_bounds__(BLOCK) void k_pred_filter(Cols cols, long long n, int* out,
+extern "C" __global__ __launch_bounds__(BLOCK) void PRED_KERNEL(Cols cols, long long n, int* out,
                                                                   unsigned long long* state, long long* ticket,
                                                                   long long* d_count, long long ntiles,
                                                                   const Term* terms, int nterms) {
@@ -243,7 +246,7 @@ void free_pred(rel_pred* p) {
   delete p;
 }
 
-rel_status compile(rel_ctx* ctx, const std::string& src, hipModule_t* mod, hipFunction_t* fn) {
+rel_status compile(rel_ctx* ctx, const std::string& src, const char* kernel, hipModule_t* mod, hipFunction_t* fn) {
   hipDeviceProp_t prop;
   REL_HIP_CHECK(ctx, hipGetDeviceProperties(&prop, ctx->device));
   const std::string arch = std::string("--offload-arch=") + prop.gcnArchName;
@@ -266,7 +269,7 @@ rel_status compile(rel_ctx* ctx, const std::string& src, hipModule_t* mod, hipFu
   hiprtcGetCode(prog, code.data());
   hiprtcDestroyProgram(&prog);
   REL_HIP_CHECK(ctx, hipModuleLoadData(mod, code.data()));
-  REL_HIP_CHECK(ctx, hipModuleGetFunction(fn, *mod, "k_pred_filter"));
+  REL_HIP_CHECK(ctx, hipModuleGetFunction(fn, *mod, kernel));
   return REL_OK;
 }
 
@@ -297,9 +300,10 @@ rel_status rel_pred_create(rel_ctx* ctx, const rel_pred_term* terms, int32_t n_t
   p->n_terms = n_terms;
   p->col_dtype = col_dtype;
   p->max_column = (int)col_dtype.size() - 1;
-  const std::string src = "#define IPT " + std::to_string(rows_per_thread(mode)) + "\n" + kSkeleton +
+  const std::string src = "#define IPT " + std::to_string(rows_per_thread(mode)) + "\n#define PRED_KERNEL " +
+                          kernel_name(mode) + "\n" + kSkeleton +
                           (mode == REL_PRED_COMPILED ? compiled_mask(terms, n_terms) : std::string(kInterpreter));
-  rel_status s = compile(ctx, src, &p->module, &p->fn);
+  rel_status s = compile(ctx, src, kernel_name(mode), &p->module, &p->fn);
   if (s == REL_OK && mode == REL_PRED_INTERPRETED) {
     hipError_t e = hipMalloc(&p->d_terms, sizeof(rel_pred_term) * n_terms);
     if (e == hipSuccess) e = hipMemcpy(p->d_terms, terms, sizeof(rel_pred_term) * n_terms, hipMemcpyHostToDevice);
