@@ -28,7 +28,6 @@
 
 namespace {
 
-// The compaction around the mask function; `tile_bits` is defined before it.
 // Rows per thread, written in front of the program text: 32 for generated
 // masks (two groups of 16-byte loads per column), 16 for the interpreter,
 // whose rows are evaluated one after another.
@@ -37,6 +36,8 @@ int rows_per_thread(int32_t mode) { return mode == REL_PRED_COMPILED ? 32 : 16; 
 // The kernel's name in each mode (profiles tell the two apart by it).
 const char* kernel_name(int32_t mode) { return mode == REL_PRED_COMPILED ? "k_pred_compiled" : "k_pred_interpreted"; }
 
+// The compaction around the mask function `tile_bits`, which the program text
+// defines after it.
 const char* kSkeleton = R"SKEL(
 typedef struct {
   int column, dtype, op, n_values;
