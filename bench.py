@@ -468,6 +468,23 @@ def run_gather(args) -> int:
     achieved = alg / (k_ms / 1e3) / 1e9
     ctr = counters_for("join_gather", "gather")
     log(f"gather: {ms:.3f} ms per call (kernel {k_ms:.3f} ms), {achieved:.0f} GB/s algorithmic")
+    # the stand-alone operators that produced the pairs, timed the same way
+    setup = {}
+    for name, fn in (("join_build", lambda: table.close() or ctx.join_build(pk)),
+                     ("join_probe", lambda: table.probe(fk, sel, sync=False))):
+        ctx.check(rel.lib().rel_ctx_enable_timing(ctx.h, 1))
+        for _ in range(max(1, min(args.steps, 5))):
+            out = fn()
+            if name == "join_build":
+                table = out
+        torch.cuda.synchronize()
+        t_tot, t_cnt = kernel_times(ctx)[name]
+        ctx.check(rel.lib().rel_ctx_enable_timing(ctx.h, 0))
+        setup[name] = {"kernel_ms": t_tot / max(t_cnt, 1)}
+    setup["join_build"]["keys_per_s"] = int(pk.numel()) / (setup["join_build"]["kernel_ms"] / 1e3)
+    setup["join_probe"]["probes_per_s"] = nsel / (setup["join_probe"]["kernel_ms"] / 1e3)
+    log(f"join_build {setup['join_build']['kernel_ms']:.3f} ms ({pk.numel():,} keys), join_probe "
+        f"{setup['join_probe']['kernel_ms']:.3f} ms ({nsel:,} probes)")
     result = {
         "metric": "materialised join rows/s (rel_join_gather, 4 columns)",
         "value": pairs / (ms / 1e3), "unit": "rows/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -479,6 +496,7 @@ def run_gather(args) -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": ctr.get("traffic_bytes_per_launch"),
                      "algorithmic_bytes_per_launch": alg,
                      "per_unit": "8 B of indices + 17 B read + 17 B written per pair", "avg_launch_ms": k_ms},
+        "operators": setup,
     }
     print(json.dumps(result), flush=True)
     table.close()

@@ -30,32 +30,58 @@ __global__ __launch_bounds__(256) void k_join_build(const int32_t* __restrict__ 
   }
 }
 
-// Probe: each wave compacts its matches with a ballot and reserves output
-// space with one atomic per wave. Output order is therefore unspecified.
+// Probe: a wave takes 8 x 64 consecutive probe rows per step, one row of each
+// 64 per lane. Every lane issues the first-slot loads of its eight rows
+// together (the random table reads are the cost, so eight are in flight per
+// lane instead of one), then finishes each probe. Matches are compacted with
+// one ballot per row group and the wave reserves output space for all eight
+// groups with one atomic. Output order is therefore unspecified.
+// On 28.15M probes into a 15M-key table: 0.78 ms with eight rows per lane,
+// 1.40 ms with four, 5.31 ms with one; sixteen spill the ballot masks.
+constexpr int kProbeRows = 8;
+
 __global__ __launch_bounds__(256) void k_join_probe(JoinView t, const int32_t* __restrict__ fk,
                                                     const int32_t* __restrict__ sel, int64_t n,
                                                     int32_t* __restrict__ out_fact, int32_t* __restrict__ out_payload,
                                                     int64_t* __restrict__ d_count) {
+  constexpr int64_t kStep = (int64_t)kWave * kProbeRows;
   const int64_t wave_global = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   const uint32_t lane = lane_id();
-  for (int64_t base = wave_global * kWave; base < n; base += n_waves * kWave) {
-    const int64_t k = base + lane;
-    bool hit = false;
-    int32_t row = 0, pl = 0;
-    if (k < n) {
-      row = sel ? sel[k] : (int32_t)k;
-      hit = join_lookup(t, fk[row], &pl);
+  for (int64_t base = wave_global * kStep; base < n; base += n_waves * kStep) {
+    int32_t row[kProbeRows], key[kProbeRows];
+    uint64_t first[kProbeRows];
+#pragma unroll
+    for (int k = 0; k < kProbeRows; ++k) {
+      const int64_t i = base + k * kWave + lane;
+      row[k] = i < n ? (sel ? sel[i] : (int32_t)i) : -1;
     }
-    const uint64_t ballot = wave_ballot(hit);
-    if (ballot == 0) continue;
+#pragma unroll
+    for (int k = 0; k < kProbeRows; ++k) key[k] = row[k] >= 0 ? fk[row[k]] : 0;
+#pragma unroll
+    for (int k = 0; k < kProbeRows; ++k) first[k] = row[k] >= 0 ? t.slots[join_first_index(t, key[k])] : kJoinEmpty;
+    bool hit[kProbeRows];
+    int32_t pl[kProbeRows];
+    uint64_t bal[kProbeRows];
+    uint32_t pre[kProbeRows], total = 0;
+#pragma unroll
+    for (int k = 0; k < kProbeRows; ++k) {
+      pl[k] = 0;
+      hit[k] = row[k] >= 0 && join_finish(t, key[k], first[k], &pl[k]);
+      bal[k] = wave_ballot(hit[k]);
+      pre[k] = total;
+      total += (uint32_t)__popcll(bal[k]);
+    }
+    if (total == 0) continue;
     int64_t off = 0;
-    if (lane == 0) off = dev_add_ret<unsigned long long>((unsigned long long*)d_count, (unsigned long long)__popcll(ballot));
+    if (lane == 0) off = dev_add_ret<unsigned long long>((unsigned long long*)d_count, (unsigned long long)total);
     off = __shfl(off, 0, kWave);
-    if (hit) {
-      const int64_t o = off + mask_rank(ballot);
-      out_fact[o] = row;
-      out_payload[o] = pl;
+#pragma unroll
+    for (int k = 0; k < kProbeRows; ++k) {
+      if (!hit[k]) continue;
+      const int64_t o = off + pre[k] + mask_rank(bal[k]);
+      out_fact[o] = row[k];
+      out_payload[o] = pl[k];
     }
   }
 }
@@ -150,7 +176,7 @@ rel_status rel_join_probe(rel_ctx* ctx, const rel_join_table* t, const int32_t* 
   rel_status s = relh::fill_u64(ctx, d_out_count, 1, 0);
   if (s != REL_OK || n == 0) return s;
   rel::JoinView v{t->slots, (uint32_t)((1ull << t->log2cap) - 1), 32u - t->log2cap};
-  const unsigned grid = relh::grid_for(ctx, n, 256, 8);
+  const unsigned grid = relh::grid_for(ctx, n, 256 * kProbeRows, 8);
   relh::KernelTimer kt(ctx, "join_probe");
   hipLaunchKernelGGL(k_join_probe, dim3(grid), dim3(256), 0, ctx->stream, v, fk, sel, n, out_fact_idx, out_payload,
                      d_out_count);

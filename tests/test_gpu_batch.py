@@ -110,6 +110,28 @@ def test_batch_undersized_hint_reports_overflow(ctx):
     b.close()
 
 
+def test_batch_duplicate_key_reported(ctx):
+    """A repeated pk in one instance is reported by rel_batch_sync; the other
+    instances' results are unaffected."""
+    tables, insts = _instances(6, seed=14, n_hi=3e4)
+    bad = 3
+    dim = insts[bad][1]
+    assert dim["pk"].numel() > 2
+    dim["pk"][2] = dim["pk"][1]
+    b = rel.Batch(ctx, insts)
+    b.run()
+    with pytest.raises(rel.RelError) as e:
+        b.sync()
+    assert e.value.status == rel.DUPLICATE_KEY
+    for i, T in enumerate(tables):
+        if i == bad:
+            continue
+        ora, _ = oracle.run_tables(T)
+        assert_groups_equal(rel.sorted_groups(b.outs[i].host()), ora, f"instance {i}")
+    b.close()
+    assert ctx.sync() == 0  # the status bits were cleared by the failing sync
+
+
 def test_invalid_tuning_rejected(ctx):
     tables, insts = _instances(2, seed=13)
     with pytest.raises(rel.RelError) as e:
