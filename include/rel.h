@@ -216,7 +216,7 @@ typedef struct rel_groups_out {
   int64_t* sum_qty;   /* device int64[cap] */
   int64_t* count;     /* device int64[cap] */
   int64_t cap;
-  int64_t* d_n_groups; /* device int64: number of groups (may exceed cap: then REL_DEV_OVERFLOW) */
+  int64_t* d_n_groups; /* device int64: number of groups, written by every call that returns REL_OK (may exceed cap: then REL_DEV_OVERFLOW) */
 } rel_groups_out;
 
 /* Groups of the rows row = sel ? sel[k] : k, k in [0, n): key[row],

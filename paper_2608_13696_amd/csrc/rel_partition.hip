@@ -723,6 +723,8 @@ struct UnitArgs {
   uint4* desc;
   uint2* split;
   int64_t* n_units;
+  int64_t* ticket;  // the join kernel's unit ticket: zeroed here
+  int64_t* out_n;   // nullable: the output group count, zeroed here
 };
 
 __global__ __launch_bounds__(kUBlk) void k_unit_count(UnitArgs a) {
@@ -780,6 +782,8 @@ __global__ __launch_bounds__(kUBlk) void k_unit_emit(UnitArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       *a.n_units = (int64_t)start + tot[0];
       *a.split_ctr = 0;  // k_unit_count has finished with it: clear it for the next call
+      *a.ticket = 0;     // counters the join kernel that follows starts from
+      if (a.out_n) *a.out_n = 0;
     }
   }
   __syncthreads();
@@ -1567,7 +1571,7 @@ struct Partitioned {
 };
 
 rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, int32_t day_lt, int pkind,
-                          const void* payload, bool with_flag, int64_t* counters, Partitioned* P) {
+                          const void* payload, bool with_flag, int64_t* counters, int64_t* out_n, Partitioned* P) {
   const int64_t n = fact->n, m = dim->m;
   uint32_t b1, b2;
   split_bits(m, &b1, &b2);
@@ -1677,6 +1681,8 @@ rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim
   ua.desc = unit_desc;
   ua.split = unit_split;
   ua.n_units = counters + CNT_AUX0;
+  ua.ticket = counters + CNT_TICKET;
+  ua.out_n = out_n;
   {
     KernelTimer kt(ctx, "unit_count");
     hipLaunchKernelGGL(k_unit_count, dim3(unit_wgs), dim3(kUBlk), 0, ctx->stream, ua);
@@ -1686,7 +1692,6 @@ rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim
     hipLaunchKernelGGL(k_unit_emit, dim3(unit_wgs), dim3(kUBlk), 0, ctx->stream, ua);
   }
   REL_LAUNCH_CHECK(ctx, "make_units");
-  TRY(fill_u64(ctx, counters + CNT_TICKET, 1, 0));
 
   P->F = F;
   P->D = D;
@@ -1707,8 +1712,7 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
                                  rel_groups_out* out, int64_t* counters) {
   Partitioned P;
   // the group key is the join key: no dim payload travels
-  TRY(partition_both(ctx, fact, dim, day_lt, PAY_NONE, nullptr, false, counters, &P));
-  TRY(fill_u64(ctx, out->d_n_groups, 1, 0));
+  TRY(partition_both(ctx, fact, dim, day_lt, PAY_NONE, nullptr, false, counters, out->d_n_groups, &P));
   KernelTimer kt(ctx, "part_groupjoin");
   JoinArgs a{};
   a.unit_desc = P.unit_desc;
@@ -1746,7 +1750,7 @@ rel_status partitioned_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_di
   Partitioned P;
   const bool prio_flag = group_by == REL_GROUP_PRIO_FLAG;
   TRY(partition_both(ctx, fact, dim, day_lt, prio_flag ? PAY_I8 : PAY_I32,
-                     prio_flag ? (const void*)dim->prio : (const void*)dim->grp, prio_flag, counters, &P));
+                     prio_flag ? (const void*)dim->prio : (const void*)dim->grp, prio_flag, counters, nullptr, &P));
   KernelTimer kt(ctx, "part_join_agg");
   AggArgs a{};
   a.unit_desc = P.unit_desc;

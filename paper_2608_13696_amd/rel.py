@@ -532,7 +532,7 @@ class Groups:
 def _alloc_groups(cap: int, device) -> Groups:
     cap = max(int(cap), 1)
     t = torch.empty((4, cap), dtype=torch.int64, device=device)
-    ng = torch.zeros(1, dtype=torch.int64, device=device)
+    ng = torch.empty(1, dtype=torch.int64, device=device)  # every successful call writes it
     g = Groups(t[0], t[1], t[2], t[3], ng, None)
     g.c = GroupsOut(_ptr(t[0]), _ptr(t[1]), _ptr(t[2]), _ptr(t[3]), cap, _ptr(ng))
     return g
