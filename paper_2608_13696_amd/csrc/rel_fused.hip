@@ -414,7 +414,8 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
   const bool part = jp == REL_PLACE_PARTITIONED ||
                     (jp == REL_PLACE_AUTO && n >= kPartitionMinRows && (gb == REL_GROUP_FK || m >= kPartitionMinDim));
   if (part && gb == REL_GROUP_FK) {
-    TRY(relh::fill_u64(ctx, cnt, 2, 0));
+    // with fact rows, the partitioning's first kernel clears the two counters
+    if (n == 0) TRY(relh::fill_u64(ctx, cnt, 2, 0));
     TRY(relh::partitioned_groupjoin(ctx, fact, dim, q->day_lt, out, cnt));
     return sync_stats(ctx, fact, dim, q, plan, out, stats, cnt, m, m, REL_PLACE_PARTITIONED, REL_PLACE_PARTITIONED);
   }

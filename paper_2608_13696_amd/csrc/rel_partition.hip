@@ -74,6 +74,7 @@ struct PartSide {
   uint32_t* pcount;  // [nb1 * nb2]
   uint4* tdesc2;     // [max tiles2] second-level tile: {first-level partition, row lo, row hi, 0}
   int64_t* ntiles2;  // number of second-level tiles
+  int64_t* zero2;    // nullable: two int64 counters that the first-level histogram clears
   uint32_t b1, b2;
 };
 
@@ -163,6 +164,10 @@ template <bool FACT>
 __global__ __launch_bounds__(kBlk) void k_p1_hist(PartSide s) {
   __shared__ uint32_t h[kMaxBins];
   const uint32_t nb1 = 1u << s.b1, shift = 32u - s.b1;
+  if (s.zero2 && blockIdx.x == 0 && threadIdx.x == 0) {  // for the kernels that follow
+    s.zero2[0] = 0;
+    s.zero2[1] = 0;
+  }
   for (uint32_t b = threadIdx.x; b < nb1; b += kBlk) h[b] = 0;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t r0 = tile * kTile1;
@@ -1629,6 +1634,7 @@ rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim
   F.pcount = cd.take<uint32_t>(nparts);
   F.tdesc2 = cd.take<uint4>((size_t)fnt2);
   F.ntiles2 = cd.take<int64_t>(1);
+  F.zero2 = counters;  // rows passed and join matches: cleared by the fact side's first kernel
 
   PartSide D{};
   D.key = dim->pk;
