@@ -164,13 +164,14 @@ def test_filter_compact_large_selectivities(ctx):
 
 @pytest.mark.parametrize("with_sel", [False, True])
 @pytest.mark.parametrize("with_payload", [False, True])
-def test_join_probe(ctx, with_sel, with_payload):
-    rng = np.random.default_rng(11)
-    m, n = 40_000, 300_001
+@pytest.mark.parametrize("n", [0, 1, 63, 511, 512, 513, 300_001])  # a wave's step is 8 x 64 probe rows
+def test_join_probe(ctx, with_sel, with_payload, n):
+    rng = np.random.default_rng(11 + n)
+    m = 40_000
     pk = datagen.permutation(m, 0, 4, 1)
     pk[0] = -1  # the key kept in the side slot (replaces a key from 0..m-1, so pk stays unique)
     fk = rng.integers(-30_000, 30_000, size=n).astype(np.int32)
-    fk[:50] = -1
+    fk[: min(50, n)] = -1
     payload = rng.integers(-(2 ** 31), 2 ** 31 - 1, size=m).astype(np.int32) if with_payload else None
     sel = np.flatnonzero(rng.random(n) < 0.45).astype(np.int32) if with_sel else None
     t = ctx.join_build(torch.from_numpy(pk).cuda(), torch.from_numpy(payload).cuda() if with_payload else None)
