@@ -300,6 +300,25 @@ __device__ __forceinline__ void group_add_wave(const GroupView& t, bool active, 
   if (active) group_add(t, key, sp, sq, 1ull);
 }
 
+// group_add_wave for partial aggregates: each active lane adds (sp, sq, cnt).
+__device__ __forceinline__ void group_add_wave_n(const GroupView& t, bool active, int64_t key, uint64_t sp, uint64_t sq,
+                                                 uint64_t cnt) {
+  const uint64_t act = wave_ballot(active);
+  if (act == 0) return;
+  const int first = __ffsll((long long)act) - 1;
+  const int64_t k0 = __shfl(key, first, kWave);
+  const bool mine = active && key == k0;
+  const uint64_t same = wave_ballot(mine);
+  if (__popcll(same) >= kWaveCombineMin) {
+    const uint64_t s1 = wave_sum_u64(mine ? sp : 0);
+    const uint64_t s2 = wave_sum_u64(mine ? sq : 0);
+    const uint64_t s3 = wave_sum_u64(mine ? cnt : 0);
+    if ((int)lane_id() == first) group_add(t, k0, s1, s2, s3);
+    active = active && !mine;
+  }
+  if (active) group_add(t, key, sp, sq, cnt);
+}
+
 // Per-dim-row aggregates of the groupjoin (group key == join key).
 struct alignas(8) RowAgg {
   uint64_t sum_price;

@@ -478,9 +478,12 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
   }
 
   if (part) {
-    // the same group table behind a per-workgroup LDS table (probe budget 0: none)
+    // the same group table behind a per-workgroup LDS table (probe budget 0:
+    // none); grouping by dim.grp with more groups than LDS holds aggregates per
+    // dim key first
+    const bool eager = gb == REL_GROUP_DIM_GRP && (gp != G_LDS || a.lds_probe != kLdsProbe);
     TRY(relh::partitioned_join_agg(ctx, fact, dim, q->day_lt, gb, gt, gl, a.groups.max_probe,
-                                   gp == G_LDS ? a.lds_probe : 0, cnt));
+                                   gp == G_LDS ? a.lds_probe : 0, eager, cnt));
     TRY(finalize(ctx, SlotSource{(const GroupSlot*)gt, group_cap}, group_cap + 1, out_args(ctx, out)));
     return sync_stats(ctx, fact, dim, q, plan, out, stats, cnt, m, group_cap, REL_PLACE_PARTITIONED,
                       gp == G_LDS ? REL_PLACE_LDS : REL_PLACE_GLOBAL);

@@ -27,10 +27,11 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
 // GROUP BY (dim.prio, fact.flag) or dim.grp over the same partitioned join:
 // aggregates into the device-memory group table group_slots (2^group_log2cap
 // slots plus the side slot, initialised by the caller; probe walks bounded by
-// max_probe) through per-workgroup LDS tables (probe budget lds_probe). Adds
-// to the same two counters.
+// max_probe) through per-workgroup LDS tables (probe budget lds_probe), or,
+// with eager (dim.grp only), through per-unit partials per dim key. Adds to
+// the same two counters.
 rel_status partitioned_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, int32_t day_lt, int group_by,
                                 void* group_slots, uint32_t group_log2cap, uint32_t max_probe, int32_t lds_probe,
-                                int64_t* counters);
+                                bool eager, int64_t* counters);
 
 }  // namespace relh

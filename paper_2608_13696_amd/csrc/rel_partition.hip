@@ -1481,6 +1481,182 @@ __global__ __launch_bounds__(kABlock, 4) void k_part_join_agg(AggArgs a) {
   if (lane == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
 }
 
+// GROUP BY dim.grp with more groups than an LDS group table holds: the
+// matches of a unit first aggregate per dim key in the unit's LDS join table
+// (count in the high half of the key word, sums beside it, as in the
+// groupjoin), and at the end of the unit each matched dim key adds its partial
+// sums to the device-memory group table under its grp (equal grp values of a
+// wave summed first). The device table then sees one update per dim key and
+// unit instead of one per fact row, which under skew is far fewer.
+__global__ __launch_bounds__(kABlock, 4) void k_part_join_eager(AggArgs a) {
+  __shared__ uint64_t tkc[kJSlots];  // {key, rows matched}; all ones = empty
+  __shared__ int32_t tpay[kJSlots];
+  __shared__ uint64_t tsp[kJSlots];
+  __shared__ uint64_t tsq[kJSlots];
+  __shared__ uint4 s_desc;
+  __shared__ uint2 s_split;
+  __shared__ int64_t s_u;
+  const int64_t n_units = *a.n_units;
+  const uint32_t tid = threadIdx.x, lane = lane_id();
+  uint64_t matched = 0;
+  // units by ticket from the largest-first list, thread 0 two tickets ahead
+  int64_t t_ahead = 0;
+  if (tid == 0) {
+    const int64_t t = take_ticket(a);
+    t_ahead = take_ticket(a);
+    s_u = t;
+    if (t < n_units) {
+      s_desc = a.unit_desc[t];
+      s_split = a.unit_split[t];
+    }
+  }
+  __syncthreads();
+  int64_t u = s_u;
+  uint4 d = s_desc;
+  uint2 usplit = s_split;
+  int32_t dk[kADK], dp[kADK];
+  AggRows<false> cur, nxt;
+  if (u < n_units) {
+    load_agg_dim(a, d, dk, dp);
+    load_agg_rows<false>(a, d.z + tid, d.w, cur);
+  }
+  while (u < n_units) {
+    const uint32_t dlo = d.x, dhi = d.y, flo = d.z, fhi = d.w;
+    int64_t t_req = 0;
+    uint4 nd = make_uint4(0, 0, 0, 0);
+    uint2 ns = make_uint2(0, 0);
+    if (tid == 0) {
+      if (t_ahead < n_units) {
+        nd = a.unit_desc[t_ahead];
+        ns = a.unit_split[t_ahead];
+      }
+      t_req = take_ticket(a);
+    }
+    for (int s = tid; s < kJSlots; s += kABlock) tkc[s] = kLdsEmpty;
+    __syncthreads();
+    // build: at most kJChunk unique keys into kJSlots slots, so a free slot always exists
+#pragma unroll
+    for (int k = 0; k < kADK; ++k) {
+      if (dlo + tid + k * kABlock >= dhi) continue;
+      const int32_t key = dk[k];
+      uint32_t h = slot_hash(key);
+      for (int step = 0; step < kJSlots; ++step) {
+        const uint64_t old = atomicCAS((unsigned long long*)&tkc[h], (unsigned long long)kLdsEmpty,
+                                       (unsigned long long)(uint32_t)key);
+        if (old == kLdsEmpty) {
+          tpay[h] = dp[k];
+          tsp[h] = 0;
+          tsq[h] = 0;
+          break;
+        }
+        if ((uint32_t)old == (uint32_t)key) {
+          set_status(a.status, kDevDupKey);
+          break;
+        }
+        h = (h + 1) & (kJSlots - 1);
+      }
+    }
+    if (tid == 0) {
+      s_u = t_ahead;
+      s_desc = nd;
+      s_split = ns;
+    }
+    __syncthreads();
+    const int64_t un = s_u;
+    const uint4 dn = s_desc;
+    const uint2 sn = s_split;
+    if (usplit.x == 0 && usplit.y > dhi) check_later_chunks<kABlock>(tkc, a.dkey, dhi, usplit.y, a.status);
+    const uint4 pd = un < n_units ? dn : d;  // past the last unit: reread this one (discarded)
+    int32_t ndk[kADK], ndp[kADK];
+    const uint32_t nrows = fhi - flo;
+    const uint32_t iters = (nrows + kJR * kABlock - 1) / (kJR * kABlock);
+    const bool early = iters <= 1;
+    if (early) {
+      load_agg_dim(a, pd, ndk, ndp);
+      load_agg_rows<false>(a, pd.z + tid, pd.w, nxt);
+    }
+    for (uint32_t it = 0; it < iters; ++it) {
+      const uint32_t i0 = flo + it * (kJR * kABlock) + tid;
+      if (it > 0) cur = nxt;
+      if (it + 1 < iters) load_agg_rows<false>(a, i0 + kJR * kABlock, fhi, nxt);
+      bool fnd[kJR];
+      int slt[kJR];
+#pragma unroll
+      for (int k = 0; k < kJR; ++k) {
+        fnd[k] = false;
+        slt[k] = 0;
+        if (i0 + k * kABlock < fhi) {
+          uint32_t h = slot_hash(cur.key[k]);
+          for (int step = 0; step < kJSlots; ++step) {
+            const uint64_t c = tkc[h];
+            if (c == kLdsEmpty) break;
+            if ((uint32_t)c == (uint32_t)cur.key[k]) {
+              fnd[k] = true;
+              slt[k] = (int)h;
+              break;
+            }
+            h = (h + 1) & (kJSlots - 1);
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kJR; ++k) {
+        bool found = fnd[k];
+        const int slot = slt[k];
+        matched += found;
+        // hot keys: many lanes of the wave on one slot are pre-summed
+        const uint64_t act = wave_ballot(found);
+        if (act == 0) continue;
+        const int first = __ffsll((long long)act) - 1;
+        const int s0 = __shfl(slot, first, kWave);
+        const uint64_t same = wave_ballot(found && slot == s0);
+        if (__popcll(same) >= kCombineMin) {
+          const bool mine = found && slot == s0;
+          const uint64_t tp = wave_sum_u64(mine ? cur.sp[k] : 0);
+          const uint64_t tq = wave_sum_u64(mine ? (uint64_t)(int64_t)cur.qty[k] : 0);
+          if ((int)lane == first) {
+            atomicAdd((unsigned long long*)&tsp[s0], (unsigned long long)tp);
+            atomicAdd((unsigned long long*)&tsq[s0], (unsigned long long)tq);
+            atomicAdd((unsigned long long*)&tkc[s0], (unsigned long long)__popcll(same) << 32);
+          }
+          found = found && !mine;
+        }
+        if (found) {
+          atomicAdd((unsigned long long*)&tsp[slot], (unsigned long long)cur.sp[k]);
+          atomicAdd((unsigned long long*)&tsq[slot], (unsigned long long)(int64_t)cur.qty[k]);
+          atomicAdd((unsigned long long*)&tkc[slot], 1ull << 32);
+        }
+      }
+    }
+    if (!early) {
+      load_agg_dim(a, pd, ndk, ndp);
+      load_agg_rows<false>(a, pd.z + tid, pd.w, nxt);
+    }
+    __syncthreads();
+    // one partial per matched dim key, into the device table under its grp
+#pragma unroll
+    for (int k = 0; k < kJSlots / kABlock; ++k) {
+      const int s = k * kABlock + tid;
+      const uint64_t c = tkc[s];
+      const bool occ = c != kLdsEmpty && (c >> 32) != 0;
+      group_add_wave_n(a.groups, occ, occ ? (int64_t)tpay[s] : 0, occ ? tsp[s] : 0, occ ? tsq[s] : 0, c >> 32);
+    }
+    __syncthreads();  // the join table and s_u / s_desc are reused by the next unit
+    t_ahead = t_req;
+    u = un;
+    d = dn;
+    usplit = sn;
+#pragma unroll
+    for (int k = 0; k < kADK; ++k) {
+      dk[k] = ndk[k];
+      dp[k] = ndp[k];
+    }
+    cur = nxt;
+  }
+  matched = wave_sum_u64(matched);
+  if (lane == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
+}
+
 #define TRY(x)                   \
   do {                           \
     rel_status s_ = (x);         \
@@ -1752,7 +1928,7 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
 // the device-memory group table g with an LDS table in front of it.
 rel_status partitioned_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, int32_t day_lt, int group_by,
                                 void* group_slots, uint32_t group_log2cap, uint32_t max_probe, int32_t lds_probe,
-                                int64_t* counters) {
+                                bool eager, int64_t* counters) {
   Partitioned P;
   const bool prio_flag = group_by == REL_GROUP_PRIO_FLAG;
   TRY(partition_both(ctx, fact, dim, day_lt, prio_flag ? PAY_I8 : PAY_I32,
@@ -1777,6 +1953,7 @@ rel_status partitioned_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_di
   a.zero = 0;
   const unsigned grid = (unsigned)ctx->num_cus * 2;
   if (prio_flag) hipLaunchKernelGGL(k_part_join_agg<REL_GROUP_PRIO_FLAG>, dim3(grid), dim3(kABlock), 0, ctx->stream, a);
+  else if (eager) hipLaunchKernelGGL(k_part_join_eager, dim3(grid), dim3(kABlock), 0, ctx->stream, a);
   else hipLaunchKernelGGL(k_part_join_agg<REL_GROUP_DIM_GRP>, dim3(grid), dim3(kABlock), 0, ctx->stream, a);
   REL_LAUNCH_CHECK(ctx, "part_join_agg");
   return REL_OK;
