@@ -54,6 +54,11 @@ def test_planned_equals_plain_and_oracle(ctx, planner, groups):
     assert_groups_equal(gp, ora, f"planned G={groups}")
     assert_groups_equal(g0, ora, f"plain G={groups}")
     assert st_p["groups"] == ost["groups"]
+    # what the network buys: a group table sized near the real group count
+    # instead of the plain bound min(N, M), and no fallback
+    assert st_p["fell_back"] == 0
+    assert st_p["group_capacity"] < st_0["group_capacity"]
+    assert st_p["group_capacity"] <= 8 * max(ost["groups"], 64), (st_p["group_capacity"], ost["groups"])
 
 
 def test_undersized_plan_falls_back_identically(ctx):
