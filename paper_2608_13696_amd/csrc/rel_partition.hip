@@ -15,7 +15,10 @@
 // Then one work unit per (partition, chunk of at most kJChunk dim keys),
 // ordered by decreasing fact-row count, builds an LDS table, streams the
 // partition's fact rows through it, and appends its groups to the output
-// with one atomic offset reservation per unit.
+// with one atomic offset reservation per unit. The same partitions and units
+// serve grouping by a dim attribute: k_part_join_agg (few groups, an LDS
+// group table per workgroup) and k_part_join_eager (many groups, partials per
+// dim key added to a device-memory table at the end of each unit).
 #include "rel_device.h"
 #include "rel_host.h"
 #include "rel_ops.h"
