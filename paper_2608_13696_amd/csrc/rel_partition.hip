@@ -871,9 +871,10 @@ __device__ __forceinline__ uint32_t unhoisted_zero_offset(uint32_t zero) {
   return threadIdx.x * z;
 }
 
+// Workgroup b starts on unit b; the units after the first gridDim.x go by ticket.
 __device__ __forceinline__ int64_t take_ticket(const JoinArgs& a) {
   unsigned long long* t = (unsigned long long*)a.ticket + unhoisted_zero_offset(a.zero);
-  return (int64_t)__hip_atomic_fetch_add(t, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return (int64_t)gridDim.x + (int64_t)__hip_atomic_fetch_add(t, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 struct RowRegs {
@@ -1010,7 +1011,7 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
   // unit's dim-key and first fact-row loads as early as its registers allow.
   int64_t t_ahead = 0;  // thread 0: ticket of the next unit
   if (tid == 0) {
-    const int64_t t = take_ticket(a);
+    const int64_t t = blockIdx.x;  // first unit without a round trip
     t_ahead = take_ticket(a);
     s_u = t;
     if (t < n_units) {
@@ -1278,7 +1279,7 @@ struct AggArgs {
 
 __device__ __forceinline__ int64_t take_ticket(const AggArgs& a) {
   unsigned long long* t = (unsigned long long*)a.ticket + unhoisted_zero_offset(a.zero);
-  return (int64_t)__hip_atomic_fetch_add(t, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return (int64_t)gridDim.x + (int64_t)__hip_atomic_fetch_add(t, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <bool FL>
@@ -1340,7 +1341,7 @@ __global__ __launch_bounds__(kABlock, 4) void k_part_join_agg(AggArgs a) {
   // (as in k_part_groupjoin)
   int64_t t_ahead = 0;
   if (tid == 0) {
-    const int64_t t = take_ticket(a);
+    const int64_t t = blockIdx.x;  // first unit without a round trip
     t_ahead = take_ticket(a);
     s_u = t;
     if (t < n_units) {
@@ -1505,7 +1506,7 @@ __global__ __launch_bounds__(kABlock, 4) void k_part_join_eager(AggArgs a) {
   // units by ticket from the largest-first list, thread 0 two tickets ahead
   int64_t t_ahead = 0;
   if (tid == 0) {
-    const int64_t t = take_ticket(a);
+    const int64_t t = blockIdx.x;  // first unit without a round trip
     t_ahead = take_ticket(a);
     s_u = t;
     if (t < n_units) {
