@@ -112,34 +112,6 @@ constexpr uint64_t kLbAgg = 1ull << 62;   // a tile's own count is published
 constexpr uint64_t kLbIncl = 2ull << 62;  // a tile's inclusive prefix is published
 constexpr uint64_t kLbVal = (1ull << 62) - 1;
 
-// Decoupled look-back (Merrill and Garland 2016) for one thread of tile
-// `tile` whose own count is `count`: publishes, waits on predecessors and
-// returns the exclusive prefix. Tiles must be numbered in the order their
-// workgroups started (a ticket), so every awaited predecessor is running and
-// publishes without waiting on this tile.
-__device__ __forceinline__ uint64_t lookback_prefix(uint64_t* state, int64_t tile, uint64_t count) {
-  if (tile == 0) {
-    __hip_atomic_store(&state[0], kLbIncl | count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return 0;
-  }
-  __hip_atomic_store(&state[tile], kLbAgg | count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  uint64_t acc = 0;
-  int64_t p = tile - 1;
-  for (;;) {
-    const uint64_t st = __hip_atomic_load(&state[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t flag = st & ~kLbVal;
-    if (flag == 0) {
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
-    acc += st & kLbVal;
-    if (flag == kLbIncl) break;
-    --p;  // stays >= 0: tile 0 only ever publishes an inclusive prefix
-  }
-  __hip_atomic_store(&state[tile], kLbIncl | (acc + count), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return acc;
-}
-
 // ---- join table -------------------------------------------------------------------------------------------------------
 
 // Slots [0, capacity) hold packed {key, payload}; an in-table key is never
@@ -274,6 +246,40 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, o, kWave);
   return v;
+}
+
+// Decoupled look-back (Merrill and Garland 2016) by one whole wave of tile
+// `tile`, whose own count is `count`: publishes the count, sums predecessors
+// and returns the exclusive prefix (the same value on every lane). Each round
+// reads the states of the 64 nearest predecessors not yet summed, so a walk
+// costs one round trip per 64 tiles rather than one per tile. Tiles must be
+// numbered in the order their workgroups started (a ticket), so every awaited
+// predecessor is running and publishes without waiting on this tile.
+__device__ __forceinline__ uint64_t lookback_prefix(uint64_t* state, int64_t tile, uint64_t count) {
+  const uint32_t lane = lane_id();
+  if (lane == 0)
+    __hip_atomic_store(&state[tile], (tile == 0 ? kLbIncl : kLbAgg) | count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t acc = 0;
+  int64_t p = tile - 1;  // nearest predecessor not yet summed
+  while (p >= 0) {
+    const int64_t q = p - (int64_t)lane;
+    // before tile 0 reads as an inclusive prefix of 0
+    const uint64_t st = q >= 0 ? __hip_atomic_load(&state[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kLbIncl;
+    const uint64_t flag = st & ~kLbVal;
+    const uint64_t incl = wave_ballot(flag == kLbIncl);
+    const uint64_t wait = wave_ballot(flag == 0);
+    const int fi = incl ? __ffsll((long long)incl) - 1 : kWave;  // nearest inclusive prefix
+    const int fw = wait ? __ffsll((long long)wait) - 1 : kWave;  // nearest tile not yet published
+    // sum up to the first unpublished tile, or through the first inclusive prefix
+    const int take = fw < fi ? fw : (fi < kWave ? fi + 1 : kWave);
+    acc += wave_sum_u64((int)lane < take ? (st & kLbVal) : 0ull);
+    if (fi < fw) break;
+    p -= take;
+    if (fw < kWave) __builtin_amdgcn_s_sleep(1);
+  }
+  if (lane == 0 && tile > 0)
+    __hip_atomic_store(&state[tile], kLbIncl | (acc + count), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return acc;
 }
 
 // Lanes sharing a key before a wave pre-sums them (below this the extra

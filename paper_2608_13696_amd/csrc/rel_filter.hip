@@ -20,9 +20,6 @@ using namespace rel;
 constexpr int kBlock = 256;
 constexpr int kIPT = 32;  // rows per thread: eight 16-byte loads
 constexpr int64_t kTile = (int64_t)kBlock * kIPT;
-constexpr uint64_t kFlagAgg = 1ull << 62;   // tile's own count is published
-constexpr uint64_t kFlagIncl = 2ull << 62;  // tile's inclusive prefix is published
-constexpr uint64_t kValMask = (1ull << 62) - 1;
 
 template <int OP>
 __device__ __forceinline__ bool pred(int32_t v, int32_t lit) {
@@ -84,30 +81,13 @@ __global__ __launch_bounds__(kBlock) void k_filter_compact(const int32_t* __rest
   }
   const uint32_t my_off = wave_off + incl - c;
 
-  // Publish, then look back.
-  if (threadIdx.x == 0) {
-    if (tile == 0) {
-      __hip_atomic_store(&state[0], kFlagIncl | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_excl = 0;
-    } else {
-      __hip_atomic_store(&state[tile], kFlagAgg | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      uint64_t acc = 0;
-      int64_t p = tile - 1;
-      for (;;) {
-        const uint64_t st = __hip_atomic_load(&state[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t flag = st & ~kValMask;
-        if (flag == 0) {
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        acc += st & kValMask;
-        if (flag == kFlagIncl) break;
-        --p;  // p > 0 here: tile 0 only ever publishes an inclusive prefix
-      }
-      __hip_atomic_store(&state[tile], kFlagIncl | (acc + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_excl = (int64_t)acc;
+  // Publish, then look back (the first wave).
+  if (wave == 0) {
+    const uint64_t excl = lookback_prefix(state, tile, total);
+    if (threadIdx.x == 0) {
+      s_excl = (int64_t)excl;
+      if (tile == ntiles - 1) *d_count = s_excl + total;
     }
-    if (tile == ntiles - 1) *d_count = s_excl + total;
   }
   uint32_t o = my_off;
   for (int k = 0; k < kIPT; ++k)

@@ -261,9 +261,12 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Src src, int64_t nitems, Ou
     if (i0 + k < nitems && src.occupied(i0 + k)) bits |= 1u << k;
   uint32_t total;
   const uint32_t off = block_excl_scan<kBlock>((uint32_t)__popc(bits), scr, &total);
-  if (threadIdx.x == 0) {
-    s_excl = lookback_prefix(state, tile, total);
-    if (tile == ntiles - 1) *o.d_n = (int64_t)(s_excl + total);
+  if (threadIdx.x < kWave) {
+    const uint64_t excl = lookback_prefix(state, tile, total);
+    if (threadIdx.x == 0) {
+      s_excl = excl;
+      if (tile == ntiles - 1) *o.d_n = (int64_t)(excl + total);
+    }
   }
   __syncthreads();
   int64_t pos = (int64_t)s_excl + off;

@@ -3,8 +3,8 @@
 //
 // Both modes are one program text built with hipRTC for the device it runs
 // on: a single-pass stable compaction (Merrill and Garland's decoupled
-// look-back, tiles taken by ticket so every awaited tile belongs to a running
-// workgroup, as in rel_filter.hip) around a function that yields, for one
+// look-back by one wave, tiles taken by ticket so every awaited tile belongs to a
+// running workgroup, as in rel_filter.hip) around a function that yields, for one
 // thread's run of consecutive rows (32 compiled, 16 interpreted), the bit mask
 // of the rows that pass. The
 // selected row numbers of a tile are staged in LDS and written out by
@@ -94,29 +94,38 @@ extern "C" __global__ __launch_bounds__(BLOCK) void PRED_KERNEL(Cols cols, long 
     wave_off += (unsigned)w < wave ? t : 0u;
     total += t;
   }
-  if (threadIdx.x == 0) {
-    if (tile == 0) {
-      __hip_atomic_store(&state[0], FLAG_INCL | (unsigned long long)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_excl = 0;
-    } else {
-      __hip_atomic_store(&state[tile], FLAG_AGG | (unsigned long long)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      unsigned long long acc = 0;
-      long long p = tile - 1;
-      for (;;) {
-        const unsigned long long st = __hip_atomic_load(&state[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned long long flag = st & ~VAL_MASK;
-        if (flag == 0) {
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        acc += st & VAL_MASK;
-        if (flag == FLAG_INCL) break;
-        --p;
-      }
-      __hip_atomic_store(&state[tile], FLAG_INCL | (acc + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_excl = (long long)acc;
+  // publish, then look back with the first wave: each round reads the states
+  // of the 64 nearest predecessors not yet summed
+  if (wave == 0) {
+    if (lane == 0)
+      __hip_atomic_store(&state[tile], (tile == 0 ? FLAG_INCL : FLAG_AGG) | (unsigned long long)total, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long acc = 0;
+    long long p = tile - 1;
+    while (p >= 0) {
+      const long long q = p - (long long)lane;
+      const unsigned long long st =
+          q >= 0 ? __hip_atomic_load(&state[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : FLAG_INCL;
+      const unsigned long long flag = st & ~VAL_MASK;
+      const unsigned long long incl = __ballot(flag == FLAG_INCL);
+      const unsigned long long wait = __ballot(flag == 0);
+      const int fi = incl ? __ffsll((long long)incl) - 1 : 64;
+      const int fw = wait ? __ffsll((long long)wait) - 1 : 64;
+      const int take = fw < fi ? fw : (fi < 64 ? fi + 1 : 64);
+      unsigned long long v = (int)lane < take ? (st & VAL_MASK) : 0ull;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      acc += v;
+      if (fi < fw) break;
+      p -= take;
+      if (fw < 64) __builtin_amdgcn_s_sleep(1);
     }
-    if (tile == ntiles - 1) *d_count = s_excl + total;
+    if (lane == 0) {
+      if (tile > 0)
+        __hip_atomic_store(&state[tile], FLAG_INCL | (acc + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_excl = (long long)acc;
+      if (tile == ntiles - 1) *d_count = s_excl + total;
+    }
   }
   __syncthreads();
   // selected rows go through LDS so that the workgroup writes them with consecutive lanes
