@@ -347,8 +347,9 @@ def test_partitioned_join_agg_degenerate(ctx, case):
     run_both(ctx, T, plan=_partitioned())
 
 
-def test_partitioned_join_agg_duplicate_pk_reported(ctx):
-    T = datagen.make_tables(10_000, 1000, 15, group_by="dim_grp", grp_card=40)
+@pytest.mark.parametrize("m", [400, 1000])  # group bound min(n, m): LDS group table / per-dim-key partials
+def test_partitioned_join_agg_duplicate_pk_reported(ctx, m):
+    T = datagen.make_tables(10_000, m, 15, group_by="dim_grp", grp_card=40)
     T.pk[7] = T.pk[8]
     fact, dim = to_dev(T)
     with pytest.raises(rel.RelError) as e:
