@@ -4,7 +4,8 @@
 //
 // Tiles are handed out by an atomic ticket, not by blockIdx, so every tile a
 // workgroup waits on belongs to a workgroup that is already running and that
-// publishes its own count before it looks back: the wait always ends.
+// publishes its own count before it looks back: the wait always ends. The
+// first wave does the look-back, reading 64 predecessor states per round.
 //
 // A thread tests 32 consecutive rows (eight 16-byte loads); the tile's
 // selected row numbers are staged in LDS in output order and written out by
