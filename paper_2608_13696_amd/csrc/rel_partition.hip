@@ -1006,9 +1006,9 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
   // Units come from the largest-first list by ticket (dynamic, so a workgroup
   // held up by a long unit takes fewer). Thread 0 runs two units ahead: at the
   // start of a unit it asks for the ticket after next and reads the next
-  // unit's descriptor (its ticket arrived during the previous unit), so
-  // neither round trip delays the unit. Every thread then issues the next
-  // unit's dim-key and first fact-row loads as early as its registers allow.
+  // unit's descriptor (its ticket arrived during the previous unit), and
+  // publishes it after the probe, so neither round trip delays the unit.
+  // Every thread then issues the next unit's dim-key and first fact-row loads.
   int64_t t_ahead = 0;  // thread 0: ticket of the next unit
   if (tid == 0) {
     const int64_t t = blockIdx.x;  // first unit without a round trip
@@ -1067,27 +1067,15 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
         h = (h + 1) & (kJSlots - 1);
       }
     }
-    if (tid == 0) {  // the next unit, read by everyone after the barrier
-      s_u = t_ahead;
-      s_desc = nd;
-      s_split = ns;
-    }
     __syncthreads();
-    const int64_t un = s_u;
-    const uint4 dn = s_desc;
-    const uint2 sn = s_split;
     if (sp.x == 0 && sp.y > dhi) check_later_chunks<kJBlock>(tkc, a.dkey, dhi, sp.y, a.status);
     int32_t ndkeys[kJDK];
-    // past the last unit the loads read the current unit again (discarded)
-    const uint4 pd = un < n_units ? dn : d;
     // probe and aggregate in LDS; long units stream further steps through nxt
     const uint32_t nrows = fhi - flo;
     const uint32_t iters = (nrows + kJR * kJBlock - 1) / (kJR * kJBlock);  // uniform over the workgroup
-    // A unit of one step leaves nxt free: the next unit's loads go out now and
-    // travel during this unit's probe and emission. Longer units issue them
-    // after the probe.
-    const bool early = iters <= 1;
-    if (early) prefetch_unit(a, pd, ndkeys, nxt);
+    // The next unit's descriptor is published at the end of the probe (so no
+    // thread waits at the build barrier for thread 0's read of it); its loads
+    // go out then and travel during the emission.
     for (uint32_t it = 0; it < iters; ++it) {
       const uint32_t i0 = flo + it * (kJR * kJBlock) + tid;
       if (it > 0) cur = nxt;
@@ -1144,7 +1132,17 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
         }
       }
     }
+    if (tid == 0) {  // the next unit, read by everyone after the barrier
+      s_u = t_ahead;
+      s_desc = nd;
+      s_split = ns;
+    }
     __syncthreads();
+    const int64_t un = s_u;
+    const uint4 dn = s_desc;
+    const uint2 sn = s_split;
+    // past the last unit the loads read the current unit again (discarded)
+    const uint4 pd = un < n_units ? dn : d;
     if (sp.x == 0) {
       // Whole unit: emit its groups. Output room is reserved with one atomic
       // per unit, taken when the unit finishes, so no unit waits on another.
@@ -1173,7 +1171,7 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
       }
       int64_t resv = 0;
       if (tid == 0 && total) resv = reserve_nowait(a, total);
-      if (!early) prefetch_unit(a, pd, ndkeys, nxt);
+      prefetch_unit(a, pd, ndkeys, nxt);
       if (tid == 0) s_excl = (uint64_t)resv;
       __syncthreads();
       const int64_t o0 = (int64_t)s_excl;
@@ -1187,7 +1185,7 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
     } else {
       // Sub-unit of a split chunk: add the partial sums into the chunk's
       // accumulator; the last sub-unit to finish emits and clears it.
-      if (!early) prefetch_unit(a, pd, ndkeys, nxt);
+      prefetch_unit(a, pd, ndkeys, nxt);
       SplitAcc* acc = a.split_acc + (size_t)(sp.x - 1) * kJChunk;
 #pragma unroll
       for (int k = 0; k < kJPer; ++k) {
