@@ -1483,6 +1483,9 @@ __global__ __launch_bounds__(kABlock, 4) void k_part_join_agg(AggArgs a) {
   if (lane == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
 }
 
+constexpr int kEagerCacheSlots = 256;
+constexpr int kEagerCacheProbe = 4;
+
 // GROUP BY dim.grp with more groups than an LDS group table holds: the
 // matches of a unit first aggregate per dim key in the unit's LDS join table
 // (count in the high half of the key word, sums beside it, as in the
@@ -1495,12 +1498,14 @@ __global__ __launch_bounds__(kABlock, 4) void k_part_join_eager(AggArgs a) {
   __shared__ int32_t tpay[kJSlots];
   __shared__ uint64_t tsp[kJSlots];
   __shared__ uint64_t tsq[kJSlots];
+  __shared__ LdsGroups<kEagerCacheSlots> cache;  // the workgroup's most frequent groups, flushed at the end
   __shared__ uint4 s_desc;
   __shared__ uint2 s_split;
   __shared__ int64_t s_u;
   const int64_t n_units = *a.n_units;
   const uint32_t tid = threadIdx.x, lane = lane_id();
   uint64_t matched = 0;
+  cache.init(tid, kABlock);
   // units by ticket from the largest-first list, thread 0 two tickets ahead
   int64_t t_ahead = 0;
   if (tid == 0) {
@@ -1635,13 +1640,19 @@ __global__ __launch_bounds__(kABlock, 4) void k_part_join_eager(AggArgs a) {
       load_agg_rows<false>(a, pd.z + tid, pd.w, nxt);
     }
     __syncthreads();
-    // one partial per matched dim key, into the device table under its grp
+    // one partial per matched dim key under its grp: into the LDS cache when
+    // the group is there or finds room within a short probe, else into the
+    // device table
 #pragma unroll
     for (int k = 0; k < kJSlots / kABlock; ++k) {
       const int s = k * kABlock + tid;
       const uint64_t c = tkc[s];
       const bool occ = c != kLdsEmpty && (c >> 32) != 0;
-      group_add_wave_n(a.groups, occ, occ ? (int64_t)tpay[s] : 0, occ ? tsp[s] : 0, occ ? tsq[s] : 0, c >> 32);
+      const int64_t g = occ ? (int64_t)tpay[s] : 0;
+      const int cs = occ ? cache.find(g, kEagerCacheProbe) : -1;
+      if (cs >= 0) cache.add(cs, tsp[s], tsq[s], c >> 32);
+      const bool dev = occ && cs < 0;
+      group_add_wave_n(a.groups, dev, g, dev ? tsp[s] : 0, dev ? tsq[s] : 0, c >> 32);
     }
     __syncthreads();  // the join table and s_u / s_desc are reused by the next unit
     t_ahead = t_req;
@@ -1655,6 +1666,8 @@ __global__ __launch_bounds__(kABlock, 4) void k_part_join_eager(AggArgs a) {
     }
     cur = nxt;
   }
+  __syncthreads();
+  cache.flush(a.groups, tid, kABlock);
   matched = wave_sum_u64(matched);
   if (lane == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
 }
