@@ -213,9 +213,11 @@ struct OutArgs {
 };
 
 // Group finalization: stream compaction of the occupied slots into the
-// output, in slot order. Each workgroup takes a tile by ticket, counts its
-// occupied slots, and finds its output offset by decoupled look-back, so no
-// single output counter is contended.
+// output. Each workgroup takes a tile by ticket, counts its occupied slots,
+// and finds its output offset by decoupled look-back, so no single output
+// counter is contended. A thread's slots are kBlock apart, so each count read
+// of a wave covers consecutive slots; the groups come out in tile order and,
+// inside a tile, thread by thread (the output order is unspecified).
 constexpr int kFinIPT = 8;
 constexpr int64_t kFinTile = (int64_t)kBlock * kFinIPT;
 
@@ -254,11 +256,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Src src, int64_t nitems, Ou
   if (threadIdx.x == 0) s_tile = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)ticket, 1ull);
   __syncthreads();
   const int64_t tile = s_tile;
-  const int64_t i0 = tile * kFinTile + (int64_t)threadIdx.x * kFinIPT;
+  const int64_t i0 = tile * kFinTile + (int64_t)threadIdx.x;  // slot of bit k: i0 + k * kBlock
   uint32_t bits = 0;
 #pragma unroll
-  for (int k = 0; k < kFinIPT; ++k)
-    if (i0 + k < nitems && src.occupied(i0 + k)) bits |= 1u << k;
+  for (int k = 0; k < kFinIPT; ++k) {
+    const int64_t i = i0 + (int64_t)k * kBlock;
+    if (i < nitems && src.occupied(i)) bits |= 1u << k;
+  }
   uint32_t total;
   const uint32_t off = block_excl_scan<kBlock>((uint32_t)__popc(bits), scr, &total);
   if (threadIdx.x < kWave) {
@@ -275,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Src src, int64_t nitems, Ou
     if (pos < o.cap) {
       int64_t key;
       uint64_t sp, sq, cnt;
-      src.get(i0 + k, &key, &sp, &sq, &cnt);
+      src.get(i0 + (int64_t)k * kBlock, &key, &sp, &sq, &cnt);
       o.key[pos] = key;
       o.sum_price[pos] = (int64_t)sp;
       o.sum_qty[pos] = (int64_t)sq;
