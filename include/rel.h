@@ -340,8 +340,8 @@ rel_status rel_batch_destroy(rel_batch* b);
 
 /* Sketch of a query's inputs: 64-register HyperLogLog of fact.fk (all rows)
  * and of dim.grp (when given), and statistics of k sampled fact rows and k
- * sampled dim rows, assembled into 40 features (layout in the design doc and the
- * sketch kernel). d_fact_sample / d_dim_sample: device int64[k] row indices in
+ * sampled dim rows, assembled into 40 features (in the fixed order the sketch
+ * kernel writes them). d_fact_sample / d_dim_sample: device int64[k] row indices in
  * [0, n) / [0, m), drawn by the caller. Outputs (device): d_features float[40],
  * d_hll uint8[128] (fk registers, then grp registers). */
 rel_status rel_sketch(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, const rel_query* q,
