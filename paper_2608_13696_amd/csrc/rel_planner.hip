@@ -258,8 +258,24 @@ __global__ __launch_bounds__(256) void k_sketch_features(SketchArgs a) {
 
 constexpr int kSPB = 16;  // samples per workgroup
 
+// The parameters into LDS, 16 loads per thread in flight at a time (one
+// after another they cost a round trip each, which dominated a single-sample
+// forward pass).
 __device__ __forceinline__ void load_params(float* lp, const float* __restrict__ p) {
-  for (int i = threadIdx.x; i < kParams; i += blockDim.x) lp[i] = p[i];
+  constexpr int kBurst = 16;
+  for (int base = 0; base < kParams; base += kBurst * (int)blockDim.x) {
+    float v[kBurst];
+#pragma unroll
+    for (int k = 0; k < kBurst; ++k) {
+      const int i = base + k * (int)blockDim.x + (int)threadIdx.x;
+      v[k] = i < kParams ? p[i] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < kBurst; ++k) {
+      const int i = base + k * (int)blockDim.x + (int)threadIdx.x;
+      if (i < kParams) lp[i] = v[k];
+    }
+  }
 }
 
 // 64 threads: thread j computes hidden unit j; threads 0 and 1 the outputs.
