@@ -61,6 +61,8 @@ def lib():
         L.or_join_gather.restype = i64
         L.or_groupby_agg.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, i64]
         L.or_groupby_agg.restype = i64
+        L.or_hll_hash.argtypes = [i32]
+        L.or_hll_hash.restype = ctypes.c_uint64
         L.or_hll_registers.argtypes = [i64, vp, vp]
         L.or_hll_registers.restype = None
         L.or_hll_estimate.argtypes = [vp]
@@ -177,6 +179,11 @@ def groupby_agg(key, price, qty, sel=None):
     ng = _check(lib().or_groupby_agg(n, _p(key), _p(price), _p(qty), _p(sel), _p(out["key"]), _p(out["sum_price"]),
                                      _p(out["sum_qty"]), _p(out["count"]), cap))
     return {k: v[:ng].copy() for k, v in out.items()}
+
+
+def hll_hash(key: int) -> int:
+    """The sketch's 64-bit hash of one int32 key."""
+    return int(lib().or_hll_hash(int(key)))
 
 
 def hll_registers(keys) -> np.ndarray:

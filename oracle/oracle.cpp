@@ -323,6 +323,10 @@ static uint64_t hll_hash(int32_t v) {
   return z ^ (z >> 31);
 }
 
+// The 64-bit hash of one key, exported so that tests can compare it with
+// SplitMix64's published output sequence.
+uint64_t or_hll_hash(int32_t v) { return hll_hash(v); }
+
 void or_hll_registers(int64_t n, const int32_t* keys, uint8_t* regs /*64*/) {
   for (int r = 0; r < 64; ++r) regs[r] = 0;
   for (int64_t i = 0; i < n; ++i) {

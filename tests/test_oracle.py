@@ -190,6 +190,30 @@ def test_groupby_agg_matches_numpy():
     np.add.at(sq, inv, qty[sel].astype(np.int64))
     assert g["sum_qty"].tolist() == sq.tolist()
     assert g["count"].tolist() == np.bincount(inv).tolist()
+    # SUM(price) of the selected rows, summed modulo 2^64 as unsigned
+    sp = np.zeros(keys.shape[0], np.uint64)
+    np.add.at(sp, inv, price[sel].view(np.uint64))
+    assert g["sum_price"].view(np.uint64).tolist() == sp.tolist()
+
+
+def test_groupby_agg_sum_price_wraps_and_uses_selected_rows():
+    # prices near 2^62 so that group sums wrap modulo 2^64, and a selection
+    # vector that is not the identity: a key's sum must add the price of each
+    # selected row (not of position k in the selection)
+    rng = np.random.default_rng(6)
+    n = 5000
+    key = rng.integers(0, 7, size=n).astype(np.int64)
+    price = rng.integers(2 ** 61, 2 ** 62, size=n, dtype=np.int64)
+    price[rng.random(n) < 0.5] *= -1
+    qty = rng.integers(1, 50, size=n).astype(np.int32)
+    sel = np.sort(rng.choice(n, size=1800, replace=False)).astype(np.int32)
+    g = oracle.groupby_agg(key, price, qty, sel)
+    want = {}
+    for r in sel.tolist():
+        want[int(key[r])] = (want.get(int(key[r]), 0) + int(price[r])) % (1 << 64)
+    assert g["key"].tolist() == sorted(want)
+    assert g["sum_price"].view(np.uint64).tolist() == [want[k] for k in sorted(want)]
+    assert any(v >= (1 << 63) for v in want.values())  # at least one sum wrapped past 2^63
 
 
 # -- join-output materialisation (gather) ---------------------------------------------------------------------------------

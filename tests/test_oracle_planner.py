@@ -47,6 +47,64 @@ def test_hll_estimate_empty_and_linear_counting():
     assert oracle.hll_estimate(regs) == pytest.approx(64 * math.log(64 / 56), rel=1e-12)
 
 
+# SplitMix64 (Steele, Lea and Flood 2014; Vigna's reference generator): state
+# advances by the golden-ratio increment, each output is the finaliser below of
+# the new state. Its published first five outputs from state 0:
+SPLITMIX64_SEED0 = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC,
+                    0x1B39896A51A8749B]
+_GAMMA = 0x9E3779B97F4A7C15
+_M64 = (1 << 64) - 1
+
+
+def _splitmix_finalise(z: int) -> int:
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def test_splitmix_finaliser_reproduces_published_sequence():
+    state, outs = 0, []
+    for _ in range(5):
+        state = (state + _GAMMA) & _M64
+        outs.append(_splitmix_finalise(state))
+    assert outs == SPLITMIX64_SEED0
+
+
+def test_hll_hash_is_first_splitmix64_output_of_the_key():
+    # key 0 seeds the generator with 0: its hash is the published first output
+    assert oracle.hll_hash(0) == SPLITMIX64_SEED0[0]
+    # any key: the generator seeded with the key as an unsigned 32-bit value
+    rng = np.random.default_rng(17)
+    keys = [1, -1, 2 ** 31 - 1, -(2 ** 31), 12345] + rng.integers(-(2 ** 31), 2 ** 31, size=200).tolist()
+    for v in keys:
+        assert oracle.hll_hash(v) == _splitmix_finalise(((v & 0xFFFFFFFF) + _GAMMA) & _M64), v
+
+
+def _index_rho(h: int):
+    idx = h >> 58
+    rest = h & ((1 << 58) - 1)
+    rho = 59 if rest == 0 else 58 - rest.bit_length() + 1
+    return idx, rho
+
+
+def test_hll_registers_by_hand():
+    # 0xE220A8397B1DCDAF: top six bits 111000 = register 56; the next bit is 1, so rho = 1
+    r = oracle.hll_registers(np.array([0], np.int32))
+    want = np.zeros(64, np.uint8)
+    want[56] = 1
+    assert np.array_equal(r, want)
+    # a key whose remaining bits start with several zeros, and a register that
+    # keeps the larger of two values
+    found = next(v for v in range(1, 1 << 20) if _index_rho(oracle.hll_hash(v))[1] >= 6)
+    i1, rho1 = _index_rho(oracle.hll_hash(found))
+    other = next(v for v in range(found + 1, 1 << 21) if _index_rho(oracle.hll_hash(v))[0] == i1
+                 and _index_rho(oracle.hll_hash(v))[1] < rho1)
+    r = oracle.hll_registers(np.array([other, found, other], np.int32))
+    want = np.zeros(64, np.uint8)
+    want[i1] = rho1
+    assert np.array_equal(r, want), (found, other)
+
+
 # -- sketch features ------------------------------------------------------------------------------------------------------
 
 def test_sketch_features_against_numpy():
@@ -68,6 +126,59 @@ def test_sketch_features_against_numpy():
     assert f[17] == pytest.approx(math.log2(1 + oracle.hll_estimate(hf)))
     gv = np.unique(T.grp[ds])
     assert f[14] == pytest.approx(len(gv) / 256)
+
+
+def test_sketch_features_remaining_against_numpy():
+    # fk over twice the pk range, so part of the sampled fk lies outside the sampled
+    # pk range; a grp domain wide enough that the grp sample has singletons and repeats
+    T = datagen.make_tables(30_000, 7_000, 23, day_lt=900, group_by="dim_grp", fk_domain=14_000, grp_card=400)
+    fs = datagen.sample_index(256, T.n, 6, 1)
+    ds = datagen.sample_index(256, T.m, 6, 2)
+    hf = oracle.hll_registers(T.fk)
+    hg = oracle.hll_registers(T.grp)
+    f = oracle.sketch_features(T.fk, T.day, T.pk, T.grp, T.day_lt, "dim_grp", fs, ds, hf, hg)
+    sfk, spk, sgrp = T.fk[fs].astype(np.int64), T.pk[ds].astype(np.int64), T.grp[ds].astype(np.int64)
+    assert f[2] == pytest.approx(math.log2((1 + T.n) / (1 + T.m)), abs=1e-12)
+    inside = np.mean((sfk >= spk.min()) & (sfk <= spk.max()))
+    assert 0.2 < inside < 0.8  # the case is not degenerate
+    assert f[11] == pytest.approx(inside, abs=1e-12)
+    assert f[12] == pytest.approx(math.log2(1 + sfk.max() - sfk.min()), abs=1e-12)
+    assert f[13] == pytest.approx(math.log2(1 + spk.max() - spk.min()), abs=1e-12)
+    _, gcnt = np.unique(sgrp, return_counts=True)
+    assert 0 < np.sum(gcnt == 1) < len(gcnt)  # singletons and repeats both occur
+    assert f[15] == pytest.approx(np.sum(gcnt == 1) / 256, abs=1e-12)
+    assert f[16] == pytest.approx(math.log2(1 + sgrp.max() - sgrp.min()), abs=1e-12)
+    assert f[18] == pytest.approx(np.mean(hf == 0), abs=1e-12)
+    assert f[19] == pytest.approx(hf.astype(float).mean() / 16, abs=1e-12)
+    assert f[20] == pytest.approx(hf.max() / 64, abs=1e-12)
+    assert f[37] == pytest.approx(math.log2(1 + oracle.hll_estimate(hg)), abs=1e-12)
+    assert f[38] == pytest.approx(np.mean(hg == 0), abs=1e-12)
+    assert np.allclose(f[21:37], np.bincount(np.minimum(hf, 15), minlength=16) / 64, rtol=0, atol=1e-12)
+
+
+def test_sketch_register_features_from_given_registers():
+    # the register features read the registers they are given: a hand-made set
+    # with zeros and values above the histogram's last bin (15)
+    T = datagen.make_tables(1000, 250, 24, group_by="dim_grp", grp_card=10)
+    fs = datagen.sample_index(256, T.n, 7, 1)
+    ds = datagen.sample_index(256, T.m, 7, 2)
+    hf = (np.arange(64) % 21).astype(np.uint8)  # 0..20, then 0..20, 0..20, 0
+    hg = np.zeros(64, np.uint8)
+    hg[:48] = 3
+    f = oracle.sketch_features(T.fk, T.day, T.pk, T.grp, T.day_lt, "dim_grp", fs, ds, hf, hg)
+    assert f[18] == pytest.approx(4 / 64)  # zeros at 0, 21, 42, 63
+    assert f[19] == pytest.approx((3 * sum(range(21))) / 64 / 16)
+    assert f[20] == pytest.approx(20 / 64)
+    hist = np.zeros(16)
+    hist[:15] = 3 / 64
+    hist[0] = 4 / 64
+    hist[15] = 3 * 6 / 64  # values 15..20, three times each
+    assert np.allclose(f[21:37], hist, rtol=0, atol=1e-15)
+    assert f[38] == pytest.approx(16 / 64)
+    # 16 of 64 registers are zero, raw estimate above 5m/2: no linear counting
+    z = 16 * 1.0 + 48 * 2.0 ** -3
+    raw = 0.709 * 64 * 64 / z
+    assert f[37] == pytest.approx(math.log2(1 + (raw if raw > 2.5 * 64 else 64 * math.log(64 / 16))), abs=1e-12)
 
 
 # -- MLP -----------------------------------------------------------------------------------------------------------------
