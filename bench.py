@@ -171,30 +171,43 @@ def host_info() -> dict:
     return {"cpu": model, "threads": os.cpu_count(), "mem_gib": mem_gb}
 
 
-def achievable_hbm() -> dict:
-    """A plain device copy (1 GiB read + 1 GiB written) and a read-only sum over
-    2 GiB, timed here: what this GPU's HBM delivers to simple streams, beside
-    the 8 TB/s peak the roofline fractions use."""
+def achievable_hbm(ctx=None) -> dict:
+    """The library's bandwidth probe (16-byte loads/stores by consecutive lanes,
+    eight in flight per thread): a 2 GiB read, a 1 GiB + 1 GiB copy and a 2 GiB
+    write, each the best of three grid sizes, timed with HIP events. What this
+    GPU's HBM delivers to simple streams, beside the 8 TB/s peak the roofline
+    fractions use."""
     import torch
 
-    a = torch.ones(1 << 27, dtype=torch.int64, device="cuda:0")
-    b = torch.empty_like(a)
-    r = torch.ones(1 << 28, dtype=torch.int64, device="cuda:0")
+    from paper_2608_13696_amd import rel
+
+    own = ctx is None
+    if own:
+        ctx = rel.Context(0)
+    big = torch.empty(1 << 31, dtype=torch.uint8, device="cuda:0")
+    half = 1 << 30
+    src, dst = big[:half], big[half:]
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda:0")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-    def rate(fn, nbytes):
-        fn()
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(5):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return nbytes / (e0.elapsed_time(e1) / 5 / 1e3) / 1e9
-
-    out = {"copy_gbs": rate(lambda: b.copy_(a), 16 * a.numel()), "read_gbs": rate(lambda: r.sum(), 8 * r.numel())}
-    del a, b, r
+    cases = {"read": (big, None, 1 << 31, 1 << 31), "copy": (src, dst, half, 2 * half), "write": (None, big, 1 << 31, 1 << 31)}
+    out = {}
+    for mode, (a, b, nbytes, moved) in cases.items():
+        best = 0.0
+        for bpc in (4, 8, 16):
+            ctx.bw_probe(mode, a, b, nbytes, bpc, sink)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(5):
+                ctx.bw_probe(mode, a, b, nbytes, bpc, sink)
+            e1.record()
+            torch.cuda.synchronize()
+            best = max(best, moved / (e0.elapsed_time(e1) / 5 / 1e3) / 1e9)
+        out[f"{mode}_gbs"] = best
+    out["probe"] = "rel_bw_probe (library kernel), best of 4/8/16 workgroups per CU"
+    del big, sink
     torch.cuda.empty_cache()
+    if own:
+        ctx.close()
     return out
 
 
@@ -398,26 +411,37 @@ def run_planner(args) -> int:
 
 
 def run_copy_calibration(args) -> int:
-    """A plain device copy of known size (1 GiB read + 1 GiB written per
-    launch), for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    """The bandwidth probe's copy of known size (1 GiB read + 1 GiB written per
+    launch, 8 workgroups per CU), for scaling the FETCH_SIZE / WRITE_SIZE
+    counters to bytes, and its read and write passes (2 GiB each)."""
     import torch
 
-    n = 1 << 27  # int64 elements: 1 GiB
-    a = torch.arange(n, dtype=torch.int64, device="cuda:0")
+    from paper_2608_13696_amd import rel
+
+    ctx = rel.Context(0)
+    n = 1 << 30
+    a = torch.ones(n, dtype=torch.uint8, device="cuda:0")
     b = torch.empty_like(a)
-    for _ in range(args.warmup):
-        torch.add(a, 1, out=b)
-    torch.cuda.synchronize()
+    big = torch.empty(2 * n, dtype=torch.uint8, device="cuda:0")
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    res = {"workload": "copy calibration", "bytes_read_per_launch": n, "bytes_written_per_launch": n}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        torch.add(a, 1, out=b)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    print(json.dumps({"workload": "copy calibration", "bytes_read_per_launch": 8 * n, "bytes_written_per_launch": 8 * n,
-                      "ms_per_launch": ms, "gbs": 16 * n / (ms / 1e3) / 1e9, "launches": args.steps + args.warmup}),
-          flush=True)
+    for mode, src, dst, nbytes, moved in (("copy", a, b, n, 2 * n), ("read", big, None, 2 * n, 2 * n),
+                                          ("write", None, big, 2 * n, 2 * n)):
+        for _ in range(args.warmup):
+            ctx.bw_probe(mode, src, dst, nbytes, 8, sink)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            ctx.bw_probe(mode, src, dst, nbytes, 8, sink)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        res[f"{mode}_ms_per_launch"] = ms
+        res[f"{mode}_gbs"] = moved / (ms / 1e3) / 1e9
+    res["launches_per_mode"] = args.steps + args.warmup
+    print(json.dumps(res), flush=True)
+    ctx.close()
     return 0
 
 
@@ -682,8 +706,9 @@ def main() -> int:
     for k, (tot, c) in sorted(kt.items(), key=lambda kv: -kv[1][0]):
         log(f"  kernel {k:18s} {tot / max(c, 1):9.3f} ms avg over {c} launches")
 
-    achievable = achievable_hbm()
-    log(f"achievable HBM here: copy {achievable['copy_gbs']:.0f} GB/s, read {achievable['read_gbs']:.0f} GB/s")
+    achievable = achievable_hbm(ctx)
+    log(f"achievable HBM here: read {achievable['read_gbs']:.0f} GB/s, copy {achievable['copy_gbs']:.0f} GB/s, "
+        f"write {achievable['write_gbs']:.0f} GB/s")
     n, m = T.n, T.m
     rows_per_s = n / (ms / 1e3)
     dom = max(kt.items(), key=lambda kv: kv[1][0])

@@ -25,7 +25,9 @@
  *   any work is enqueued; out-parameters are written only on REL_OK.
  *   Conditions found on the device (a full table, a duplicate build key) set
  *   sticky bits in the context's device status word; rel_ctx_sync returns and
- *   clears them.
+ *   clears them. A synchronising rel_filter_join_agg call and a batch report
+ *   through status words of their own (cleared when they start), so they
+ *   neither consume nor are charged with bits that earlier calls left.
  * - Integer sums and counts are 64-bit and wrap modulo 2^64, so results do not
  *   depend on the order in which atomic updates land.
  */
@@ -281,7 +283,10 @@ typedef struct rel_stats {
 
 /* Run the fused pipeline. plan nullable (plain). stats nullable; when given,
  * the call synchronises and fills it. Returns REL_DUPLICATE_KEY / REL_OVERFLOW
- * only when it synchronises (stats given or fallback allowed). */
+ * only when it synchronises (stats given or fallback allowed); such a call
+ * reads only the conditions its own kernels raised and leaves the sticky
+ * status bits of earlier calls for rel_ctx_sync. A call that does not
+ * synchronise leaves its conditions in the sticky bits. */
 rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, const rel_query* q,
                                const rel_plan* plan, rel_groups_out* out, rel_stats* stats);
 
@@ -321,9 +326,11 @@ rel_status rel_batch_create(rel_ctx* ctx, const rel_batch_item* items, int32_t k
                             int32_t n_tuning, rel_batch** out);
 /* Enqueue one run of every instance on the context's stream (one graph launch). */
 rel_status rel_batch_run(rel_batch* b);
-/* Synchronise and report: stats (nullable, k entries) with rows passed / join
- * matches / groups per instance; REL_OVERFLOW if any instance's table
- * overflowed, REL_DUPLICATE_KEY on a repeated pk. */
+/* Synchronise and report on the last run: stats (nullable, k entries) with
+ * rows passed / join matches / groups per instance; REL_OVERFLOW if any
+ * instance's table overflowed, REL_DUPLICATE_KEY on a repeated pk (the batch's
+ * own status word, cleared at the start of every run; the context's sticky
+ * bits are not touched). */
 rel_status rel_batch_sync(rel_batch* b, rel_stats* stats);
 rel_status rel_batch_destroy(rel_batch* b);
 
@@ -386,6 +393,23 @@ rel_status rel_planner_plan(rel_planner* p, const rel_fact* fact, const rel_dim*
                             const int64_t* d_fact_sample, const int64_t* d_dim_sample, int32_t k, rel_plan* plan,
                             float* pred);
 rel_status rel_planner_destroy(rel_planner* p);
+
+/* ------------------------------------------------------------------------------------------------------------------
+ * Bandwidth probe: the rate HBM gives this library's simplest access pattern
+ * (16-byte loads and stores by consecutive lanes, eight per thread in
+ * flight), the "achievable" bandwidth measured beside the vendor peak that the
+ * rooflines use as their denominator (Section 3.1 and Table 2 take the
+ * bandwidth of each GPU as the memory roofline).
+ */
+typedef enum rel_bw_mode { REL_BW_READ = 0, REL_BW_COPY = 1, REL_BW_WRITE = 2 } rel_bw_mode;
+
+/* One streaming pass over `bytes` (a multiple of 16): READ reads src, COPY
+ * copies src to dst, WRITE fills dst. src / dst are 16-byte aligned device
+ * buffers (unused ones may be NULL); d_sink is one device uint64 that READ
+ * may write so its loads are not optimised away. The grid is
+ * blocks_per_cu (1..64) 256-thread workgroups per CU. Stream-ordered. */
+rel_status rel_bw_probe(rel_ctx* ctx, int32_t mode, const void* src, void* dst, int64_t bytes, int32_t blocks_per_cu,
+                        uint64_t* d_sink);
 
 #ifdef __cplusplus
 }

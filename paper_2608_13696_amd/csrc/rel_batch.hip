@@ -251,12 +251,13 @@ struct rel_batch {
   BItem* d_items = nullptr;
   int64_t* d_tickets = nullptr;
   int64_t* d_stats = nullptr;
+  uint32_t* d_status = nullptr;  // this batch's status word, cleared at the start of every run
   uint64_t* d_join = nullptr;
   size_t join_words = 0;
   GroupSlot* d_groups = nullptr;
   size_t group_slots = 0;
   int64_t fin_lo = 0, fin_n = 0;
-  size_t zero_words = 0;  // tickets + stats
+  size_t zero_words = 0;  // tickets + stats + status word
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -434,7 +435,8 @@ rel_status rel_batch_create(rel_ctx* ctx, const rel_batch_item* items, int32_t k
   const size_t o_inst = 0;
   const size_t o_items = al(o_inst + sizeof(BInst) * (size_t)std::max(k, 1));
   const size_t o_zero = al(o_items + sizeof(BItem) * std::max<size_t>(hitems.size(), 1));
-  b->zero_words = n_tickets + 3 * (size_t)k;
+  // tickets, per-instance stats, and the batch's own status word (all cleared at the start of every run)
+  b->zero_words = n_tickets + 3 * (size_t)k + 1;
   const size_t o_join = al(o_zero + 8 * b->zero_words);
   const size_t o_groups = al(o_join + 8 * jw);
   const size_t total = al(o_groups + sizeof(GroupSlot) * gs);
@@ -449,6 +451,7 @@ rel_status rel_batch_create(rel_ctx* ctx, const rel_batch_item* items, int32_t k
   b->d_items = (BItem*)(base + o_items);
   b->d_tickets = (int64_t*)(base + o_zero);
   b->d_stats = b->d_tickets + n_tickets;
+  b->d_status = (uint32_t*)(b->d_stats + 3 * (size_t)k);
   b->d_join = (uint64_t*)(base + o_join);
   b->join_words = jw;
   b->d_groups = (GroupSlot*)(base + o_groups);
@@ -483,17 +486,17 @@ rel_status rel_batch_create(rel_ctx* ctx, const rel_batch_item* items, int32_t k
       const BucketPlan& bp = b->buckets[t];
       if (bp.build_n)
         launch_build(s, persistent_grid(ctx, bp.build_n, bp.t.block), bp.t.block, b->d_inst, b->d_items + bp.build_lo,
-                     bp.build_n, b->d_tickets + 2 * t, ctx->d_status);
+                     bp.build_n, b->d_tickets + 2 * t, b->d_status);
     }
     for (size_t t = 0; t < b->buckets.size(); ++t) {
       const BucketPlan& bp = b->buckets[t];
       if (bp.probe_n)
         launch_probe_any(s, persistent_grid(ctx, bp.probe_n, bp.t.block), bp.t.block, bp.t.items_per_thread, b->d_inst,
-                         b->d_items + bp.probe_lo, bp.probe_n, b->d_tickets + 2 * t + 1, ctx->d_status);
+                         b->d_items + bp.probe_lo, bp.probe_n, b->d_tickets + 2 * t + 1, b->d_status);
     }
     if (b->fin_n)
       hipLaunchKernelGGL(k_batch_finalize, dim3(persistent_grid(ctx, b->fin_n, 256)), dim3(256), 0, s, b->d_inst,
-                         b->d_items + b->fin_lo, b->fin_n, b->d_tickets + 2 * tun.size(), ctx->d_status);
+                         b->d_items + b->fin_lo, b->fin_n, b->d_tickets + 2 * tun.size(), b->d_status);
     hip(hipGetLastError(), "batch kernels");
     hipGraph_t g = nullptr;
     hipError_t ee = hipStreamEndCapture(s, &g);
@@ -520,13 +523,8 @@ rel_status rel_batch_sync(rel_batch* b, rel_stats* stats) {
   if (!b) return REL_INVALID_ARG;
   rel_ctx* ctx = b->ctx;
   REL_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
-  uint32_t bits = 0;
-  REL_HIP_CHECK(ctx, hipMemcpy(&bits, ctx->d_status, sizeof bits, hipMemcpyDeviceToHost));
-  if (bits) {
-    rel_status s = relh::fill_u32(ctx, ctx->d_status, 1, 0);
-    if (s != REL_OK) return s;
-    REL_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
-  }
+  uint32_t bits = 0;  // the last run's own status word
+  REL_HIP_CHECK(ctx, hipMemcpy(&bits, b->d_status, sizeof bits, hipMemcpyDeviceToHost));
   if (stats && b->k > 0) {
     std::vector<int64_t> h(3 * (size_t)b->k);
     REL_HIP_CHECK(ctx, hipMemcpy(h.data(), b->d_stats, 8 * h.size(), hipMemcpyDeviceToHost));

@@ -209,14 +209,15 @@ rel_status rel_ctx_create(int device, void* hip_stream, rel_ctx** out) {
   ctx->stream = (hipStream_t)hip_stream;
   ctx->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   ctx->lds_per_block = prop.sharedMemPerBlock;
-  e = hipMalloc(&ctx->d_status, 256);
+  e = hipMalloc(&ctx->d_status_words, 256);
   if (e != hipSuccess) {
     delete ctx;
     return REL_OOM;
   }
-  if (relh::fill_u32(ctx, ctx->d_status, 64, 0) != REL_OK || relh::ensure_counters(ctx) != REL_OK ||
+  ctx->d_status = ctx->d_status_words;
+  if (relh::fill_u32(ctx, ctx->d_status_words, 64, 0) != REL_OK || relh::ensure_counters(ctx) != REL_OK ||
       hipStreamSynchronize(ctx->stream) != hipSuccess) {
-    (void)hipFree(ctx->d_status);
+    (void)hipFree(ctx->d_status_words);
     delete ctx;
     return REL_HIP;
   }
@@ -242,7 +243,7 @@ rel_status rel_ctx_destroy(rel_ctx* ctx) {
     (void)hipEventDestroy(ctx->ev_fork);
     (void)hipEventDestroy(ctx->ev_join);
   }
-  if (ctx->d_status) (void)hipFree(ctx->d_status);
+  if (ctx->d_status_words) (void)hipFree(ctx->d_status_words);
   delete ctx;
   return REL_OK;
 }
@@ -258,9 +259,9 @@ rel_status rel_ctx_sync(rel_ctx* ctx, uint32_t* status_bits) {
   REL_HIP_CHECK(ctx, hipSetDevice(ctx->device));
   REL_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
   uint32_t bits = 0;
-  REL_HIP_CHECK(ctx, hipMemcpy(&bits, ctx->d_status, sizeof bits, hipMemcpyDeviceToHost));
+  REL_HIP_CHECK(ctx, hipMemcpy(&bits, ctx->d_status_words, sizeof bits, hipMemcpyDeviceToHost));
   if (bits) {
-    rel_status s = relh::fill_u32(ctx, ctx->d_status, 1, 0);
+    rel_status s = relh::fill_u32(ctx, ctx->d_status_words, 1, 0);
     if (s != REL_OK) return s;
     REL_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
   }

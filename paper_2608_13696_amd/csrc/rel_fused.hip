@@ -413,6 +413,19 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
   TRY(relh::ensure_counters(ctx));
   int64_t* cnt = relh::counters(ctx);
   const bool planned = plan && plan->group_capacity > 0;
+  // A call that synchronises reports through its own status word, cleared
+  // here; the others leave their bits in the sticky word for rel_ctx_sync.
+  struct StatusScope {
+    rel_ctx* c;
+    uint32_t* saved;
+    ~StatusScope() { c->d_status = saved; }
+  } scope{ctx, ctx->d_status};
+  if (stats != nullptr || (planned && plan->allow_fallback)) {
+    ctx->d_status = ctx->d_status_words + 1;
+    TRY(relh::fill_u32(ctx, ctx->d_status, 1, 0));
+  } else {
+    ctx->d_status = ctx->d_status_words;  // also inside a synchronising call's fallback run
+  }
 
   // Radix partitioning of both sides: asked for, or chosen for large inputs
   // (for a dim-attribute group key only when the dim side is large enough that
@@ -529,11 +542,8 @@ rel_status sync_stats(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, co
   uint32_t bits = 0;
   REL_HIP_CHECK(ctx, hipMemcpy(hc, cnt, sizeof hc, hipMemcpyDeviceToHost));
   REL_HIP_CHECK(ctx, hipMemcpy(&ng, out->d_n_groups, sizeof ng, hipMemcpyDeviceToHost));
+  // this call's own word (cleared at its start)
   REL_HIP_CHECK(ctx, hipMemcpy(&bits, ctx->d_status, sizeof bits, hipMemcpyDeviceToHost));
-  if (bits) {
-    TRY(relh::fill_u32(ctx, ctx->d_status, 1, 0));
-    REL_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
-  }
   if (bits & kDevDupKey) return relh::fail(ctx, REL_DUPLICATE_KEY, "rel_filter_join_agg: duplicate pk");
   const bool overflow = (bits & kDevOverflow) != 0;
   if (overflow && ng > out->cap) return relh::fail(ctx, REL_CAPACITY, "rel_filter_join_agg: %lld groups > cap", (long long)ng);

@@ -61,6 +61,12 @@ struct rel_ctx {
   hipStream_t stream = nullptr;
   int num_cus = 256;
   size_t lds_per_block = 65536;
+  // Device status words (64 x u32, one allocation). Word 0 is the sticky word
+  // rel_ctx_sync reads; word 1 belongs to a synchronising fused call, which
+  // clears it first and reads it at its end, so that bits left by earlier
+  // calls are neither charged to it nor dropped. d_status is the word that
+  // kernels launched now report to.
+  uint32_t* d_status_words = nullptr;
   uint32_t* d_status = nullptr;
   std::string err;
   ScratchBuf scratch[SCR_COUNT];
@@ -108,6 +114,7 @@ inline unsigned grid_for(const rel_ctx* ctx, int64_t items, int64_t per_block, i
 
 // Fill helpers (plain kernels, so that the calls stay legal inside a captured graph).
 rel_status fill_u64(rel_ctx* ctx, void* p, size_t n_u64, uint64_t v);
+
 rel_status fill_u32(rel_ctx* ctx, void* p, size_t n_u32, uint32_t v);
 
 // Records a start event on construction and a stop event on destruction when

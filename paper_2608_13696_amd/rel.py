@@ -22,6 +22,7 @@ CMP = {"lt": 0, "le": 1, "gt": 2, "ge": 3, "eq": 4, "ne": 5}
 PLACE = {"auto": 0, "lds": 1, "global": 2, "partitioned": 3}
 PLACE_NAME = {v: k for k, v in PLACE.items()}
 GROUP_BY = {"prio_flag": 0, "fk": 1, "dim_grp": 2}
+BW_MODE = {"read": 0, "copy": 1, "write": 2}
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -120,6 +121,7 @@ def lib():
         L.rel_last_error.argtypes = [_vp]
         L.rel_last_error.restype = ctypes.c_char_p
         L.rel_filter_compact.argtypes = [_vp, _vp, _i64, ctypes.c_int, _i32, _vp, _i64, _vp]
+        L.rel_bw_probe.argtypes = [_vp, _i32, _vp, _vp, _i64, _i32, _vp]
         L.rel_join_build.argtypes = [_vp, _vp, _vp, _i64, P(TableOpts), P(_vp)]
         L.rel_join_table_destroy.argtypes = [_vp]
         L.rel_join_probe.argtypes = [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp]
@@ -221,6 +223,15 @@ class Context:
             return out, cnt
         c = int(cnt.item())
         return out[:c], c
+
+    def bw_probe(self, mode: str, src: torch.Tensor | None, dst: torch.Tensor | None, nbytes: int,
+                 blocks_per_cu: int = 8, sink: torch.Tensor | None = None):
+        """One pass of the bandwidth probe (mode "read", "copy" or "write") over nbytes."""
+        if sink is None:
+            sink = torch.zeros(1, dtype=torch.int64, device=(src if src is not None else dst).device)
+        self.check(lib().rel_bw_probe(self.h, BW_MODE[mode], _ptr(src), _ptr(dst), int(nbytes), int(blocks_per_cu),
+                                      _ptr(sink)))
+        return sink
 
     def join_build(self, pk: torch.Tensor, payload: torch.Tensor | None = None, capacity_hint: int = 0,
                    max_load: float = 0.0) -> "JoinTable":

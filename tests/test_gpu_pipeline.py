@@ -118,6 +118,31 @@ def test_duplicate_pk_reported(ctx):
     assert e.value.status == rel.DUPLICATE_KEY
 
 
+@pytest.mark.parametrize("path", ["plain", "partitioned"])
+def test_status_bits_of_earlier_calls(ctx, path):
+    # Bits left in the sticky status word by earlier calls are neither charged
+    # to a synchronising fused call nor dropped by it.
+    n = 300_000 if path == "plain" else 1_200_000
+    T = datagen.make_tables(n, n // 4, 12, day_lt=1500, group_by="fk", fk_zipf=0.8)
+    fact, dim = to_dev(T)
+    ora, _ = oracle.run_tables(T)
+    assert ctx.sync() == 0
+    # an out-of-range gather index: a device-side argument error
+    src = torch.arange(10, dtype=torch.int32, device="cuda:0")
+    idx = torch.tensor([1, 12, 3, 0], dtype=torch.int32, device="cuda:0")
+    ctx.join_gather(idx, None, torch.tensor([4], dtype=torch.int64, device="cuda:0"), [(src, "fact")], max_pairs=4)
+    # a fused call without statistics whose output is too small: an overflow it cannot report
+    ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, stats=False, out_cap=5)
+    # a synchronising call afterwards succeeds with the right result
+    out, st = ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by)
+    assert st["join_placement"] == ("global" if path == "plain" else "partitioned")
+    assert_groups_equal(gpu_groups(out), ora, "after earlier status bits")
+    # and the earlier conditions are still there for rel_ctx_sync, once
+    bits = ctx.sync()
+    assert bits & rel.DEV_BADARG and bits & rel.DEV_OVERFLOW
+    assert ctx.sync() == 0
+
+
 @pytest.mark.parametrize("placement", ["lds", "global"])
 def test_planned_overflow_falls_back_to_plain(ctx, placement):
     T = datagen.make_tables(200_000, 50_000, 9, day_lt=1800, group_by="dim_grp", grp_card=5000)
