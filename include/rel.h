@@ -96,6 +96,19 @@ typedef enum rel_cmp { REL_LT = 0, REL_LE = 1, REL_GT = 2, REL_GE = 3, REL_EQ = 
 rel_status rel_filter_compact(rel_ctx* ctx, const int32_t* col, int64_t n, rel_cmp op, int32_t literal,
                               int32_t* out_idx, int64_t out_cap, int64_t* d_out_count);
 
+/* rel_filter_compact without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, result and errors as rel_filter_compact,
+ * plus REL_UNSUPPORTED for n > 2^30 rows. Its scratch (the ticket and the
+ * look-back tile states, at most 1 MiB) is a fixed device array that each GPU
+ * holds until the process ends; its address is looked up by rel_ctx_create.
+ * It enqueues two fill kernels and the compaction kernel on the context's
+ * stream and calls no allocating routine. Every call on one GPU shares that
+ * array: calls whose work overlaps in time on one GPU (two streams, two
+ * contexts, two threads) race and give wrong results. */
+rel_status rel_filter_compact_noalloc(rel_ctx* ctx, const int32_t* col, int64_t n, rel_cmp op, int32_t literal,
+                                      int32_t* out_idx, int64_t out_cap, int64_t* d_out_count);
+
 /* ------------------------------------------------------------------------------------------------------------------
  * General selection predicates (the compute-column step widened): a
  * conjunction of up to 8 terms over typed columns. Section 7 finds cuDF's

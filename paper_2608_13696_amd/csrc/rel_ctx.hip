@@ -216,7 +216,7 @@ rel_status rel_ctx_create(int device, void* hip_stream, rel_ctx** out) {
   }
   ctx->d_status = ctx->d_status_words;
   if (relh::fill_u32(ctx, ctx->d_status_words, 64, 0) != REL_OK || relh::ensure_counters(ctx) != REL_OK ||
-      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      relh::noalloc_scratch_init(ctx, device) != REL_OK || hipStreamSynchronize(ctx->stream) != hipSuccess) {
     (void)hipFree(ctx->d_status_words);
     delete ctx;
     return REL_HIP;

@@ -11,6 +11,8 @@
 // selected row numbers are staged in LDS in output order and written out by
 // consecutive lanes, so the stores are contiguous rather than one 4-byte
 // store per selected row scattered across a thread's output run.
+#include <mutex>
+
 #include "rel_device.h"
 #include "rel_host.h"
 
@@ -99,13 +101,62 @@ __global__ __launch_bounds__(kBlock) void k_filter_compact(const int32_t* __rest
 }
 
 template <int OP>
-void launch(rel_ctx* ctx, const int32_t* col, int64_t n, int32_t lit, int32_t* out, uint64_t* state, int64_t* ticket,
-            int64_t* d_count, int64_t ntiles) {
-  hipLaunchKernelGGL(k_filter_compact<OP>, dim3((unsigned)ntiles), dim3(kBlock), 0, ctx->stream, col, n, lit, out, state,
+void launch(hipStream_t stream, const int32_t* col, int64_t n, int32_t lit, int32_t* out, uint64_t* state,
+            int64_t* ticket, int64_t* d_count, int64_t ntiles) {
+  hipLaunchKernelGGL(k_filter_compact<OP>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, col, n, lit, out, state,
                      ticket, d_count, ntiles);
 }
 
+void launch_op(hipStream_t stream, rel_cmp op, const int32_t* col, int64_t n, int32_t lit, int32_t* out,
+               uint64_t* state, int64_t* ticket, int64_t* d_count, int64_t ntiles) {
+  switch (op) {
+    case REL_LT: launch<REL_LT>(stream, col, n, lit, out, state, ticket, d_count, ntiles); break;
+    case REL_LE: launch<REL_LE>(stream, col, n, lit, out, state, ticket, d_count, ntiles); break;
+    case REL_GT: launch<REL_GT>(stream, col, n, lit, out, state, ticket, d_count, ntiles); break;
+    case REL_GE: launch<REL_GE>(stream, col, n, lit, out, state, ticket, d_count, ntiles); break;
+    case REL_EQ: launch<REL_EQ>(stream, col, n, lit, out, state, ticket, d_count, ntiles); break;
+    case REL_NE: launch<REL_NE>(stream, col, n, lit, out, state, ticket, d_count, ntiles); break;
+  }
+}
+
+// ---- the allocation-free variant ---------------------------------------------------------------------------------------
+//
+// Its look-back tile states and its ticket live in a fixed device array: word
+// 0 is the ticket, words 1.. the states of up to kNoAllocTiles tiles (1 MiB),
+// so it compacts at most kNoAllocTiles * kTile = 2^30 rows. Every device that
+// runs the library holds its own copy until the process ends. In host code
+// the array's name is not a device address; the address is looked up once
+// per device (noalloc_scratch_init, from rel_ctx_create) and kept here.
+constexpr int64_t kNoAllocTiles = 1 << 17;
+constexpr int64_t kNoAllocMaxRows = kNoAllocTiles * kTile;
+static __device__ __align__(256) uint64_t scratch[1 + kNoAllocTiles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+namespace relh {
+
+// Looks up this device's copy of the fixed scratch array (the device must be
+// current). Called by rel_ctx_create; later calls for the same device return
+// at once.
+rel_status noalloc_scratch_init(rel_ctx* ctx, int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(ctx, REL_UNSUPPORTED, "device index %d above %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return REL_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(::scratch));
+  if (e != hipSuccess || p == nullptr) {
+    (void)hipGetLastError();
+    return fail(ctx, REL_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+  }
+  g_scratch_ptr[device] = p;
+  return REL_OK;
+}
+
+}  // namespace relh
 
 extern "C" rel_status rel_filter_compact(rel_ctx* ctx, const int32_t* col, int64_t n, rel_cmp op, int32_t literal,
                                          int32_t* out_idx, int64_t out_cap, int64_t* d_out_count) {
@@ -126,14 +177,33 @@ extern "C" rel_status rel_filter_compact(rel_ctx* ctx, const int32_t* col, int64
   if ((s = relh::fill_u64(ctx, ticket, 1, 0)) != REL_OK) return s;
   uint64_t* state = (uint64_t*)st;
   relh::KernelTimer kt(ctx, "filter_compact");
-  switch (op) {
-    case REL_LT: launch<REL_LT>(ctx, col, n, literal, out_idx, state, ticket, d_out_count, ntiles); break;
-    case REL_LE: launch<REL_LE>(ctx, col, n, literal, out_idx, state, ticket, d_out_count, ntiles); break;
-    case REL_GT: launch<REL_GT>(ctx, col, n, literal, out_idx, state, ticket, d_out_count, ntiles); break;
-    case REL_GE: launch<REL_GE>(ctx, col, n, literal, out_idx, state, ticket, d_out_count, ntiles); break;
-    case REL_EQ: launch<REL_EQ>(ctx, col, n, literal, out_idx, state, ticket, d_out_count, ntiles); break;
-    case REL_NE: launch<REL_NE>(ctx, col, n, literal, out_idx, state, ticket, d_out_count, ntiles); break;
-  }
+  launch_op(ctx->stream, op, col, n, literal, out_idx, state, ticket, d_out_count, ntiles);
   REL_LAUNCH_CHECK(ctx, "filter_compact");
+  return REL_OK;
+}
+
+// rel_filter_compact with its scratch in the fixed array: no allocation, only
+// two fill kernels and the compaction kernel on the context's stream.
+extern "C" rel_status rel_filter_compact_noalloc(rel_ctx* ctx, const int32_t* col, int64_t n, rel_cmp op,
+                                                 int32_t literal, int32_t* out_idx, int64_t out_cap,
+                                                 int64_t* d_out_count) {
+  if (!ctx || n < 0 || !d_out_count || (n > 0 && (!col || !out_idx)) || op < REL_LT || op > REL_NE)
+    return relh::fail(ctx, REL_INVALID_ARG, "rel_filter_compact_noalloc: bad argument");
+  if (n > kNoAllocMaxRows)
+    return relh::fail(ctx, REL_UNSUPPORTED, "rel_filter_compact_noalloc: n = %lld above the maximum of %lld rows",
+                      (long long)n, (long long)kNoAllocMaxRows);
+  if (col && !relh::aligned16(col))
+    return relh::fail(ctx, REL_INVALID_ARG, "rel_filter_compact_noalloc: column not 16-byte aligned");
+  if (out_cap < n) return relh::fail(ctx, REL_CAPACITY, "rel_filter_compact_noalloc: out_cap < n");
+  void* base = (ctx->device >= 0 && ctx->device < kMaxDevices) ? g_scratch_ptr[ctx->device] : nullptr;
+  if (!base) return relh::fail(ctx, REL_HIP, "rel_filter_compact_noalloc: scratch address of device %d unknown", ctx->device);
+  if (n == 0) return relh::fill_u64(ctx, d_out_count, 1, 0);
+  const int64_t ntiles = (n + kTile - 1) / kTile;
+  uint64_t* words = (uint64_t*)base;
+  // the ticket and this call's tile states start at zero (the array keeps the last call's contents)
+  rel_status s = relh::fill_u64(ctx, words, (size_t)(1 + ntiles), 0);
+  if (s != REL_OK) return s;
+  launch_op(ctx->stream, op, col, n, literal, out_idx, words + 1, (int64_t*)words, d_out_count, ntiles);
+  REL_LAUNCH_CHECK(ctx, "filter_compact_noalloc");
   return REL_OK;
 }

@@ -114,7 +114,9 @@ inline unsigned grid_for(const rel_ctx* ctx, int64_t items, int64_t per_block, i
 
 // Fill helpers (plain kernels, so that the calls stay legal inside a captured graph).
 rel_status fill_u64(rel_ctx* ctx, void* p, size_t n_u64, uint64_t v);
-
+// Address of this device's fixed scratch array for the allocation-free entry
+// point (rel_filter.hip); the device must be current.
+rel_status noalloc_scratch_init(rel_ctx* ctx, int device);
 rel_status fill_u32(rel_ctx* ctx, void* p, size_t n_u32, uint32_t v);
 
 // Records a start event on construction and a stop event on destruction when

@@ -121,6 +121,7 @@ def lib():
         L.rel_last_error.argtypes = [_vp]
         L.rel_last_error.restype = ctypes.c_char_p
         L.rel_filter_compact.argtypes = [_vp, _vp, _i64, ctypes.c_int, _i32, _vp, _i64, _vp]
+        L.rel_filter_compact_noalloc.argtypes = [_vp, _vp, _i64, ctypes.c_int, _i32, _vp, _i64, _vp]
         L.rel_bw_probe.argtypes = [_vp, _i32, _vp, _vp, _i64, _i32, _vp]
         L.rel_join_build.argtypes = [_vp, _vp, _vp, _i64, P(TableOpts), P(_vp)]
         L.rel_join_table_destroy.argtypes = [_vp]
@@ -223,6 +224,18 @@ class Context:
             return out, cnt
         c = int(cnt.item())
         return out[:c], c
+
+    def filter_compact_noalloc(self, col: torch.Tensor, op: str, literal: int, out: torch.Tensor, count: torch.Tensor,
+                               n: int | None = None):
+        """rel_filter_compact_noalloc into caller buffers: out (int32, at least n
+        rows) and count (one int64); n defaults to col.numel(). No allocation
+        inside the library; returns nothing (the count stays on the device)."""
+        _dev_check(col, torch.int32, "col")
+        _dev_check(out, torch.int32, "out")
+        _dev_check(count, torch.int64, "count")
+        n = col.numel() if n is None else int(n)
+        self.check(lib().rel_filter_compact_noalloc(self.h, _ptr(col), n, CMP[op], int(literal), _ptr(out), out.numel(),
+                                                    _ptr(count)))
 
     def bw_probe(self, mode: str, src: torch.Tensor | None, dst: torch.Tensor | None, nbytes: int,
                  blocks_per_cu: int = 8, sink: torch.Tensor | None = None):
