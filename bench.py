@@ -174,7 +174,7 @@ def host_info() -> dict:
 def achievable_hbm(ctx=None) -> dict:
     """The library's bandwidth probe (16-byte loads/stores by consecutive lanes,
     eight in flight per thread): a 2 GiB read, a 1 GiB + 1 GiB copy and a 2 GiB
-    write, each the best of three grid sizes, timed with HIP events. What this
+    write, each the best of four grid sizes, timed with HIP events. What this
     GPU's HBM delivers to simple streams, beside the 8 TB/s peak the roofline
     fractions use."""
     import torch
@@ -193,7 +193,7 @@ def achievable_hbm(ctx=None) -> dict:
     out = {}
     for mode, (a, b, nbytes, moved) in cases.items():
         best = 0.0
-        for bpc in (4, 8, 16):
+        for bpc in (2, 4, 8, 16):
             ctx.bw_probe(mode, a, b, nbytes, bpc, sink)
             torch.cuda.synchronize()
             e0.record()
@@ -203,7 +203,7 @@ def achievable_hbm(ctx=None) -> dict:
             torch.cuda.synchronize()
             best = max(best, moved / (e0.elapsed_time(e1) / 5 / 1e3) / 1e9)
         out[f"{mode}_gbs"] = best
-    out["probe"] = "rel_bw_probe (library kernel), best of 4/8/16 workgroups per CU"
+    out["probe"] = "rel_bw_probe (library kernel, non-temporal 16-byte accesses), best of 2/4/8/16 workgroups per CU"
     del big, sink
     torch.cuda.empty_cache()
     if own:

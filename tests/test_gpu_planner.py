@@ -93,3 +93,37 @@ def test_prediction_tracks_group_count(ctx, planner):
         actual.append(np.log2(1.0 + st["groups"]))
     assert preds[0] < preds[1] < preds[2]
     assert all(abs(p - a) < 2.0 for p, a in zip(preds, actual)), (preds, actual)
+
+
+def test_planned_run_is_not_slower_than_plain(ctx, planner):
+    """The gain the network buys, timed: on the 60M-row planner workload with
+    1e6 groups, the planned run (sketch, network, one host read and the sized
+    run) is not slower than the plain run, and both give the same groups."""
+    T = datagen.planner_eval(1_000_000)
+    fact, dim = to_dev(T)
+    fs, ds = _samples(T)
+
+    def plain():
+        return ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, stats=False)[0]
+
+    def planned():
+        plan, _ = planner.plan(fact, dim, T.day_lt, T.group_by, fs, ds)
+        return ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by, plan=plan, stats=False)[0]
+
+    a, b = gpu_groups(plain()), gpu_groups(planned())
+    assert a["n_groups"] == b["n_groups"]
+    for k in ("key", "sum_price", "sum_qty", "count"):
+        assert np.array_equal(a[k], b[k]), k
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = {}
+    for name, fn in (("plain", plain), ("planned", planned)):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms[name] = e0.elapsed_time(e1) / 5
+    print(f"plain {ms['plain']:.3f} ms, planned {ms['planned']:.3f} ms", flush=True)
+    assert ms["planned"] <= ms["plain"], ms
