@@ -852,15 +852,16 @@ struct JoinArgs {
 };
 
 constexpr uint64_t kLdsEmpty = ~0ull;
-constexpr int kJR = 4;                                   // fact rows per thread per step
+constexpr int kJR = 4;                                   // fact rows per thread per step (dim-attribute kernels)
+constexpr int kGR = 4;                                   // fact rows per thread per step (groupjoin)
 constexpr int kJDK = (kJChunk + kJBlock - 1) / kJBlock;  // dim keys per thread
 constexpr int kJPer = kJSlots / kJBlock;                 // LDS slots per thread at emission
 
-// The next unit's ticket. The address is written so that the compiler cannot
-// prove it uniform (zero is a run-time 0): a uniform-address atomic would be
-// rewritten into a wave-wide one whose result is broadcast at once, stalling
-// the wave on the round trip; this way the wave waits only where the ticket
-// is used, after the current unit's build.
+// An offset of zero that the compiler cannot prove uniform (zero is a
+// run-time 0), for the address of an atomic issued by one thread: a
+// uniform-address atomic would be rewritten into a wave-wide one whose result
+// is broadcast at once, stalling the wave on the round trip; this way the wave
+// waits only where the result is used.
 // The offset is rebuilt at each call (the empty asm keeps the compiler from
 // hoisting it out of the unit loop): a loop-invariant address would hold two
 // registers for the whole loop, and when spilled its reload waits for every
@@ -871,59 +872,42 @@ __device__ __forceinline__ uint32_t unhoisted_zero_offset(uint32_t zero) {
   return threadIdx.x * z;
 }
 
-// Workgroup b starts on unit b; the units after the first gridDim.x go by ticket.
-__device__ __forceinline__ int64_t take_ticket(const JoinArgs& a) {
-  unsigned long long* t = (unsigned long long*)a.ticket + unhoisted_zero_offset(a.zero);
-  return (int64_t)gridDim.x + (int64_t)__hip_atomic_fetch_add(t, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Workgroup b takes units b, b + G, b + 2G, ... (G workgroups). The list is
+// ordered largest first, so each workgroup's share mixes the size classes
+// alike. (Units by atomic ticket would balance the tail better, but every
+// ticket is an atomic on one cache line, and atomics on one line serialise on
+// this chip at about 12 ns each: tens of thousands of units per launch make
+// that line a bottleneck.)
+__device__ __forceinline__ int64_t take_ticket(const JoinArgs& a, int64_t& seq) {
+  (void)a;
+  seq += gridDim.x;
+  return seq;
 }
 
-struct RowRegs {
-  int32_t key[kJR];
-  int32_t qty[kJR];
-  uint64_t sp[kJR];
+// The groupjoin's fact rows of one step (kGR per thread, kGR * kJBlock per
+// workgroup): keys, and the prices and quantities that the updates use.
+struct KeyRegs {
+  int32_t key[kGR];
+};
+struct PayRegs {
+  int32_t qty[kGR];
+  uint64_t sp[kGR];
 };
 
-__device__ __forceinline__ void load_rows(const JoinArgs& a, uint32_t i0, uint32_t fhi, RowRegs& r) {
+// Row indices are clamped into the (never empty) range [.., fhi): the loads
+// carry no branch, so their number is fixed; lanes past the range hold copies
+// that the probe skips.
+__device__ __forceinline__ void load_keys(const JoinArgs& a, uint32_t i0, uint32_t fhi, KeyRegs& r) {
 #pragma unroll
-  for (int k = 0; k < kJR; ++k) {
+  for (int k = 0; k < kGR; ++k) {
     const uint32_t i = i0 + k * kJBlock;
-    const bool ok = i < fhi;
-    r.key[k] = ok ? a.fkey[i] : 0;
-    r.sp[k] = ok ? (uint64_t)a.fprice[i] : 0;
-    r.qty[k] = ok ? a.fqty[i] : 0;
+    r.key[k] = a.fkey[i < fhi ? i : fhi - 1];
   }
 }
 
-__device__ __forceinline__ void load_dkeys(const JoinArgs& a, uint32_t dlo, uint32_t dhi, int32_t (&dk)[kJDK]) {
+__device__ __forceinline__ void load_payload(const JoinArgs& a, uint32_t i0, uint32_t fhi, PayRegs& r) {
 #pragma unroll
-  for (int k = 0; k < kJDK; ++k) {
-    const uint32_t j = dlo + threadIdx.x + k * kJBlock;
-    dk[k] = j < dhi ? a.dkey[j] : 0;
-  }
-}
-
-// The next unit's dim keys and the keys of its first fact rows, with indices
-// clamped into the unit's (never empty) ranges: the loads carry no branch, so
-// their number is fixed and a later wait for an earlier atomic does not have to
-// wait for them. Lanes past the ranges hold copies that the build and probe
-// skip. The rows' prices and quantities follow at the start of the unit
-// (load_payload), so they do not hold registers through this unit.
-__device__ __forceinline__ void prefetch_unit(const JoinArgs& a, uint4 u, int32_t (&dk)[kJDK], RowRegs& r) {
-#pragma unroll
-  for (int k = 0; k < kJDK; ++k) {
-    const uint32_t j = u.x + threadIdx.x + k * kJBlock;
-    dk[k] = a.dkey[j < u.y ? j : u.y - 1];
-  }
-#pragma unroll
-  for (int k = 0; k < kJR; ++k) {
-    uint32_t i = u.z + threadIdx.x + k * kJBlock;
-    r.key[k] = a.fkey[i < u.w ? i : u.w - 1];
-  }
-}
-
-__device__ __forceinline__ void load_payload(const JoinArgs& a, uint32_t i0, uint32_t fhi, RowRegs& r) {
-#pragma unroll
-  for (int k = 0; k < kJR; ++k) {
+  for (int k = 0; k < kGR; ++k) {
     uint32_t i = i0 + k * kJBlock;
     i = i < fhi ? i : fhi - 1;
     r.sp[k] = (uint64_t)a.fprice[i];
@@ -931,8 +915,21 @@ __device__ __forceinline__ void load_payload(const JoinArgs& a, uint32_t i0, uin
   }
 }
 
-// Output room for `total` groups. Like take_ticket, the address is not provably
-// uniform, so the wave waits for the result only where it is used.
+// The next unit's dim keys and the keys of its first step of fact rows (its
+// prices and quantities follow at the start of the unit, so they do not hold
+// registers through this unit).
+__device__ __forceinline__ void prefetch_unit(const JoinArgs& a, uint4 u, int32_t (&dk)[kJDK], KeyRegs& r) {
+#pragma unroll
+  for (int k = 0; k < kJDK; ++k) {
+    const uint32_t j = u.x + threadIdx.x + k * kJBlock;
+    dk[k] = a.dkey[j < u.y ? j : u.y - 1];
+  }
+  load_keys(a, u.z + threadIdx.x, u.w, r);
+}
+
+// Output room for `total` groups. The address is not provably uniform (see
+// unhoisted_zero_offset), so the wave waits for the result only where it is
+// used.
 __device__ __forceinline__ int64_t reserve_nowait(const JoinArgs& a, uint32_t total) {
   unsigned long long* p = (unsigned long long*)a.d_n + unhoisted_zero_offset(a.zero);
   return (int64_t)__hip_atomic_fetch_add(p, (unsigned long long)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1003,16 +1000,16 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
   const int64_t n_units = *a.n_units;
   const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   uint64_t matched = 0;
-  // Units come from the largest-first list by ticket (dynamic, so a workgroup
-  // held up by a long unit takes fewer). Thread 0 runs two units ahead: at the
-  // start of a unit it asks for the ticket after next and reads the next
-  // unit's descriptor (its ticket arrived during the previous unit), and
-  // publishes it after the probe, so neither round trip delays the unit.
-  // Every thread then issues the next unit's dim-key and first fact-row loads.
-  int64_t t_ahead = 0;  // thread 0: ticket of the next unit
+  // Units come from the largest-first list in static round robin (see
+  // take_ticket). Thread 0 runs a unit ahead: at the start of a unit it reads
+  // the next unit's descriptor and publishes it after the probe, so the read
+  // never delays a unit. Every thread then issues the next unit's dim-key and
+  // first fact-row loads.
+  int64_t t_ahead = 0;  // thread 0: the next unit
+  int64_t seq = blockIdx.x;
   if (tid == 0) {
     const int64_t t = blockIdx.x;  // first unit without a round trip
-    t_ahead = take_ticket(a);
+    t_ahead = take_ticket(a, seq);
     s_u = t;
     if (t < n_units) {
       s_desc = a.unit_desc[t];
@@ -1028,43 +1025,60 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
   uint4 d = s_desc;
   uint2 sp = s_split;
   int32_t dkeys[kJDK];
-  RowRegs cur, nxt;
-  if (u < n_units) prefetch_unit(a, d, dkeys, cur);
+  KeyRegs ck, nk;  // this step's keys; the next step's (or the next unit's first step's)
+  PayRegs pay;
+  if (u < n_units) prefetch_unit(a, d, dkeys, nk);
   while (u < n_units) {
     const uint32_t dlo = d.x, dhi = d.y, flo = d.z, fhi = d.w;
-    load_payload(a, flo + tid, fhi, cur);
+    load_payload(a, flo + tid, fhi, pay);
     int64_t t_req = 0;
     uint4 nd = make_uint4(0, 0, 0, 0);
     uint2 ns = make_uint2(0, 0);
     if (tid == 0) {
-      // the descriptor loads go out before the ticket atomic, so waiting for
-      // them (before the build's barrier) never waits for the atomic as well
       if (t_ahead < n_units) {
         nd = a.unit_desc[t_ahead];
         ns = a.unit_split[t_ahead];
       }
-      t_req = take_ticket(a);
+      t_req = take_ticket(a, seq);
     }
-    // build: at most kJChunk unique keys into kJSlots slots, so a free slot always exists
+    // build: at most kJChunk unique keys into kJSlots slots, so a free slot
+    // always exists. Every key's first compare-and-swap is issued before any
+    // result is examined (one LDS round trip for most keys); keys whose home
+    // slot was taken walk on one slot at a time.
+    {
+      uint32_t h[kJDK];
+      uint64_t old[kJDK];
 #pragma unroll
-    for (int k = 0; k < kJDK; ++k) {
-      const uint32_t pos = tid + k * kJBlock;
-      if (dlo + pos >= dhi) continue;
-      const int32_t key = dkeys[k];
-      const uint64_t want = (uint64_t)(uint32_t)key | (sp.x != 0 ? (uint64_t)pos << (32 + kPosShift) : 0ull);
-      uint32_t h = slot_hash(key);
-      for (int step = 0; step < kJSlots; ++step) {
-        const uint64_t old = atomicCAS((unsigned long long*)&tkc[h], (unsigned long long)kLdsEmpty, (unsigned long long)want);
-        if (old == kLdsEmpty) {
-          tsp[h] = 0;
-          tsq[h] = 0;
-          break;
+      for (int k = 0; k < kJDK; ++k) {
+        const uint32_t pos = tid + k * kJBlock;
+        h[k] = slot_hash(dkeys[k]);
+        old[k] = kLdsEmpty;
+        if (dlo + pos < dhi) {
+          const uint64_t want = (uint64_t)(uint32_t)dkeys[k] | (sp.x != 0 ? (uint64_t)pos << (32 + kPosShift) : 0ull);
+          old[k] = atomicCAS((unsigned long long*)&tkc[h[k]], (unsigned long long)kLdsEmpty, (unsigned long long)want);
         }
-        if ((uint32_t)old == (uint32_t)key) {
-          set_status(a.status, kDevDupKey);
-          break;
+      }
+#pragma unroll
+      for (int k = 0; k < kJDK; ++k) {
+        const uint32_t pos = tid + k * kJBlock;
+        if (dlo + pos >= dhi) continue;
+        const int32_t key = dkeys[k];
+        const uint64_t want = (uint64_t)(uint32_t)key | (sp.x != 0 ? (uint64_t)pos << (32 + kPosShift) : 0ull);
+        uint32_t hh = h[k];
+        uint64_t o = old[k];
+        for (int step = 0; step < kJSlots; ++step) {
+          if (o == kLdsEmpty) {
+            tsp[hh] = 0;
+            tsq[hh] = 0;
+            break;
+          }
+          if ((uint32_t)o == (uint32_t)key) {
+            set_status(a.status, kDevDupKey);
+            break;
+          }
+          hh = (hh + 1) & (kJSlots - 1);
+          o = atomicCAS((unsigned long long*)&tkc[hh], (unsigned long long)kLdsEmpty, (unsigned long long)want);
         }
-        h = (h + 1) & (kJSlots - 1);
       }
     }
     __syncthreads();
@@ -1072,43 +1086,58 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
     int32_t ndkeys[kJDK];
     // probe and aggregate in LDS; long units stream further steps through nxt
     const uint32_t nrows = fhi - flo;
-    const uint32_t iters = (nrows + kJR * kJBlock - 1) / (kJR * kJBlock);  // uniform over the workgroup
+    const uint32_t iters = (nrows + kGR * kJBlock - 1) / (kGR * kJBlock);  // uniform over the workgroup
     // The next unit's descriptor is published at the end of the probe (so no
     // thread waits at the build barrier for thread 0's read of it); its loads
     // go out then and travel during the emission.
+    const bool combine = sp.x != 0;
     for (uint32_t it = 0; it < iters; ++it) {
-      const uint32_t i0 = flo + it * (kJR * kJBlock) + tid;
-      if (it > 0) cur = nxt;
-      if (it + 1 < iters) load_rows(a, i0 + kJR * kJBlock, fhi, nxt);
-      // find every row's slot first, then update: the LDS reads of the finds
-      // are not queued behind the previous row's atomics
-      bool fnd[kJR];
-      int slt[kJR];
+      const uint32_t i0 = flo + it * (kGR * kJBlock) + tid;
+      ck = nk;
+      if (it > 0) load_payload(a, i0, fhi, pay);
+      if (it + 1 < iters) load_keys(a, i0 + kGR * kJBlock, fhi, nk);
+      // find every row's slot first, then update: all rows' home slots are
+      // read before any is examined (one LDS round trip for most rows), so
+      // the finds are not a chain of dependent reads; rows whose home slot
+      // holds another key walk on. The updates follow, not queued behind
+      // the finds.
+      bool fnd[kGR];
+      int slt[kGR];
+      {
+        uint64_t c[kGR];
 #pragma unroll
-      for (int k = 0; k < kJR; ++k) {
-        fnd[k] = false;
-        slt[k] = 0;
-        if (i0 + k * kJBlock < fhi) {
-          uint32_t h = slot_hash(cur.key[k]);
+        for (int k = 0; k < kGR; ++k) {
+          slt[k] = (int)slot_hash(ck.key[k]);
+          c[k] = tkc[slt[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < kGR; ++k) {
+          fnd[k] = false;
+          if (i0 + k * kJBlock >= fhi) continue;
+          uint32_t h = (uint32_t)slt[k];
+          uint64_t cc = c[k];
           for (int step = 0; step < kJSlots; ++step) {
-            const uint64_t c = tkc[h];
-            if (c == kLdsEmpty) break;
-            if ((uint32_t)c == (uint32_t)cur.key[k]) {
+            if (cc == kLdsEmpty) break;
+            if ((uint32_t)cc == (uint32_t)ck.key[k]) {
               fnd[k] = true;
-              slt[k] = (int)h;
               break;
             }
             h = (h + 1) & (kJSlots - 1);
+            cc = tkc[h];
           }
+          slt[k] = (int)h;
         }
       }
 #pragma unroll
-      for (int k = 0; k < kJR; ++k) {
+      for (int k = 0; k < kGR; ++k) {
         bool found = fnd[k];
         const int slot = slt[k];
         matched += found;
         // Hot keys: when many lanes of the wave hit one slot, pre-sum them so the
         // LDS sees one update instead of a serialised run of same-address atomics.
+        // Only sub-units of split chunks check: the hottest keys are what makes
+        // a chunk split, and elsewhere the check costs more than it saves.
+        if (combine) {
         const uint64_t act = wave_ballot(found);
         if (act == 0) continue;
         const int first = __ffsll((long long)act) - 1;
@@ -1116,8 +1145,8 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
         const uint64_t same = wave_ballot(found && slot == s0);
         if (__popcll(same) >= kCombineMin) {
           const bool mine = found && slot == s0;
-          const uint64_t tsum_p = wave_sum_u64(mine ? cur.sp[k] : 0);
-          const uint64_t tsum_q = wave_sum_u64(mine ? (uint64_t)(int64_t)cur.qty[k] : 0);
+          const uint64_t tsum_p = wave_sum_u64(mine ? pay.sp[k] : 0);
+          const uint64_t tsum_q = wave_sum_u64(mine ? (uint64_t)(int64_t)pay.qty[k] : 0);
           if ((int)lane == first) {
             atomicAdd((unsigned long long*)&tsp[s0], (unsigned long long)tsum_p);
             atomicAdd((unsigned long long*)&tsq[s0], (unsigned long long)tsum_q);
@@ -1125,9 +1154,10 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
           }
           found = found && !mine;
         }
+        }
         if (found) {
-          atomicAdd((unsigned long long*)&tsp[slot], (unsigned long long)cur.sp[k]);
-          atomicAdd((unsigned long long*)&tsq[slot], (unsigned long long)(int64_t)cur.qty[k]);
+          atomicAdd((unsigned long long*)&tsp[slot], (unsigned long long)pay.sp[k]);
+          atomicAdd((unsigned long long*)&tsq[slot], (unsigned long long)(int64_t)pay.qty[k]);
           atomicAdd((unsigned long long*)&tkc[slot], 1ull << 32);
         }
       }
@@ -1171,7 +1201,7 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
       }
       int64_t resv = 0;
       if (tid == 0 && total) resv = reserve_nowait(a, total);
-      prefetch_unit(a, pd, ndkeys, nxt);
+      prefetch_unit(a, pd, ndkeys, nk);
       if (tid == 0) s_excl = (uint64_t)resv;
       __syncthreads();
       const int64_t o0 = (int64_t)s_excl;
@@ -1185,7 +1215,7 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
     } else {
       // Sub-unit of a split chunk: add the partial sums into the chunk's
       // accumulator; the last sub-unit to finish emits and clears it.
-      prefetch_unit(a, pd, ndkeys, nxt);
+      prefetch_unit(a, pd, ndkeys, nk);
       SplitAcc* acc = a.split_acc + (size_t)(sp.x - 1) * kJChunk;
 #pragma unroll
       for (int k = 0; k < kJPer; ++k) {
@@ -1237,7 +1267,6 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
     sp = sn;
 #pragma unroll
     for (int k = 0; k < kJDK; ++k) dkeys[k] = ndkeys[k];
-    cur = nxt;
   }
   matched = wave_sum_u64(matched);
   if (lane == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
@@ -1275,9 +1304,11 @@ struct AggArgs {
   uint32_t zero;  // 0 at run time; see take_ticket
 };
 
-__device__ __forceinline__ int64_t take_ticket(const AggArgs& a) {
-  unsigned long long* t = (unsigned long long*)a.ticket + unhoisted_zero_offset(a.zero);
-  return (int64_t)gridDim.x + (int64_t)__hip_atomic_fetch_add(t, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Units by static round robin, as in k_part_groupjoin.
+__device__ __forceinline__ int64_t take_ticket(const AggArgs& a, int64_t& seq) {
+  (void)a;
+  seq += gridDim.x;
+  return seq;
 }
 
 template <bool FL>
@@ -1335,12 +1366,13 @@ __global__ __launch_bounds__(kABlock, 4) void k_part_join_agg(AggArgs a) {
   const uint32_t tid = threadIdx.x, lane = lane_id();
   uint64_t matched = 0;
   grp.init(tid, kABlock);
-  // units by ticket from the largest-first list, thread 0 two tickets ahead
-  // (as in k_part_groupjoin)
+  // units in static round robin from the largest-first list, thread 0 a unit
+  // ahead (as in k_part_groupjoin)
   int64_t t_ahead = 0;
+  int64_t seq = blockIdx.x;
   if (tid == 0) {
     const int64_t t = blockIdx.x;  // first unit without a round trip
-    t_ahead = take_ticket(a);
+    t_ahead = take_ticket(a, seq);
     s_u = t;
     if (t < n_units) {
       s_desc = a.unit_desc[t];
@@ -1367,7 +1399,7 @@ __global__ __launch_bounds__(kABlock, 4) void k_part_join_agg(AggArgs a) {
         nd = a.unit_desc[t_ahead];
         ns = a.unit_split[t_ahead];
       }
-      t_req = take_ticket(a);
+      t_req = take_ticket(a, seq);
     }
     for (int s = tid; s < kJSlots; s += kABlock) tkey[s] = kLdsEmpty;
     __syncthreads();
@@ -1506,11 +1538,12 @@ __global__ __launch_bounds__(kABlock, 4) void k_part_join_eager(AggArgs a) {
   const uint32_t tid = threadIdx.x, lane = lane_id();
   uint64_t matched = 0;
   cache.init(tid, kABlock);
-  // units by ticket from the largest-first list, thread 0 two tickets ahead
+  // units in static round robin from the largest-first list, thread 0 a unit ahead
   int64_t t_ahead = 0;
+  int64_t seq = blockIdx.x;
   if (tid == 0) {
     const int64_t t = blockIdx.x;  // first unit without a round trip
-    t_ahead = take_ticket(a);
+    t_ahead = take_ticket(a, seq);
     s_u = t;
     if (t < n_units) {
       s_desc = a.unit_desc[t];
@@ -1537,7 +1570,7 @@ __global__ __launch_bounds__(kABlock, 4) void k_part_join_eager(AggArgs a) {
         nd = a.unit_desc[t_ahead];
         ns = a.unit_split[t_ahead];
       }
-      t_req = take_ticket(a);
+      t_req = take_ticket(a, seq);
     }
     for (int s = tid; s < kJSlots; s += kABlock) tkc[s] = kLdsEmpty;
     __syncthreads();
