@@ -2,10 +2,11 @@
 // pass: single-pass prefix scan with decoupled look-back (Merrill and
 // Garland, 2016).
 //
-// Tiles are handed out by an atomic ticket, not by blockIdx, so every tile a
-// workgroup waits on belongs to a workgroup that is already running and that
-// publishes its own count before it looks back: the wait always ends. The
-// first wave does the look-back, reading 64 predecessor states per round.
+// Groups of four consecutive tiles are handed out by an atomic ticket, not by
+// blockIdx, so every group a workgroup waits on belongs to a workgroup that is
+// already running and that publishes its own count before it looks back: the
+// wait always ends. The first wave does the look-back, reading 64 predecessor
+// states per round.
 //
 // A thread tests 32 consecutive rows (eight 16-byte loads); the tile's
 // selected row numbers are staged in LDS in output order and written out by
@@ -23,6 +24,10 @@ using namespace rel;
 constexpr int kBlock = 256;
 constexpr int kIPT = 32;  // rows per thread: eight 16-byte loads
 constexpr int64_t kTile = (int64_t)kBlock * kIPT;
+// Consecutive tiles a workgroup takes with one ticket. Every ticket is an
+// atomic on one cache line, and atomics on one line serialise on this chip
+// at about 12 ns each; four tiles per ticket keep that line out of the way.
+constexpr int64_t kTilesPerTicket = 4;
 
 template <int OP>
 __device__ __forceinline__ bool pred(int32_t v, int32_t lit) {
@@ -34,20 +39,9 @@ __device__ __forceinline__ bool pred(int32_t v, int32_t lit) {
   return v != lit;
 }
 
+// Row bits of one thread for one tile: bit k = row r0 + k passes.
 template <int OP>
-__global__ __launch_bounds__(kBlock) void k_filter_compact(const int32_t* __restrict__ col, int64_t n, int32_t lit,
-                                                           int32_t* __restrict__ out, uint64_t* __restrict__ state,
-                                                           int64_t* __restrict__ ticket, int64_t* __restrict__ d_count,
-                                                           int64_t ntiles) {
-  __shared__ int64_t s_tile;
-  __shared__ int64_t s_excl;
-  __shared__ uint32_t s_wave[kBlock / kWave];
-  __shared__ int32_t s_rows[kTile];
-  if (threadIdx.x == 0) s_tile = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)ticket, 1ull);
-  __syncthreads();
-  const int64_t tile = s_tile;
-  const int64_t r0 = tile * kTile + (int64_t)threadIdx.x * kIPT;
-
+__device__ __forceinline__ uint32_t tile_bits(const int32_t* __restrict__ col, int64_t n, int32_t lit, int64_t r0) {
   uint32_t bits = 0;
   if (r0 + kIPT <= n) {
 #pragma unroll
@@ -62,49 +56,92 @@ __global__ __launch_bounds__(kBlock) void k_filter_compact(const int32_t* __rest
     for (int k = 0; k < kIPT; ++k)
       if (r0 + k < n) bits |= (uint32_t)pred<OP>(col[r0 + k], lit) << k;
   }
-  const uint32_t c = __popc(bits);
+  return bits;
+}
 
-  // Exclusive scan of c over the workgroup: wave scan, then wave totals.
+// One workgroup per ticket, and a ticket is kTilesPerTicket consecutive
+// tiles (a group): the group's rows are all tested first, its count is
+// published and looked back once (the look-back state is per group, so no
+// group waits on the end of another group's writes), then its tiles are
+// staged and written one after another. Per-thread counts of the group's
+// tiles travel packed in one 64-bit word, 16 bits per tile (a tile holds at
+// most 8192 rows), so one scan serves them all.
+template <int OP>
+__global__ __launch_bounds__(kBlock) void k_filter_compact(const int32_t* __restrict__ col, int64_t n, int32_t lit,
+                                                           int32_t* __restrict__ out, uint64_t* __restrict__ state,
+                                                           int64_t* __restrict__ ticket, int64_t* __restrict__ d_count,
+                                                           int64_t ngroups) {
+  static_assert(kTile < (1 << 16) && kTilesPerTicket * 16 <= 64, "packed per-tile counts");
+  __shared__ int64_t s_group;
+  __shared__ int64_t s_excl;
+  __shared__ uint64_t s_wave[kBlock / kWave];
+  __shared__ int32_t s_rows[kTile];
+  if (threadIdx.x == 0) s_group = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)ticket, 1ull);
+  __syncthreads();
+  const int64_t group = s_group;
+  const int64_t t0 = group * kTilesPerTicket;
+  uint32_t bits[kTilesPerTicket];
+  uint64_t c = 0;
+#pragma unroll
+  for (int g = 0; g < kTilesPerTicket; ++g) {
+    const int64_t r0 = (t0 + g) * kTile + (int64_t)threadIdx.x * kIPT;
+    bits[g] = r0 < n ? tile_bits<OP>(col, n, lit, r0) : 0u;
+    c |= (uint64_t)__popc(bits[g]) << (16 * g);
+  }
+
+  // Exclusive scan of the packed counts over the workgroup: wave scan, then wave totals.
   const uint32_t lane = lane_id();
   const uint32_t wave = threadIdx.x / kWave;
-  uint32_t incl = c;
+  uint64_t incl = c;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t t = __shfl_up(incl, o, kWave);
+    const uint64_t t = (uint64_t)__shfl_up((unsigned long long)incl, o, kWave);
     if (lane >= (uint32_t)o) incl += t;
   }
   if (lane == kWave - 1) s_wave[wave] = incl;
   __syncthreads();
-  uint32_t wave_off = 0, total = 0;
+  uint64_t wave_off = 0, total = 0;
 #pragma unroll
   for (int w = 0; w < kBlock / kWave; ++w) {
-    const uint32_t t = s_wave[w];
-    wave_off += (uint32_t)w < wave ? t : 0u;
+    const uint64_t t = s_wave[w];
+    wave_off += (uint32_t)w < wave ? t : 0ull;
     total += t;
   }
-  const uint32_t my_off = wave_off + incl - c;
+  const uint64_t my_off = wave_off + incl - c;
+  uint32_t group_total = 0;
+#pragma unroll
+  for (int g = 0; g < kTilesPerTicket; ++g) group_total += (uint32_t)(total >> (16 * g)) & 0xFFFFu;
 
   // Publish, then look back (the first wave).
   if (wave == 0) {
-    const uint64_t excl = lookback_prefix(state, tile, total);
+    const uint64_t excl = lookback_prefix(state, group, group_total);
     if (threadIdx.x == 0) {
       s_excl = (int64_t)excl;
-      if (tile == ntiles - 1) *d_count = s_excl + total;
+      if (group == ngroups - 1) *d_count = s_excl + group_total;
     }
   }
-  uint32_t o = my_off;
-  for (int k = 0; k < kIPT; ++k)
-    if (bits & (1u << k)) s_rows[o++] = (int32_t)(r0 + k);
-  __syncthreads();
-  int32_t* dst = out + s_excl;
-  for (uint32_t j = threadIdx.x; j < total; j += kBlock) dst[j] = s_rows[j];
+  uint32_t before = 0;  // rows of the group's earlier tiles
+#pragma unroll
+  for (int g = 0; g < kTilesPerTicket; ++g) {
+    const int64_t r0 = (t0 + g) * kTile + (int64_t)threadIdx.x * kIPT;
+    const uint32_t tile_total = (uint32_t)(total >> (16 * g)) & 0xFFFFu;
+    uint32_t o = (uint32_t)(my_off >> (16 * g)) & 0xFFFFu;
+    for (int k = 0; k < kIPT; ++k)
+      if (bits[g] & (1u << k)) s_rows[o++] = (int32_t)(r0 + k);
+    __syncthreads();
+    int32_t* dst = out + s_excl + before;
+    for (uint32_t j = threadIdx.x; j < tile_total; j += kBlock) dst[j] = s_rows[j];
+    before += tile_total;
+    __syncthreads();  // s_rows is reused by the next tile
+  }
 }
 
 template <int OP>
 void launch(hipStream_t stream, const int32_t* col, int64_t n, int32_t lit, int32_t* out, uint64_t* state,
             int64_t* ticket, int64_t* d_count, int64_t ntiles) {
-  hipLaunchKernelGGL(k_filter_compact<OP>, dim3((unsigned)ntiles), dim3(kBlock), 0, stream, col, n, lit, out, state,
-                     ticket, d_count, ntiles);
+  const int64_t ngroups = (ntiles + kTilesPerTicket - 1) / kTilesPerTicket;
+  hipLaunchKernelGGL(k_filter_compact<OP>, dim3((unsigned)ngroups), dim3(kBlock), 0, stream, col, n, lit, out, state,
+                     ticket, d_count, ngroups);
 }
 
 void launch_op(hipStream_t stream, rel_cmp op, const int32_t* col, int64_t n, int32_t lit, int32_t* out,

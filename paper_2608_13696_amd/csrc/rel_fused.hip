@@ -213,13 +213,19 @@ struct OutArgs {
 };
 
 // Group finalization: stream compaction of the occupied slots into the
-// output. Each workgroup takes a tile by ticket, counts its occupied slots,
+// output. Each workgroup takes a group of kFinTilesPerTicket consecutive
+// tiles by ticket, counts the group's occupied slots (per tile, packed 16
+// bits a tile in one word for a single scan),
 // and finds its output offset by decoupled look-back, so no single output
 // counter is contended. A thread's slots are kBlock apart, so each count read
 // of a wave covers consecutive slots; the groups come out in tile order and,
 // inside a tile, thread by thread (the output order is unspecified).
 constexpr int kFinIPT = 8;
 constexpr int64_t kFinTile = (int64_t)kBlock * kFinIPT;
+// Consecutive tiles per ticket (one look-back per group of them): tickets
+// are atomics on one cache line, which serialise on this chip at about 12 ns
+// each.
+constexpr int64_t kFinTilesPerTicket = 4;
 
 struct SlotSource {  // group table; the last slot holds the key INT64_MIN
   const GroupSlot* slots;
@@ -249,45 +255,77 @@ struct RowAggSource {  // groupjoin accumulators; the key is the dim row's pk
 
 template <class Src>
 __global__ __launch_bounds__(kBlock) void k_finalize(Src src, int64_t nitems, OutArgs o, uint64_t* __restrict__ state,
-                                                     int64_t* __restrict__ ticket, int64_t ntiles) {
-  __shared__ int64_t s_tile;
+                                                     int64_t* __restrict__ ticket, int64_t ngroups) {
+  static_assert(kFinTile < (1 << 16) && kFinTilesPerTicket * 16 <= 64, "packed per-tile counts");
+  __shared__ int64_t s_group;
   __shared__ uint64_t s_excl;
-  __shared__ uint32_t scr[kBlock / kWave];
-  if (threadIdx.x == 0) s_tile = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)ticket, 1ull);
+  __shared__ uint64_t s_wave[kBlock / kWave];
+  if (threadIdx.x == 0) s_group = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)ticket, 1ull);
   __syncthreads();
-  const int64_t tile = s_tile;
-  const int64_t i0 = tile * kFinTile + (int64_t)threadIdx.x;  // slot of bit k: i0 + k * kBlock
-  uint32_t bits = 0;
+  const int64_t group = s_group;
+  const int64_t t0 = group * kFinTilesPerTicket;
+  uint32_t bits[kFinTilesPerTicket];
+  uint64_t c = 0;
 #pragma unroll
-  for (int k = 0; k < kFinIPT; ++k) {
-    const int64_t i = i0 + (int64_t)k * kBlock;
-    if (i < nitems && src.occupied(i)) bits |= 1u << k;
+  for (int g = 0; g < kFinTilesPerTicket; ++g) {
+    const int64_t i0 = (t0 + g) * kFinTile + (int64_t)threadIdx.x;  // slot of bit k: i0 + k * kBlock
+    bits[g] = 0;
+#pragma unroll
+    for (int k = 0; k < kFinIPT; ++k) {
+      const int64_t i = i0 + (int64_t)k * kBlock;
+      if (i < nitems && src.occupied(i)) bits[g] |= 1u << k;
+    }
+    c |= (uint64_t)__popc(bits[g]) << (16 * g);
   }
-  uint32_t total;
-  const uint32_t off = block_excl_scan<kBlock>((uint32_t)__popc(bits), scr, &total);
-  if (threadIdx.x < kWave) {
-    const uint64_t excl = lookback_prefix(state, tile, total);
+  const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+  uint64_t incl = c;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint64_t t = (uint64_t)__shfl_up((unsigned long long)incl, d, kWave);
+    if (lane >= (uint32_t)d) incl += t;
+  }
+  if (lane == kWave - 1) s_wave[wave] = incl;
+  __syncthreads();
+  uint64_t wave_off = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / kWave; ++w) {
+    const uint64_t t = s_wave[w];
+    wave_off += (uint32_t)w < wave ? t : 0ull;
+    total += t;
+  }
+  const uint64_t my_off = wave_off + incl - c;
+  uint32_t group_total = 0;
+#pragma unroll
+  for (int g = 0; g < kFinTilesPerTicket; ++g) group_total += (uint32_t)(total >> (16 * g)) & 0xFFFFu;
+  if (wave == 0) {
+    const uint64_t excl = lookback_prefix(state, group, group_total);
     if (threadIdx.x == 0) {
       s_excl = excl;
-      if (tile == ntiles - 1) *o.d_n = (int64_t)(excl + total);
+      if (group == ngroups - 1) *o.d_n = (int64_t)(excl + group_total);
     }
   }
   __syncthreads();
-  int64_t pos = (int64_t)s_excl + off;
-  for (int k = 0; k < kFinIPT; ++k) {
-    if (!(bits & (1u << k))) continue;
-    if (pos < o.cap) {
-      int64_t key;
-      uint64_t sp, sq, cnt;
-      src.get(i0 + (int64_t)k * kBlock, &key, &sp, &sq, &cnt);
-      o.key[pos] = key;
-      o.sum_price[pos] = (int64_t)sp;
-      o.sum_qty[pos] = (int64_t)sq;
-      o.count[pos] = (int64_t)cnt;
-    } else {
-      set_status(o.status, kDevOverflow);
+  int64_t before = 0;  // groups of the earlier tiles of this ticket
+#pragma unroll
+  for (int g = 0; g < kFinTilesPerTicket; ++g) {
+    const int64_t i0 = (t0 + g) * kFinTile + (int64_t)threadIdx.x;
+    int64_t pos = (int64_t)s_excl + before + (int64_t)((my_off >> (16 * g)) & 0xFFFFu);
+    for (int k = 0; k < kFinIPT; ++k) {
+      if (!(bits[g] & (1u << k))) continue;
+      if (pos < o.cap) {
+        int64_t key;
+        uint64_t sp, sq, cnt;
+        src.get(i0 + (int64_t)k * kBlock, &key, &sp, &sq, &cnt);
+        o.key[pos] = key;
+        o.sum_price[pos] = (int64_t)sp;
+        o.sum_qty[pos] = (int64_t)sq;
+        o.count[pos] = (int64_t)cnt;
+      } else {
+        set_status(o.status, kDevOverflow);
+      }
+      ++pos;
     }
-    ++pos;
+    before += (total >> (16 * g)) & 0xFFFFu;
   }
 }
 
@@ -302,8 +340,9 @@ rel_status finalize(rel_ctx* ctx, const Src& src, int64_t nitems, const OutArgs&
   int64_t* ticket = relh::counters(ctx) + CNT_TICKET;
   if ((s = relh::fill_u64(ctx, ticket, 1, 0)) != REL_OK) return s;
   relh::KernelTimer kt(ctx, "finalize");
-  hipLaunchKernelGGL(k_finalize<Src>, dim3((unsigned)ntiles), dim3(kBlock), 0, ctx->stream, src, nitems, o,
-                     (uint64_t*)st, ticket, ntiles);
+  const int64_t ngroups = (ntiles + kFinTilesPerTicket - 1) / kFinTilesPerTicket;
+  hipLaunchKernelGGL(k_finalize<Src>, dim3((unsigned)ngroups), dim3(kBlock), 0, ctx->stream, src, nitems, o,
+                     (uint64_t*)st, ticket, ngroups);
   REL_LAUNCH_CHECK(ctx, "finalize");
   return REL_OK;
 }

@@ -33,12 +33,17 @@ __global__ __launch_bounds__(256) void k_join_build(const int32_t* __restrict__ 
 // Probe: a wave takes 8 x 64 consecutive probe rows per step, one row of each
 // 64 per lane. Every lane issues the first-slot loads of its eight rows
 // together (the random table reads are the cost, so eight are in flight per
-// lane instead of one), then finishes each probe. Matches are compacted with
-// one ballot per row group and the wave reserves output space for all eight
-// groups with one atomic. Output order is therefore unspecified.
-// On 28.15M probes into a 15M-key table: 0.78 ms with eight rows per lane,
-// 1.40 ms with four, 5.31 ms with one; sixteen spill the ballot masks.
+// lane instead of one), then finishes each probe. A wave runs kProbeGroup
+// steps, keeping each row's match in registers, and then reserves output
+// space for all of them with one atomic: the count is one word, and atomics
+// on one cache line serialise on this chip at about 12 ns each, so one per
+// step (512 rows) bounded the kernel. Matches are compacted with one ballot
+// per row group. Output order is therefore unspecified.
+// On 28.15M probes into a 15M-key table: 0.78 ms with eight rows per lane and
+// one atomic per step, 1.40 ms with four, 5.31 ms with one; sixteen spill the
+// ballot masks.
 constexpr int kProbeRows = 8;
+constexpr int kProbeGroup = 4;
 
 __global__ __launch_bounds__(256) void k_join_probe(JoinView t, const int32_t* __restrict__ fk,
                                                     const int32_t* __restrict__ sel, int64_t n,
@@ -48,40 +53,48 @@ __global__ __launch_bounds__(256) void k_join_probe(JoinView t, const int32_t* _
   const int64_t wave_global = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   const uint32_t lane = lane_id();
-  for (int64_t base = wave_global * kStep; base < n; base += n_waves * kStep) {
-    int32_t row[kProbeRows], key[kProbeRows];
-    uint64_t first[kProbeRows];
+  for (int64_t base0 = wave_global * kStep * kProbeGroup; base0 < n; base0 += n_waves * kStep * kProbeGroup) {
+    int32_t hrow[kProbeGroup][kProbeRows];  // the matching fact row, or -1
+    int32_t hpl[kProbeGroup][kProbeRows];
+    uint32_t total = 0;
 #pragma unroll
-    for (int k = 0; k < kProbeRows; ++k) {
-      const int64_t i = base + k * kWave + lane;
-      row[k] = i < n ? (sel ? sel[i] : (int32_t)i) : -1;
-    }
+    for (int g = 0; g < kProbeGroup; ++g) {
+      const int64_t base = base0 + g * kStep;
+      int32_t row[kProbeRows], key[kProbeRows];
+      uint64_t first[kProbeRows];
 #pragma unroll
-    for (int k = 0; k < kProbeRows; ++k) key[k] = row[k] >= 0 ? fk[row[k]] : 0;
+      for (int k = 0; k < kProbeRows; ++k) {
+        const int64_t i = base + k * kWave + lane;
+        row[k] = i < n ? (sel ? sel[i] : (int32_t)i) : -1;
+      }
 #pragma unroll
-    for (int k = 0; k < kProbeRows; ++k) first[k] = row[k] >= 0 ? t.slots[join_first_index(t, key[k])] : kJoinEmpty;
-    bool hit[kProbeRows];
-    int32_t pl[kProbeRows];
-    uint64_t bal[kProbeRows];
-    uint32_t pre[kProbeRows], total = 0;
+      for (int k = 0; k < kProbeRows; ++k) key[k] = row[k] >= 0 ? fk[row[k]] : 0;
 #pragma unroll
-    for (int k = 0; k < kProbeRows; ++k) {
-      pl[k] = 0;
-      hit[k] = row[k] >= 0 && join_finish(t, key[k], first[k], &pl[k]);
-      bal[k] = wave_ballot(hit[k]);
-      pre[k] = total;
-      total += (uint32_t)__popcll(bal[k]);
+      for (int k = 0; k < kProbeRows; ++k) first[k] = row[k] >= 0 ? t.slots[join_first_index(t, key[k])] : kJoinEmpty;
+#pragma unroll
+      for (int k = 0; k < kProbeRows; ++k) {
+        hpl[g][k] = 0;
+        const bool hit = row[k] >= 0 && join_finish(t, key[k], first[k], &hpl[g][k]);
+        hrow[g][k] = hit ? row[k] : -1;
+        total += (uint32_t)__popcll(wave_ballot(hit));
+      }
     }
     if (total == 0) continue;
     int64_t off = 0;
     if (lane == 0) off = dev_add_ret<unsigned long long>((unsigned long long*)d_count, (unsigned long long)total);
     off = __shfl(off, 0, kWave);
 #pragma unroll
-    for (int k = 0; k < kProbeRows; ++k) {
-      if (!hit[k]) continue;
-      const int64_t o = off + pre[k] + mask_rank(bal[k]);
-      out_fact[o] = row[k];
-      out_payload[o] = pl[k];
+    for (int g = 0; g < kProbeGroup; ++g) {
+#pragma unroll
+      for (int k = 0; k < kProbeRows; ++k) {
+        const uint64_t b = wave_ballot(hrow[g][k] >= 0);
+        if (hrow[g][k] >= 0) {
+          const int64_t o = off + mask_rank(b);
+          out_fact[o] = hrow[g][k];
+          out_payload[o] = hpl[g][k];
+        }
+        off += __popcll(b);
+      }
     }
   }
 }
