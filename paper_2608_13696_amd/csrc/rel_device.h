@@ -170,6 +170,59 @@ __device__ __forceinline__ bool join_finish(const JoinView& t, int32_t key, uint
   return false;
 }
 
+// ---- join index: dense array or hash table --------------------------------------------------------------------------
+//
+// When the build keys span a range no wider than the index's dense capacity
+// (surrogate keys numbered from some base, as dimension keys usually are),
+// entry key - kmin of a plain array identifies the key's dim row, and a probe
+// is one read at a computed address; otherwise the hash table above is used.
+// The choice is made on the device, from the keys' minimum and maximum, so no
+// host round trip is needed. An entry is 0 (no key) or the dim row j + 1; with
+// an int8 payload and fewer than 2^24 dim rows the payload byte sits in the
+// top 8 bits, so the probe needs no second read.
+constexpr int64_t kDensePackedRows = 1 << 24;  // int8 payloads are packed below this many dim rows
+
+struct JoinIndex {
+  JoinView hash;
+  uint32_t* dense;     // dense_cap entries
+  const uint32_t* mm;  // {max of ~(key ^ 2^31), max of (key ^ 2^31)}: the keys' min and max, order-encoded
+  int64_t dense_cap;
+  const void* payload;  // the dim payload column (int32 or int8), or null for row ids
+  int32_t pkind;        // relh::PayloadKind
+  int32_t packed;       // int8 payload packed into the entry
+};
+
+struct DenseRange {
+  int32_t kmin;
+  int64_t range;  // kmax - kmin + 1 (not positive when there are no keys)
+  bool dense;
+};
+
+__device__ __forceinline__ DenseRange dense_range(const JoinIndex& x) {
+  const uint32_t w0 = x.mm[0], w1 = x.mm[1];
+  DenseRange r;
+  r.kmin = (int32_t)(~w0 ^ 0x80000000u);
+  const int32_t kmax = (int32_t)(w1 ^ 0x80000000u);
+  r.range = (int64_t)kmax - (int64_t)r.kmin + 1;
+  r.dense = r.range <= x.dense_cap;
+  return r;
+}
+
+// The dense entry of a key: 0 when the key is outside the range or absent.
+__device__ __forceinline__ uint32_t dense_entry(const JoinIndex& x, const DenseRange& r, int32_t key) {
+  const int64_t off = (int64_t)key - r.kmin;
+  return (off >= 0 && off < r.range) ? x.dense[off] : 0u;
+}
+
+// Payload of a non-zero dense entry (PayloadKind values: 0 row id, 1 int32, 2 int8).
+__device__ __forceinline__ int32_t dense_payload(const JoinIndex& x, uint32_t e) {
+  if (x.packed) return (int32_t)(int8_t)(e >> 24);
+  const uint32_t j = e - 1u;
+  if (x.pkind == 1) return ((const int32_t*)x.payload)[j];
+  if (x.pkind == 2) return (int32_t)((const int8_t*)x.payload)[j];
+  return (int32_t)j;
+}
+
 // Insert (key, payload) into a join table with one 64-bit CAS per attempted
 // slot; a repeated key sets kDevDupKey, a full table kDevOverflow.
 __device__ __forceinline__ void join_insert(uint64_t* slots, uint32_t mask, uint32_t shift, int32_t key, int32_t pl,

@@ -40,7 +40,7 @@ struct FusedArgs {
   const int8_t* flag;
   int64_t n;
   int32_t day_lt;
-  JoinView join;
+  JoinIndex join;
   GroupView groups;
   RowAgg* row_agg;
   int64_t* counters;  // [0] rows passed, [1] join matches
@@ -103,6 +103,7 @@ __global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
     __syncthreads();
   }
   uint64_t passed = 0, matched = 0;
+  const DenseRange dr = dense_range(a.join);
   constexpr int64_t tile_rows = (int64_t)NT * kIPT;
   const int64_t ntiles = (a.n + tile_rows - 1) / tile_rows;
   int64_t tile = blockIdx.x;
@@ -111,21 +112,29 @@ __global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
   for (; tile < ntiles; tile += gridDim.x) {
     const int64_t tn = tile + gridDim.x;
     if (tn < ntiles) load_fused<MODE>(a, tn * tile_rows + (int64_t)threadIdx.x * kIPT, nxt);
-    // every row's first join slot is loaded before any is examined, so the
-    // tile's random reads overlap instead of following one another
+    // every row's first join read (its dense entry, or its first hash slot)
+    // is issued before any is examined, so the tile's random reads overlap
+    // instead of following one another
     bool pass[kIPT];
     uint64_t first[kIPT];
 #pragma unroll
     for (int k = 0; k < kIPT; ++k) {
       pass[k] = k < cur.nv && cur.d[k] < a.day_lt;
-      first[k] = pass[k] ? a.join.slots[join_first_index(a.join, cur.f[k])] : kJoinEmpty;
+      if (dr.dense) first[k] = pass[k] ? dense_entry(a.join, dr, cur.f[k]) : 0u;
+      else first[k] = pass[k] ? a.join.hash.slots[join_first_index(a.join.hash, cur.f[k])] : kJoinEmpty;
     }
 #pragma unroll
     for (int k = 0; k < kIPT; ++k) {
       // no early exits: the device-memory update below is a wave-wide call
       passed += pass[k];
       int32_t pl = 0;
-      const bool hit = pass[k] && join_finish(a.join, cur.f[k], first[k], &pl);
+      bool hit;
+      if (dr.dense) {
+        hit = first[k] != 0;
+        if (hit) pl = dense_payload(a.join, (uint32_t)first[k]);
+      } else {
+        hit = pass[k] && join_finish(a.join.hash, cur.f[k], first[k], &pl);
+      }
       matched += hit;
       const uint64_t sp = (uint64_t)cur.p[k], sq = (uint64_t)(int64_t)cur.q[k];
       if (GP == G_ROWAGG) {
@@ -392,9 +401,10 @@ rel_status launch_fused(rel_ctx* ctx, int gp, const FusedArgs& a, unsigned grid)
 // Fact tables at least this large take the radix-partitioned path unless a
 // plan says otherwise ...
 constexpr int64_t kPartitionMinRows = 1 << 20;
-// ... and, grouping by a dim attribute, at least this many dim rows (a plain
-// join table of 2^19 slots or more no longer fits one XCD's L2).
-constexpr int64_t kPartitionMinDim = 1 << 18;
+// ... and, grouping by a dim attribute, at least this many dim rows. Below
+// it the plain path's join index (a dense array of 4 B per key when the keys
+// are dense, 16 MB at this size) stays in the caches.
+constexpr int64_t kPartitionMinDim = 1 << 22;
 
 rel_status sync_stats(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, const rel_query* q, const rel_plan* plan,
                       rel_groups_out* out, rel_stats* stats, int64_t* cnt, int64_t join_cap, int64_t group_cap,
@@ -479,17 +489,19 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
     return sync_stats(ctx, fact, dim, q, plan, out, stats, cnt, m, m, REL_PLACE_PARTITIONED, REL_PLACE_PARTITIONED);
   }
 
-  // Join table: plain sizing (2m rounded up to a power of two), in device memory.
+  // rows passed, join matches, and the words that receive the keys' minimum and maximum
+  TRY(relh::fill_u64(ctx, cnt, CNT_AUX2 + 1, 0));
+  // Join index: a dense array when the dim keys span at most 2m values, else
+  // a hash table of plain sizing (2m rounded up to a power of two); both in
+  // device memory, the choice made on the device.
+  JoinIndex jx{};
   uint32_t jl = 0;
-  void* jt = nullptr;
   if (!part) {
     jl = relh::join_log2cap(m, nullptr);
-    TRY(relh::scratch(ctx, SCR_JOIN_TABLE, ((size_t)8 << jl) + 8, &jt));
     const void* payload = gb == REL_GROUP_PRIO_FLAG ? (const void*)dim->prio : gb == REL_GROUP_DIM_GRP ? (const void*)dim->grp : nullptr;
     const int pkind = gb == REL_GROUP_PRIO_FLAG ? relh::PAY_I8 : gb == REL_GROUP_DIM_GRP ? relh::PAY_I32 : relh::PAY_ROW_ID;
-    TRY(relh::join_build_into(ctx, dim->pk, payload, pkind, m, (uint64_t*)jt, jl));
+    TRY(relh::join_index_build(ctx, dim->pk, payload, pkind, m, (uint32_t*)(cnt + CNT_AUX2), &jx));
   }
-  TRY(relh::fill_u64(ctx, cnt, 2, 0));
 
   FusedArgs a{};
   a.fk = fact->fk;
@@ -499,7 +511,7 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
   a.flag = fact->flag;
   a.n = n;
   a.day_lt = q->day_lt;
-  a.join = JoinView{(const uint64_t*)jt, (uint32_t)((1ull << jl) - 1), 32u - jl};
+  a.join = jx;
   a.counters = cnt;
 
   int gp;

@@ -30,6 +30,7 @@ enum ScratchId : int {
   SCR_PART_E,
   SCR_SKETCH,
   SCR_MLP,
+  SCR_DENSE,           // dense join index entries
   SCR_COUNT
 };
 

@@ -30,6 +30,90 @@ __global__ __launch_bounds__(256) void k_join_build(const int32_t* __restrict__ 
   }
 }
 
+// ---- join index (dense array or hash table) ----------------------------------------------------------------------------
+
+// Minimum and maximum of the build keys, order-encoded so that both are
+// maxima over unsigned words that start at 0 (see JoinIndex::mm): one atomic
+// pair per workgroup.
+constexpr int kIdxBlock = 256;
+__global__ __launch_bounds__(kIdxBlock) void k_key_minmax(const int32_t* __restrict__ pk, int64_t m, uint32_t* mm) {
+  __shared__ uint32_t s_lo[kIdxBlock / kWave], s_hi[kIdxBlock / kWave];
+  uint32_t lo = 0, hi = 0;  // max of ~(key ^ 2^31), max of (key ^ 2^31)
+  for (int64_t j = blockIdx.x * (int64_t)kIdxBlock + threadIdx.x; j < m; j += (int64_t)gridDim.x * kIdxBlock) {
+    const uint32_t o = (uint32_t)pk[j] ^ 0x80000000u;
+    lo = max(lo, ~o);
+    hi = max(hi, o);
+  }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    lo = max(lo, (uint32_t)__shfl_xor((int)lo, d, kWave));
+    hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, kWave));
+  }
+  if (lane_id() == 0) {
+    s_lo[threadIdx.x / kWave] = lo;
+    s_hi[threadIdx.x / kWave] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kIdxBlock / kWave; ++w) {
+      lo = max(lo, s_lo[w]);
+      hi = max(hi, s_hi[w]);
+    }
+    __hip_atomic_fetch_max(&mm[0], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_max(&mm[1], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Clears whichever structure the keys' range selects: the dense entries in
+// [0, range) or the hash slots (capacity + the side slot).
+__global__ __launch_bounds__(kIdxBlock) void k_index_clear(JoinIndex x, int64_t hash_words) {
+  const DenseRange r = dense_range(x);
+  const int64_t stride = (int64_t)gridDim.x * kIdxBlock;
+  int64_t i = blockIdx.x * (int64_t)kIdxBlock + threadIdx.x;
+  if (r.dense) {
+    for (; i < r.range; i += stride) x.dense[i] = 0u;
+  } else {
+    uint64_t* slots = const_cast<uint64_t*>(x.hash.slots);
+    for (; i < hash_words; i += stride) slots[i] = kJoinEmpty;
+  }
+}
+
+__device__ __forceinline__ uint32_t dense_encode(const JoinIndex& x, int64_t j) {
+  const uint32_t e = (uint32_t)(j + 1);
+  return x.packed ? e | ((uint32_t)(uint8_t)((const int8_t*)x.payload)[j] << 24) : e;
+}
+
+// Dense: each dim row writes its entry with a plain store (a repeated key is
+// found by k_index_verify). Hash: one 64-bit CAS per attempted slot.
+template <int PK>
+__global__ __launch_bounds__(kIdxBlock) void k_index_build(const int32_t* __restrict__ pk, int64_t m, JoinIndex x,
+                                                           uint32_t* __restrict__ status) {
+  const DenseRange r = dense_range(x);
+  const int64_t stride = (int64_t)gridDim.x * kIdxBlock;
+  for (int64_t j = blockIdx.x * (int64_t)kIdxBlock + threadIdx.x; j < m; j += stride) {
+    const int32_t key = pk[j];
+    if (r.dense) {
+      x.dense[(int64_t)key - r.kmin] = dense_encode(x, j);
+    } else {
+      const int32_t pl = PK == PAY_ROW_ID ? (int32_t)j
+                         : PK == PAY_I32  ? ((const int32_t*)x.payload)[j]
+                                          : (int32_t)((const int8_t*)x.payload)[j];
+      join_insert(const_cast<uint64_t*>(x.hash.slots), x.hash.mask, x.hash.shift, key, pl, status);
+    }
+  }
+}
+
+// Dense only: a key stored twice keeps one of its rows' entries, so the other
+// row finds an entry that is not its own.
+__global__ __launch_bounds__(kIdxBlock) void k_index_verify(const int32_t* __restrict__ pk, int64_t m, JoinIndex x,
+                                                            uint32_t* __restrict__ status) {
+  const DenseRange r = dense_range(x);
+  if (!r.dense) return;
+  const int64_t stride = (int64_t)gridDim.x * kIdxBlock;
+  for (int64_t j = blockIdx.x * (int64_t)kIdxBlock + threadIdx.x; j < m; j += stride)
+    if (x.dense[(int64_t)pk[j] - r.kmin] != dense_encode(x, j)) set_status(status, kDevDupKey);
+}
+
 // Probe: a wave takes 8 x 64 consecutive probe rows per step, one row of each
 // 64 per lane. Every lane issues the first-slot loads of its eight rows
 // together (the random table reads are the cost, so eight are in flight per
@@ -126,6 +210,55 @@ rel_status join_build_into(rel_ctx* ctx, const int32_t* pk, const void* payload,
     hipLaunchKernelGGL(k_join_build<PAY_ROW_ID>, dim3(grid), dim3(256), 0, ctx->stream, pk, payload, m, slots, mask,
                        shift, ctx->d_status);
   REL_LAUNCH_CHECK(ctx, "join_build");
+  return REL_OK;
+}
+
+rel_status join_index_build(rel_ctx* ctx, const int32_t* pk, const void* payload, int payload_kind, int64_t m,
+                            uint32_t* mm, rel::JoinIndex* out) {
+  const uint32_t jl = join_log2cap(m, nullptr);
+  void *jt, *dt;
+  rel_status s;
+  if ((s = scratch(ctx, SCR_JOIN_TABLE, ((size_t)8 << jl) + 8, &jt)) != REL_OK) return s;
+  const int64_t dcap = 2 * (m > 8 ? m : 8);
+  if ((s = scratch(ctx, SCR_DENSE, (size_t)dcap * 4, &dt)) != REL_OK) return s;
+  rel::JoinIndex x{};
+  x.hash = rel::JoinView{(const uint64_t*)jt, (uint32_t)((1ull << jl) - 1), 32u - jl};
+  x.dense = (uint32_t*)dt;
+  x.mm = mm;
+  x.dense_cap = dcap;
+  x.payload = payload;
+  x.pkind = payload_kind;
+  x.packed = payload_kind == PAY_I8 && m < rel::kDensePackedRows;
+  const unsigned gm = grid_for(ctx, m, kIdxBlock * 8, 1);
+  {
+    KernelTimer kt(ctx, "join_index_minmax");
+    if (m > 0) hipLaunchKernelGGL(k_key_minmax, dim3(gm < 128 ? gm : 128), dim3(kIdxBlock), 0, ctx->stream, pk, m, mm);
+  }
+  {
+    KernelTimer kt(ctx, "join_table_init");
+    const int64_t words = (int64_t)(1ull << jl) + 1;
+    const int64_t most = dcap > words ? dcap : words;
+    hipLaunchKernelGGL(k_index_clear, dim3(grid_for(ctx, most, kIdxBlock * 8, 4)), dim3(kIdxBlock), 0, ctx->stream, x, words);
+  }
+  REL_LAUNCH_CHECK(ctx, "join index clear");
+  if (m > 0) {
+    const unsigned grid = grid_for(ctx, m, kIdxBlock * 4, 8);
+    {
+      KernelTimer kt(ctx, "join_build");
+      if (payload_kind == PAY_I32)
+        hipLaunchKernelGGL(k_index_build<PAY_I32>, dim3(grid), dim3(kIdxBlock), 0, ctx->stream, pk, m, x, ctx->d_status);
+      else if (payload_kind == PAY_I8)
+        hipLaunchKernelGGL(k_index_build<PAY_I8>, dim3(grid), dim3(kIdxBlock), 0, ctx->stream, pk, m, x, ctx->d_status);
+      else
+        hipLaunchKernelGGL(k_index_build<PAY_ROW_ID>, dim3(grid), dim3(kIdxBlock), 0, ctx->stream, pk, m, x, ctx->d_status);
+    }
+    {
+      KernelTimer kt(ctx, "join_index_verify");
+      hipLaunchKernelGGL(k_index_verify, dim3(grid), dim3(kIdxBlock), 0, ctx->stream, pk, m, x, ctx->d_status);
+    }
+    REL_LAUNCH_CHECK(ctx, "join index build");
+  }
+  *out = x;
   return REL_OK;
 }
 

@@ -1,6 +1,7 @@
 // Internal entry points shared between librel's translation units.
 #pragma once
 
+#include "rel_device.h"
 #include "rel_host.h"
 
 namespace relh {
@@ -17,6 +18,12 @@ rel_status join_build_into(rel_ctx* ctx, const int32_t* pk, const void* payload,
                            uint64_t* slots, uint32_t log2cap);
 // log2 of the join-table capacity for m keys under opts (plain: 2m rounded up).
 uint32_t join_log2cap(int64_t m, const rel_table_opts* opts);
+// The join index over pk[0..m) (dense array when the keys' range is at most
+// 2m wide, else the plain-sized hash table; decided on the device), in the
+// context's scratch. mm: two device words, zero on entry, that receive the
+// keys' order-encoded minimum and maximum.
+rel_status join_index_build(rel_ctx* ctx, const int32_t* pk, const void* payload, int payload_kind, int64_t m,
+                            uint32_t* mm, rel::JoinIndex* out);
 
 // GROUP BY fk of fact JOIN dim ON fk = pk WHERE day < day_lt through radix
 // partitioning of both sides and LDS-resident per-partition tables. Adds the

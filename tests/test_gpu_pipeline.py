@@ -61,7 +61,13 @@ def test_small_workload(ctx):
 
 
 def test_medium_workload(ctx):
-    st = run_both(ctx, datagen.medium(), repeats=3)
+    # by default the plain path (a dense join index over the 1.5M dim keys);
+    # forced, the radix-partitioned path
+    T = datagen.medium()
+    st = run_both(ctx, T, repeats=3)
+    assert st["groups"] == 15 and st["join_placement"] == "global"
+    plan = rel.Plan(group_capacity=0, group_placement=0, join_placement=rel.PLACE["partitioned"], allow_fallback=0)
+    st = run_both(ctx, T, plan=plan)
     assert st["groups"] == 15 and st["join_placement"] == "partitioned"
 
 
@@ -100,6 +106,56 @@ def test_degenerate(ctx, case):
     run_both(ctx, T)
     T.group_by = "fk"
     run_both(ctx, T)
+
+
+@pytest.mark.parametrize("keys", ["dense_offset", "dense_negative", "dense_gaps", "just_too_wide", "sparse"])
+@pytest.mark.parametrize("group_by", ["prio_flag", "dim_grp", "fk"])
+def test_join_index_dense_or_hash(ctx, keys, group_by):
+    # The plain path's join index is a dense array when the dim keys span at
+    # most 2m values and a hash table otherwise; both must give the oracle's
+    # groups, with fact keys inside, below and above the key range.
+    m, n = 3000, 40_000
+    T = datagen.make_tables(n, m, 91, day_lt=2000, group_by=group_by, grp_card=37 if group_by == "dim_grp" else None)
+    rng = np.random.default_rng(91)
+    if keys == "dense_offset":
+        base = 1_000_000
+    elif keys == "dense_negative":
+        base = -(2 ** 31)  # the range starts at the smallest key
+    else:
+        base = -2000
+    if keys in ("dense_gaps", "just_too_wide"):
+        # 2m - 1 wide: still dense, half the entries empty; 2m + 1 wide: the
+        # hash table. Both ends are keys, the rest distinct keys in between.
+        width = 2 * m - 1 if keys == "dense_gaps" else 2 * m + 1
+        inner = 1 + rng.choice(width - 2, size=m - 2, replace=False)
+        T.pk = (base + np.concatenate([[0, width - 1], inner])).astype(np.int32)
+        T.pk = T.pk[rng.permutation(m)]
+    elif keys == "sparse":
+        T.pk = rng.choice(np.arange(-(2 ** 31), 2 ** 31 - 1, 7919, dtype=np.int64), size=m, replace=False).astype(np.int32)
+    else:
+        T.pk = (base + rng.permutation(m)).astype(np.int32)
+    lo, hi = int(T.pk.min()), int(T.pk.max())
+    # fact keys: mostly dim keys, some just outside the range on both sides, some in gaps
+    T.fk = T.pk[rng.integers(0, m, size=n)]
+    T.fk[::7] = np.clip(rng.integers(lo - 5, hi + 6, size=T.fk[::7].shape[0]), -(2 ** 31), 2 ** 31 - 1).astype(np.int32)
+    run_both(ctx, T)
+
+
+@pytest.mark.parametrize("group_by", ["prio_flag", "dim_grp", "fk"])
+def test_join_index_duplicate_key(ctx, group_by):
+    # a repeated pk in a dense key range (same payload byte, so only the row
+    # number tells the two entries apart) and in a hash-table one
+    for base, spread in ((0, 1), (-100_000_000, 997)):
+        T = datagen.make_tables(3000, 500, 92, group_by=group_by, grp_card=11 if group_by == "dim_grp" else None)
+        T.pk = (base + spread * np.arange(500)).astype(np.int32)
+        T.pk[300] = T.pk[17]
+        T.prio[300] = T.prio[17]
+        if T.grp is not None:
+            T.grp[300] = T.grp[17]
+        fact, dim = to_dev(T)
+        with pytest.raises(rel.RelError) as e:
+            ctx.filter_join_agg(fact, dim, T.day_lt, T.group_by)
+        assert e.value.status == rel.DUPLICATE_KEY, (base, spread)
 
 
 def test_negative_prio_and_flag(ctx):
