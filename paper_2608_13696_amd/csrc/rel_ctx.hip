@@ -54,6 +54,7 @@ rel_status scratch(rel_ctx* ctx, int id, size_t bytes, void** out) {
       return fail(ctx, REL_OOM, "scratch allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
     }
     b.bytes = want;
+    b.clean = 0;
   }
   *out = b.ptr;
   return REL_OK;

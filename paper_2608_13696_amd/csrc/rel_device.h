@@ -301,6 +301,25 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   return v;
 }
 
+// Sum of a 64-bit value over a workgroup of NT threads, valid in thread 0.
+// Every thread must call it; s is NT / 64 words of LDS that no thread touches
+// until the workgroup's next barrier.
+// Kernels add their totals to a device counter once per workgroup, never once
+// per wave: thousands of atomics on one cache line at a kernel's end
+// serialise on this chip (about 12 ns each) and hold up its completion.
+template <int NT>
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* s) {
+  v = wave_sum_u64(v);
+  if (lane_id() == 0) s[threadIdx.x / kWave] = v;
+  __syncthreads();
+  uint64_t t = 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < NT / kWave; ++w) t += s[w];
+  }
+  return t;
+}
+
 // Decoupled look-back (Merrill and Garland 2016) by one whole wave of tile
 // `tile`, whose own count is `count`: publishes the count, sums predecessors
 // and returns the exclusive prefix (the same value on every lane). Each round

@@ -6,7 +6,9 @@
 // instruction-level parallelism), evaluates the compiled predicate, probes the
 // join table and updates the group state:
 //   * few groups: a per-workgroup LDS table (the shared-memory aggregation of
-//     Section 7), flushed to device memory once per workgroup;
+//     Section 7); a workgroup that ends with few groups stages them with plain
+//     stores and one workgroup merges the stages, else it flushes its table
+//     to device memory;
 //   * many groups: a device-memory table updated with device-scope atomics;
 //   * group key == join key (GROUP BY fk): a groupjoin, aggregating straight
 //     into per-dim-row accumulators so no second hash table exists.
@@ -31,6 +33,9 @@ constexpr int kLdsCacheProbe = 4;
 // load of 0.5 linear probing practically never walks that far), so that an
 // undersized table reports overflow instead of degrading to a linear scan.
 constexpr uint32_t kPlannedProbe = 256;
+// Groups a workgroup of the LDS variant may stage for the merge kernel (more
+// and it adds them to the device table itself).
+constexpr int kStageMax = 32;
 
 struct FusedArgs {
   const int32_t* fk;
@@ -43,7 +48,11 @@ struct FusedArgs {
   JoinIndex join;
   GroupView groups;
   RowAgg* row_agg;
-  int64_t* counters;  // [0] rows passed, [1] join matches
+  uint64_t* wg_counts;  // per workgroup: rows passed, join matches
+  // LDS variant: kStageMax group slots per workgroup (unused ones zero), and
+  // a word set when any row or group went to the device table instead
+  GroupSlot* stage;
+  uint32_t* touched;
   int32_t lds_probe;  // LDS probe budget before a row goes to device memory
 };
 
@@ -91,6 +100,41 @@ __device__ __forceinline__ void load_fused(const FusedArgs& a, int64_t r0, Fused
   }
 }
 
+// End of the LDS variant, one LDS slot per thread: a table holding at most
+// kStageMax groups is compacted into the workgroup's stage (the rest of the
+// stage zeroed); a fuller one goes to the device table with atomics. Few
+// groups shared by every workgroup would otherwise mean hundreds of
+// workgroups adding into the same few device slots at the kernel's end, and
+// atomics on one cache line serialise (about 12 ns each on this chip).
+template <int NT>
+__device__ void stage_or_flush(LdsGroups<kLdsSlots>& lds, const FusedArgs& a, uint64_t dev_rows) {
+  static_assert(NT == kLdsSlots, "one LDS slot per thread");
+  __shared__ uint32_t s_wcnt[NT / kWave];
+  __shared__ uint64_t s_red[NT / kWave];
+  const int t = threadIdx.x;
+  const bool occ = lds.count[t] != 0;
+  const uint64_t ball = wave_ballot(occ);
+  const uint32_t wave = t / kWave;
+  if (lane_id() == 0) s_wcnt[wave] = (uint32_t)__popcll(ball);
+  dev_rows = block_sum_u64<NT>(dev_rows, s_red);  // (its barrier also publishes s_wcnt)
+  uint32_t total = 0, before = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < NT / kWave; ++w) {
+    const uint32_t c = s_wcnt[w];
+    before += w < wave ? c : 0u;
+    total += c;
+  }
+  GroupSlot* st = a.stage + (int64_t)blockIdx.x * kStageMax;
+  if (total <= (uint32_t)kStageMax) {
+    if (occ) st[before + mask_rank(ball)] = GroupSlot{lds.key[t], lds.sum_price[t], lds.sum_qty[t], lds.count[t]};
+    if (t >= (int)total && t < kStageMax) st[t] = GroupSlot{kGroupEmpty, 0, 0, 0};
+  } else {
+    if (occ) group_add(a.groups, lds.key[t], lds.sum_price[t], lds.sum_qty[t], lds.count[t]);
+    if (t < kStageMax) st[t] = GroupSlot{kGroupEmpty, 0, 0, 0};
+  }
+  if (t == 0 && (dev_rows != 0 || total > (uint32_t)kStageMax)) *a.touched = 1u;
+}
+
 // Persistent: each workgroup walks tiles with a grid stride and loads its next
 // tile while it probes and aggregates the current one. With an LDS group
 // table there is one large workgroup per CU, so the table is flushed to device
@@ -102,7 +146,7 @@ __global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
     lds.init(threadIdx.x, NT);
     __syncthreads();
   }
-  uint64_t passed = 0, matched = 0;
+  uint64_t passed = 0, matched = 0, dev_rows = 0;
   const DenseRange dr = dense_range(a.join);
   constexpr int64_t tile_rows = (int64_t)NT * kIPT;
   const int64_t ntiles = (a.n + tile_rows - 1) / tile_rows;
@@ -154,22 +198,46 @@ __global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
             global = false;
           }
         }
+        if (GP == G_LDS) dev_rows += global;
         group_add_wave(a.groups, global, key, sp, sq);
       }
     }
     cur = nxt;
   }
-  if (GP == G_LDS) {
+  if constexpr (GP == G_LDS) {
     __syncthreads();
-    lds.flush(a.groups, threadIdx.x, NT);
+    stage_or_flush<NT>(lds, a, dev_rows);
   }
-  passed = wave_sum(passed);
-  matched = wave_sum(matched);
-  if (lane_id() == 0) {
-    if (passed) dev_add<unsigned long long>((unsigned long long*)&a.counters[0], passed);
-    if (matched) dev_add<unsigned long long>((unsigned long long*)&a.counters[1], matched);
+  // the two totals go out with plain stores, one pair per workgroup; the
+  // finalize kernel adds them up
+  __shared__ uint64_t s_red[2][NT / kWave];
+  passed = block_sum_u64<NT>(passed, s_red[0]);
+  matched = block_sum_u64<NT>(matched, s_red[1]);
+  if (threadIdx.x == 0) {
+    a.wg_counts[2 * blockIdx.x] = passed;
+    a.wg_counts[2 * blockIdx.x + 1] = matched;
   }
 }
+
+// One workgroup merges the stages of the LDS variant in its own LDS table.
+// When nothing went to the device table and every merged group found an LDS
+// slot, it writes the output itself (groups, their number, the two counters)
+// and sets `done`, and the finalize kernel returns at once; otherwise it adds
+// its groups to the device table and the finalize kernel scans that.
+constexpr int kMergeUnroll = 8;
+
+struct MergeArgs {
+  const GroupSlot* stage;  // n_wg * kStageMax
+  const uint32_t* touched;
+  int64_t n_wg;
+  const uint64_t* wg_counts;
+  int64_t* counters;
+  GroupView groups;
+  uint32_t* done;
+};
+
+struct OutArgs;
+__global__ __launch_bounds__(kLdsBlock) void k_group_merge(MergeArgs m, OutArgs o);
 
 // Standalone group-by over key[row], row = sel ? sel[k] : k.
 template <int GP>
@@ -219,7 +287,88 @@ struct OutArgs {
   int64_t cap;
   int64_t* d_n;
   uint32_t* status;
+  // the streaming kernel's per-workgroup (rows passed, join matches), summed
+  // into counters[0] and [1] by the first group of tiles; n_wg = 0: none
+  const uint64_t* wg_counts;
+  int64_t n_wg;
+  int64_t* counters;
+  const uint32_t* done;  // set: the merge kernel wrote the output (may be null)
 };
+
+__global__ __launch_bounds__(kLdsBlock) void k_group_merge(MergeArgs m, OutArgs o) {
+  __shared__ LdsGroups<kLdsSlots> lds;
+  __shared__ uint32_t s_lost;  // a group went to the device table here
+  __shared__ uint32_t s_wcnt[kLdsBlock / kWave];
+  __shared__ uint64_t s_red[2][kLdsBlock / kWave];
+  const int t = threadIdx.x;
+  lds.init(t, kLdsBlock);
+  if (t == 0) s_lost = 0;
+  __syncthreads();
+  const int64_t nflat = m.n_wg * kStageMax;
+  for (int64_t f0 = 0; f0 < nflat; f0 += (int64_t)kLdsBlock * kMergeUnroll) {
+    GroupSlot e[kMergeUnroll];
+#pragma unroll
+    for (int u = 0; u < kMergeUnroll; ++u) {
+      const int64_t f = f0 + (int64_t)u * kLdsBlock + t;
+      if (f < nflat) e[u] = m.stage[f];
+      else e[u].count = 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kMergeUnroll; ++u) {
+      if (e[u].count == 0) continue;
+      const int s = lds.find(e[u].key, kLdsProbe);
+      if (s >= 0) {
+        lds.add(s, e[u].sum_price, e[u].sum_qty, e[u].count);
+      } else {
+        group_add(m.groups, e[u].key, e[u].sum_price, e[u].sum_qty, e[u].count);
+        s_lost = 1;
+      }
+    }
+  }
+  // the streaming kernel's per-workgroup counts
+  uint64_t p = 0, q = 0;
+  for (int64_t i = t; i < m.n_wg; i += kLdsBlock) {
+    p += m.wg_counts[2 * i];
+    q += m.wg_counts[2 * i + 1];
+  }
+  p = block_sum_u64<kLdsBlock>(p, s_red[0]);  // (its barrier also ends the merge)
+  q = block_sum_u64<kLdsBlock>(q, s_red[1]);
+  if (t == 0) {
+    m.counters[0] = (int64_t)p;
+    m.counters[1] = (int64_t)q;
+  }
+  const bool occ = lds.count[t] != 0;
+  if (*m.touched != 0 || s_lost != 0) {
+    if (occ) group_add(m.groups, lds.key[t], lds.sum_price[t], lds.sum_qty[t], lds.count[t]);
+    return;
+  }
+  const uint64_t ball = wave_ballot(occ);
+  const uint32_t wave = t / kWave;
+  if (lane_id() == 0) s_wcnt[wave] = (uint32_t)__popcll(ball);
+  __syncthreads();
+  uint32_t total = 0, before = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < kLdsBlock / kWave; ++w) {
+    const uint32_t c = s_wcnt[w];
+    before += w < wave ? c : 0u;
+    total += c;
+  }
+  if (occ) {
+    const int64_t pos = before + mask_rank(ball);
+    if (pos < o.cap) {
+      o.key[pos] = lds.key[t];
+      o.sum_price[pos] = (int64_t)lds.sum_price[t];
+      o.sum_qty[pos] = (int64_t)lds.sum_qty[t];
+      o.count[pos] = (int64_t)lds.count[t];
+    } else {
+      set_status(o.status, kDevOverflow);
+    }
+  }
+  if (t == 0) {
+    *o.d_n = (int64_t)total;
+    *m.done = 1u;
+  }
+}
 
 // Group finalization: stream compaction of the occupied slots into the
 // output. Each workgroup takes a group of kFinTilesPerTicket consecutive
@@ -236,9 +385,13 @@ constexpr int64_t kFinTile = (int64_t)kBlock * kFinIPT;
 // each.
 constexpr int64_t kFinTilesPerTicket = 4;
 
-struct SlotSource {  // group table; the last slot holds the key INT64_MIN
-  const GroupSlot* slots;
+// Group table; the last slot holds the key INT64_MIN. With `clean` each slot
+// read is emptied again, so that the table needs no clearing before its next
+// use (only occupied slots are written, instead of the whole table).
+struct SlotSource {
+  GroupSlot* slots;
   int64_t side;
+  bool clean;
   __device__ bool occupied(int64_t i) const { return slots[i].count != 0; }
   __device__ void get(int64_t i, int64_t* key, uint64_t* sp, uint64_t* sq, uint64_t* cnt) const {
     const GroupSlot g = slots[i];
@@ -246,6 +399,7 @@ struct SlotSource {  // group table; the last slot holds the key INT64_MIN
     *sp = g.sum_price;
     *sq = g.sum_qty;
     *cnt = g.count;
+    if (clean) slots[i] = GroupSlot{kGroupEmpty, 0, 0, 0};
   }
 };
 
@@ -269,6 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Src src, int64_t nitems, Ou
   __shared__ int64_t s_group;
   __shared__ uint64_t s_excl;
   __shared__ uint64_t s_wave[kBlock / kWave];
+  if (o.done != nullptr && *o.done != 0) return;
   if (threadIdx.x == 0) s_group = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)ticket, 1ull);
   __syncthreads();
   const int64_t group = s_group;
@@ -336,13 +491,29 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Src src, int64_t nitems, Ou
     }
     before += (total >> (16 * g)) & 0xFFFFu;
   }
+  if (group == 0 && o.n_wg > 0) {  // (as the merge kernel does when there is one)
+    __shared__ uint64_t s_red[2][kBlock / kWave];
+    uint64_t p = 0, m = 0;
+    for (int64_t i = threadIdx.x; i < o.n_wg; i += kBlock) {
+      p += o.wg_counts[2 * i];
+      m += o.wg_counts[2 * i + 1];
+    }
+    p = block_sum_u64<kBlock>(p, s_red[0]);
+    m = block_sum_u64<kBlock>(m, s_red[1]);
+    if (threadIdx.x == 0) {
+      o.counters[0] = (int64_t)p;
+      o.counters[1] = (int64_t)m;
+    }
+  }
 }
 
 template <class Src>
 rel_status finalize(rel_ctx* ctx, const Src& src, int64_t nitems, const OutArgs& o) {
-  rel_status s = relh::fill_u64(ctx, o.d_n, 1, 0);
-  if (s != REL_OK || nitems == 0) return s;
-  const int64_t ntiles = (nitems + kFinTile - 1) / kFinTile;
+  // (when the kernel runs, its last group of tiles writes the group count)
+  if (nitems == 0 && o.n_wg == 0) return relh::fill_u64(ctx, o.d_n, 1, 0);
+  rel_status s;
+  // with no items, one (empty) tile still sums the per-workgroup counts
+  const int64_t ntiles = nitems > 0 ? (nitems + kFinTile - 1) / kFinTile : 1;
   void* st;
   if ((s = relh::scratch(ctx, SCR_SCAN_STATE, (size_t)ntiles * 8, &st)) != REL_OK) return s;
   if ((s = relh::fill_u64(ctx, st, (size_t)ntiles, 0)) != REL_OK) return s;
@@ -369,7 +540,8 @@ bool out_ok(const rel_groups_out* out) {
 }
 
 OutArgs out_args(rel_ctx* ctx, const rel_groups_out* out) {
-  return OutArgs{out->key, out->sum_price, out->sum_qty, out->count, out->cap, out->d_n_groups, ctx->d_status};
+  return OutArgs{out->key, out->sum_price, out->sum_qty, out->count, out->cap, out->d_n_groups, ctx->d_status,
+                 nullptr, 0, nullptr, nullptr};
 }
 
 // Group-table capacity (power of two) for `expected` distinct keys at load `load`.
@@ -441,7 +613,7 @@ rel_status rel_groupby_agg(rel_ctx* ctx, const int64_t* key, const int64_t* pric
       hipLaunchKernelGGL(k_groupby<G_GLOBAL>, dim3(grid), dim3(kBlock), 0, ctx->stream, key, price, qty, sel, n, g);
     REL_LAUNCH_CHECK(ctx, "groupby");
   }
-  return finalize(ctx, SlotSource{(const GroupSlot*)tbl, nslots - 1}, nslots, out_args(ctx, out));
+  return finalize(ctx, SlotSource{(GroupSlot*)tbl, nslots - 1, false}, nslots, out_args(ctx, out));
 }
 
 rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, const rel_query* q,
@@ -489,7 +661,8 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
     return sync_stats(ctx, fact, dim, q, plan, out, stats, cnt, m, m, REL_PLACE_PARTITIONED, REL_PLACE_PARTITIONED);
   }
 
-  // rows passed, join matches, and the words that receive the keys' minimum and maximum
+  // rows passed, join matches, the merge kernel's two flags, and the words
+  // that receive the keys' minimum and maximum
   TRY(relh::fill_u64(ctx, cnt, CNT_AUX2 + 1, 0));
   // Join index: a dense array when the dim keys span at most 2m values, else
   // a hash table of plain sizing (2m rounded up to a power of two); both in
@@ -512,12 +685,12 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
   a.n = n;
   a.day_lt = q->day_lt;
   a.join = jx;
-  a.counters = cnt;
 
   int gp;
   int64_t group_cap = 0;
   uint32_t gl = 0;
   void* gt = nullptr;
+  size_t clean_after = 0;
   if (gb == REL_GROUP_FK) {
     gp = G_ROWAGG;  // group key == join key: per-dim-row accumulators
     group_cap = m;
@@ -542,8 +715,19 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
     gl = group_log2cap(expected, 0.5);
     if (gl > 31) return relh::fail(ctx, REL_UNSUPPORTED, "rel_filter_join_agg: group table above 2^31 slots");
     group_cap = 1ll << gl;
-    TRY(relh::scratch(ctx, SCR_GROUP_TABLE, (size_t)(group_cap + 1) * sizeof(GroupSlot), &gt));
-    TRY(init_groups(ctx, (GroupSlot*)gt, group_cap + 1));
+    const size_t gbytes = (size_t)(group_cap + 1) * sizeof(GroupSlot);
+    if (part) {
+      TRY(relh::scratch(ctx, SCR_GROUP_TABLE, gbytes, &gt));
+      TRY(init_groups(ctx, (GroupSlot*)gt, group_cap + 1));
+    } else {
+      // the plain path's table is emptied again by the kernel that reads it,
+      // so only its first use (or a larger one) clears it
+      TRY(relh::scratch(ctx, SCR_GROUP_CLEAN, gbytes, &gt));
+      ScratchBuf& sb = ctx->scratch[SCR_GROUP_CLEAN];
+      clean_after = sb.clean > gbytes ? sb.clean : gbytes;
+      if (sb.clean < gbytes) TRY(init_groups(ctx, (GroupSlot*)gt, group_cap + 1));
+      sb.clean = 0;  // until this call's finalize kernel is enqueued
+    }
     a.groups = GroupView{(GroupSlot*)gt, (uint32_t)(group_cap - 1), 32u - gl, ctx->d_status,
                          planned ? kPlannedProbe : (uint32_t)group_cap};
   }
@@ -555,21 +739,46 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
     const bool eager = gb == REL_GROUP_DIM_GRP && (gp != G_LDS || a.lds_probe != kLdsProbe);
     TRY(relh::partitioned_join_agg(ctx, fact, dim, q->day_lt, gb, gt, gl, a.groups.max_probe,
                                    gp == G_LDS ? a.lds_probe : 0, eager, cnt));
-    TRY(finalize(ctx, SlotSource{(const GroupSlot*)gt, group_cap}, group_cap + 1, out_args(ctx, out)));
+    TRY(finalize(ctx, SlotSource{(GroupSlot*)gt, group_cap, false}, group_cap + 1, out_args(ctx, out)));
     return sync_stats(ctx, fact, dim, q, plan, out, stats, cnt, m, group_cap, REL_PLACE_PARTITIONED,
                       gp == G_LDS ? REL_PLACE_LDS : REL_PLACE_GLOBAL);
   }
 
+  OutArgs oa = out_args(ctx, out);
   if (n > 0) {
     const unsigned grid = gp == G_LDS ? relh::grid_for(ctx, n, kLdsBlock * kIPT, 1) : relh::grid_for(ctx, n, kBlock * kIPT, 8);
+    void* wc;
+    TRY(relh::scratch(ctx, SCR_WG_COUNTS, (size_t)grid * 16, &wc));
+    a.wg_counts = (uint64_t*)wc;
+    oa.wg_counts = a.wg_counts;
+    oa.n_wg = grid;
+    oa.counters = cnt;
+    uint32_t* flags = (uint32_t*)(cnt + CNT_AUX1);  // [0] touched, [1] done; cleared above
+    if (gp == G_LDS) {
+      void* stage;
+      TRY(relh::scratch(ctx, SCR_STAGE, (size_t)grid * kStageMax * sizeof(GroupSlot), &stage));
+      a.stage = (GroupSlot*)stage;
+      a.touched = flags;
+    }
     if (gb == REL_GROUP_PRIO_FLAG) TRY(launch_fused<M_PRIO_FLAG>(ctx, gp, a, grid));
     else if (gb == REL_GROUP_FK) TRY(launch_fused<M_FK>(ctx, gp, a, grid));
     else TRY(launch_fused<M_DIM_GRP>(ctx, gp, a, grid));
+    if (gp == G_LDS) {
+      MergeArgs mg{a.stage, flags, (int64_t)grid, a.wg_counts, cnt, a.groups, flags + 1};
+      oa.n_wg = 0;  // the merge kernel sums the counts
+      oa.done = flags + 1;
+      relh::KernelTimer kt(ctx, "group_merge");
+      hipLaunchKernelGGL(k_group_merge, dim3(1), dim3(kLdsBlock), 0, ctx->stream, mg, oa);
+      REL_LAUNCH_CHECK(ctx, "group_merge");
+    }
   }
 
-  const OutArgs oa = out_args(ctx, out);
-  if (gp == G_ROWAGG) TRY(finalize(ctx, RowAggSource{(const RowAgg*)gt, dim->pk}, m, oa));
-  else TRY(finalize(ctx, SlotSource{(const GroupSlot*)gt, group_cap}, group_cap + 1, oa));
+  if (gp == G_ROWAGG) {
+    TRY(finalize(ctx, RowAggSource{(const RowAgg*)gt, dim->pk}, m, oa));
+  } else {
+    TRY(finalize(ctx, SlotSource{(GroupSlot*)gt, group_cap, true}, group_cap + 1, oa));
+    ctx->scratch[SCR_GROUP_CLEAN].clean = clean_after;
+  }
   return sync_stats(ctx, fact, dim, q, plan, out, stats, cnt, (int64_t)1 << jl, group_cap, REL_PLACE_GLOBAL,
                     gp == G_LDS ? REL_PLACE_LDS : REL_PLACE_GLOBAL);
 }

@@ -15,6 +15,7 @@
 struct ScratchBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
+  size_t clean = 0;  // leading bytes known to hold an empty group table (SCR_GROUP_CLEAN)
 };
 
 // Scratch slots a context keeps between calls (each grows on demand, never shrinks).
@@ -31,6 +32,9 @@ enum ScratchId : int {
   SCR_SKETCH,
   SCR_MLP,
   SCR_DENSE,           // dense join index entries
+  SCR_WG_COUNTS,       // per-workgroup counts of a streaming kernel
+  SCR_GROUP_CLEAN,     // plain path's group table, left empty by its finalize
+  SCR_STAGE,           // per-workgroup staged groups for the merge kernel
   SCR_COUNT
 };
 

@@ -1268,8 +1268,9 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
 #pragma unroll
     for (int k = 0; k < kJDK; ++k) dkeys[k] = ndkeys[k];
   }
-  matched = wave_sum_u64(matched);
-  if (lane == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
+  __shared__ uint64_t s_matched[kJBlock / kWave];
+  matched = block_sum_u64<kJBlock>(matched, s_matched);
+  if (threadIdx.x == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
 }
 
 // ---- partitioned join + aggregate ------------------------------------------------------------------------------------
@@ -1511,8 +1512,9 @@ __global__ __launch_bounds__(kABlock, 4) void k_part_join_agg(AggArgs a) {
   }
   __syncthreads();
   grp.flush(a.groups, tid, kABlock);
-  matched = wave_sum_u64(matched);
-  if (lane == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
+  __shared__ uint64_t s_matched[kABlock / kWave];
+  matched = block_sum_u64<kABlock>(matched, s_matched);
+  if (threadIdx.x == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
 }
 
 constexpr int kEagerCacheSlots = 256;
@@ -1701,8 +1703,9 @@ __global__ __launch_bounds__(kABlock, 4) void k_part_join_eager(AggArgs a) {
   }
   __syncthreads();
   cache.flush(a.groups, tid, kABlock);
-  matched = wave_sum_u64(matched);
-  if (lane == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
+  __shared__ uint64_t s_matched[kABlock / kWave];
+  matched = block_sum_u64<kABlock>(matched, s_matched);
+  if (threadIdx.x == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
 }
 
 #define TRY(x)                   \
