@@ -190,6 +190,8 @@ struct JoinIndex {
   const void* payload;  // the dim payload column (int32 or int8), or null for row ids
   int32_t pkind;        // relh::PayloadKind
   int32_t packed;       // int8 payload packed into the entry
+  const int32_t* pk;    // the build keys (m of them), for the dense index's duplicate check
+  int64_t m;
 };
 
 struct DenseRange {
@@ -212,6 +214,43 @@ __device__ __forceinline__ DenseRange dense_range(const JoinIndex& x) {
 __device__ __forceinline__ uint32_t dense_entry(const JoinIndex& x, const DenseRange& r, int32_t key) {
   const int64_t off = (int64_t)key - r.kmin;
   return (off >= 0 && off < r.range) ? x.dense[off] : 0u;
+}
+
+// The dense entry dim row j stores: j + 1, with the int8 payload in the top
+// byte when packed.
+__device__ __forceinline__ uint32_t dense_encode(const JoinIndex& x, int64_t j) {
+  const uint32_t e = (uint32_t)(j + 1);
+  return x.packed ? e | ((uint32_t)(uint8_t)((const int8_t*)x.payload)[j] << 24) : e;
+}
+
+// Duplicate check of a dense index, rows [j0, j1) by NT threads: a key stored
+// twice keeps one of its rows' entries, so the other row finds an entry that
+// is not its own. Loads are issued four rows at a time.
+template <int NT>
+__device__ __forceinline__ void dense_verify_rows(const JoinIndex& x, const DenseRange& r, int64_t j0, int64_t j1,
+                                                  uint32_t* status) {
+  constexpr int U = 4;
+  for (int64_t b = j0 + threadIdx.x; b < j1; b += (int64_t)NT * U) {
+    int32_t key[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = b + (int64_t)u * NT;
+      key[u] = j < j1 ? x.pk[j] : 0;
+    }
+    uint32_t e[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = b + (int64_t)u * NT;
+      e[u] = j < j1 ? x.dense[(int64_t)key[u] - r.kmin] : 0u;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = b + (int64_t)u * NT;
+      bad |= j < j1 && e[u] != dense_encode(x, j);
+    }
+    if (bad) set_status(status, kDevDupKey);
+  }
 }
 
 // Payload of a non-zero dense entry (PayloadKind values: 0 row id, 1 int32, 2 int8).

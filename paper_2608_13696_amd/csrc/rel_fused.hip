@@ -53,6 +53,7 @@ struct FusedArgs {
   // a word set when any row or group went to the device table instead
   GroupSlot* stage;
   uint32_t* touched;
+  uint32_t* status;
   int32_t lds_probe;  // LDS probe budget before a row goes to device memory
 };
 
@@ -153,6 +154,13 @@ __global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
   int64_t tile = blockIdx.x;
   FusedRows cur, nxt;
   if (tile < ntiles) load_fused<MODE>(a, tile * tile_rows + (int64_t)threadIdx.x * kIPT, cur);
+  if (dr.dense) {
+    // this workgroup's share of the dense index's duplicate check, while its
+    // first tile loads
+    const int64_t per = (a.join.m + gridDim.x - 1) / gridDim.x;
+    const int64_t j0 = (int64_t)blockIdx.x * per;
+    dense_verify_rows<NT>(a.join, dr, j0, min(a.join.m, j0 + per), a.status);
+  }
   for (; tile < ntiles; tile += gridDim.x) {
     const int64_t tn = tile + gridDim.x;
     if (tn < ntiles) load_fused<MODE>(a, tn * tile_rows + (int64_t)threadIdx.x * kIPT, nxt);
@@ -685,6 +693,7 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
   a.n = n;
   a.day_lt = q->day_lt;
   a.join = jx;
+  a.status = ctx->d_status;
 
   int gp;
   int64_t group_cap = 0;
@@ -773,6 +782,7 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
     }
   }
 
+  if (n == 0) TRY(relh::join_index_verify(ctx, jx));  // (no probing kernel ran)
   if (gp == G_ROWAGG) {
     TRY(finalize(ctx, RowAggSource{(const RowAgg*)gt, dim->pk}, m, oa));
   } else {

@@ -33,17 +33,32 @@ __global__ __launch_bounds__(256) void k_join_build(const int32_t* __restrict__ 
 // ---- join index (dense array or hash table) ----------------------------------------------------------------------------
 
 // Minimum and maximum of the build keys, order-encoded so that both are
-// maxima over unsigned words that start at 0 (see JoinIndex::mm): one atomic
-// pair per workgroup.
+// maxima over unsigned words that start at 0 (see JoinIndex::mm). Few, large
+// workgroups with two 16-byte loads in flight per thread: one atomic pair per
+// workgroup, and atomics on one cache line serialise.
 constexpr int kIdxBlock = 256;
-__global__ __launch_bounds__(kIdxBlock) void k_key_minmax(const int32_t* __restrict__ pk, int64_t m, uint32_t* mm) {
-  __shared__ uint32_t s_lo[kIdxBlock / kWave], s_hi[kIdxBlock / kWave];
+constexpr int kMinMaxBlock = 512;
+constexpr int kMinMaxGrid = 64;
+__device__ __forceinline__ void minmax_add(int32_t k, uint32_t& lo, uint32_t& hi) {
+  const uint32_t o = (uint32_t)k ^ 0x80000000u;
+  lo = max(lo, ~o);
+  hi = max(hi, o);
+}
+
+__global__ __launch_bounds__(kMinMaxBlock) void k_key_minmax(const int32_t* __restrict__ pk, int64_t m, uint32_t* mm) {
+  __shared__ uint32_t s_lo[kMinMaxBlock / kWave], s_hi[kMinMaxBlock / kWave];
   uint32_t lo = 0, hi = 0;  // max of ~(key ^ 2^31), max of (key ^ 2^31)
-  for (int64_t j = blockIdx.x * (int64_t)kIdxBlock + threadIdx.x; j < m; j += (int64_t)gridDim.x * kIdxBlock) {
-    const uint32_t o = (uint32_t)pk[j] ^ 0x80000000u;
-    lo = max(lo, ~o);
-    hi = max(hi, o);
+  const int64_t nq = m / 4;  // whole 16-byte quads (pk is 16-byte aligned)
+  const int4* q = reinterpret_cast<const int4*>(pk);
+  const int64_t stride = (int64_t)gridDim.x * kMinMaxBlock * 2;
+  for (int64_t i = blockIdx.x * (int64_t)kMinMaxBlock * 2 + threadIdx.x; i < nq; i += stride) {
+    const int64_t i2 = i + kMinMaxBlock;
+    const int4 a = q[i];
+    const int4 b = i2 < nq ? q[i2] : a;
+    minmax_add(a.x, lo, hi); minmax_add(a.y, lo, hi); minmax_add(a.z, lo, hi); minmax_add(a.w, lo, hi);
+    minmax_add(b.x, lo, hi); minmax_add(b.y, lo, hi); minmax_add(b.z, lo, hi); minmax_add(b.w, lo, hi);
   }
+  if (blockIdx.x == 0 && threadIdx.x < (m & 3)) minmax_add(pk[nq * 4 + threadIdx.x], lo, hi);
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) {
     lo = max(lo, (uint32_t)__shfl_xor((int)lo, d, kWave));
@@ -55,7 +70,7 @@ __global__ __launch_bounds__(kIdxBlock) void k_key_minmax(const int32_t* __restr
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 1; w < kIdxBlock / kWave; ++w) {
+    for (int w = 1; w < kMinMaxBlock / kWave; ++w) {
       lo = max(lo, s_lo[w]);
       hi = max(hi, s_hi[w]);
     }
@@ -65,7 +80,7 @@ __global__ __launch_bounds__(kIdxBlock) void k_key_minmax(const int32_t* __restr
 }
 
 // Clears whichever structure the keys' range selects: the dense entries in
-// [0, range) or the hash slots (capacity + the side slot).
+// use, or the whole hash table.
 __global__ __launch_bounds__(kIdxBlock) void k_index_clear(JoinIndex x, int64_t hash_words) {
   const DenseRange r = dense_range(x);
   const int64_t stride = (int64_t)gridDim.x * kIdxBlock;
@@ -78,40 +93,58 @@ __global__ __launch_bounds__(kIdxBlock) void k_index_clear(JoinIndex x, int64_t 
   }
 }
 
-__device__ __forceinline__ uint32_t dense_encode(const JoinIndex& x, int64_t j) {
-  const uint32_t e = (uint32_t)(j + 1);
-  return x.packed ? e | ((uint32_t)(uint8_t)((const int8_t*)x.payload)[j] << 24) : e;
-}
-
-// Dense: each dim row writes its entry with a plain store (a repeated key is
-// found by k_index_verify). Hash: one 64-bit CAS per attempted slot.
+// Dense: plain stores (a repeated key is found by the duplicate check, which
+// the probing kernel runs). The key range is cut into one slice per XCD and
+// the workgroups of XCD x (block index = x mod 8) store only the keys of slice
+// x: each reads every key, but its stores all land in a range that its own L2
+// holds, instead of random lines written back from all eight L2s.
+// Hash: one 64-bit CAS per attempted slot, over a grid-stride loop.
+// The grid is a multiple of 8.
 template <int PK>
 __global__ __launch_bounds__(kIdxBlock) void k_index_build(const int32_t* __restrict__ pk, int64_t m, JoinIndex x,
                                                            uint32_t* __restrict__ status) {
   const DenseRange r = dense_range(x);
+  if (r.dense) {
+    const int64_t slice = (r.range + kNumXcd - 1) / kNumXcd;
+    const int64_t lo = (int64_t)(blockIdx.x % kNumXcd) * slice, hi = lo + slice;
+    const int64_t per_xcd = gridDim.x / kNumXcd;
+    const int64_t nq = (m + 3) / 4;
+    const int4* q = reinterpret_cast<const int4*>(pk);
+    for (int64_t i = (blockIdx.x / kNumXcd) * kIdxBlock + threadIdx.x; i < nq; i += per_xcd * kIdxBlock) {
+      int32_t k4[4];
+      if (4 * i + 4 <= m) {
+        const int4 v = q[i];
+        k4[0] = v.x; k4[1] = v.y; k4[2] = v.z; k4[3] = v.w;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) k4[u] = 4 * i + u < m ? pk[4 * i + u] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t off = (int64_t)k4[u] - r.kmin;
+        if (off >= lo && off < hi && 4 * i + u < m) x.dense[off] = dense_encode(x, 4 * i + u);
+      }
+    }
+    return;
+  }
   const int64_t stride = (int64_t)gridDim.x * kIdxBlock;
   for (int64_t j = blockIdx.x * (int64_t)kIdxBlock + threadIdx.x; j < m; j += stride) {
     const int32_t key = pk[j];
-    if (r.dense) {
-      x.dense[(int64_t)key - r.kmin] = dense_encode(x, j);
-    } else {
-      const int32_t pl = PK == PAY_ROW_ID ? (int32_t)j
-                         : PK == PAY_I32  ? ((const int32_t*)x.payload)[j]
-                                          : (int32_t)((const int8_t*)x.payload)[j];
-      join_insert(const_cast<uint64_t*>(x.hash.slots), x.hash.mask, x.hash.shift, key, pl, status);
-    }
+    const int32_t pl = PK == PAY_ROW_ID ? (int32_t)j
+                       : PK == PAY_I32  ? ((const int32_t*)x.payload)[j]
+                                        : (int32_t)((const int8_t*)x.payload)[j];
+    join_insert(const_cast<uint64_t*>(x.hash.slots), x.hash.mask, x.hash.shift, key, pl, status);
   }
 }
 
-// Dense only: a key stored twice keeps one of its rows' entries, so the other
-// row finds an entry that is not its own.
-__global__ __launch_bounds__(kIdxBlock) void k_index_verify(const int32_t* __restrict__ pk, int64_t m, JoinIndex x,
-                                                            uint32_t* __restrict__ status) {
+// The dense index's duplicate check on its own, for calls whose probing
+// kernel does not run (no probe rows); a no-op for a hash table.
+__global__ __launch_bounds__(kIdxBlock) void k_index_verify(JoinIndex x, uint32_t* __restrict__ status) {
   const DenseRange r = dense_range(x);
   if (!r.dense) return;
-  const int64_t stride = (int64_t)gridDim.x * kIdxBlock;
-  for (int64_t j = blockIdx.x * (int64_t)kIdxBlock + threadIdx.x; j < m; j += stride)
-    if (x.dense[(int64_t)pk[j] - r.kmin] != dense_encode(x, j)) set_status(status, kDevDupKey);
+  const int64_t per = (x.m + gridDim.x - 1) / gridDim.x;
+  const int64_t j0 = (int64_t)blockIdx.x * per;
+  dense_verify_rows<kIdxBlock>(x, r, j0, min(x.m, j0 + per), status);
 }
 
 // Probe: a wave takes 8 x 64 consecutive probe rows per step, one row of each
@@ -229,10 +262,13 @@ rel_status join_index_build(rel_ctx* ctx, const int32_t* pk, const void* payload
   x.payload = payload;
   x.pkind = payload_kind;
   x.packed = payload_kind == PAY_I8 && m < rel::kDensePackedRows;
-  const unsigned gm = grid_for(ctx, m, kIdxBlock * 8, 1);
+  x.pk = pk;
+  x.m = m;
   {
     KernelTimer kt(ctx, "join_index_minmax");
-    if (m > 0) hipLaunchKernelGGL(k_key_minmax, dim3(gm < 128 ? gm : 128), dim3(kIdxBlock), 0, ctx->stream, pk, m, mm);
+    int64_t gm = (m + kMinMaxBlock * 8 - 1) / (kMinMaxBlock * 8);
+    if (gm > kMinMaxGrid) gm = kMinMaxGrid;
+    if (m > 0) hipLaunchKernelGGL(k_key_minmax, dim3((unsigned)gm), dim3(kMinMaxBlock), 0, ctx->stream, pk, m, mm);
   }
   {
     KernelTimer kt(ctx, "join_table_init");
@@ -242,7 +278,7 @@ rel_status join_index_build(rel_ctx* ctx, const int32_t* pk, const void* payload
   }
   REL_LAUNCH_CHECK(ctx, "join index clear");
   if (m > 0) {
-    const unsigned grid = grid_for(ctx, m, kIdxBlock * 4, 8);
+    const unsigned grid = (grid_for(ctx, m, kIdxBlock * 4, 8) + kNumXcd - 1) / kNumXcd * kNumXcd;
     {
       KernelTimer kt(ctx, "join_build");
       if (payload_kind == PAY_I32)
@@ -252,13 +288,18 @@ rel_status join_index_build(rel_ctx* ctx, const int32_t* pk, const void* payload
       else
         hipLaunchKernelGGL(k_index_build<PAY_ROW_ID>, dim3(grid), dim3(kIdxBlock), 0, ctx->stream, pk, m, x, ctx->d_status);
     }
-    {
-      KernelTimer kt(ctx, "join_index_verify");
-      hipLaunchKernelGGL(k_index_verify, dim3(grid), dim3(kIdxBlock), 0, ctx->stream, pk, m, x, ctx->d_status);
-    }
     REL_LAUNCH_CHECK(ctx, "join index build");
   }
   *out = x;
+  return REL_OK;
+}
+
+rel_status join_index_verify(rel_ctx* ctx, const rel::JoinIndex& x) {
+  if (x.m == 0) return REL_OK;
+  KernelTimer kt(ctx, "join_index_verify");
+  hipLaunchKernelGGL(k_index_verify, dim3(grid_for(ctx, x.m, kIdxBlock * 4, 8)), dim3(kIdxBlock), 0, ctx->stream, x,
+                     ctx->d_status);
+  REL_LAUNCH_CHECK(ctx, "join index verify");
   return REL_OK;
 }
 

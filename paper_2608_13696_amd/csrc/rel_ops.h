@@ -21,9 +21,12 @@ uint32_t join_log2cap(int64_t m, const rel_table_opts* opts);
 // The join index over pk[0..m) (dense array when the keys' range is at most
 // 2m wide, else the plain-sized hash table; decided on the device), in the
 // context's scratch. mm: two device words, zero on entry, that receive the
-// keys' order-encoded minimum and maximum.
+// keys' order-encoded minimum and maximum. A dense index is not yet checked
+// for repeated keys: the kernel that probes it runs dense_verify_rows over
+// the build rows, or the caller runs join_index_verify.
 rel_status join_index_build(rel_ctx* ctx, const int32_t* pk, const void* payload, int payload_kind, int64_t m,
                             uint32_t* mm, rel::JoinIndex* out);
+rel_status join_index_verify(rel_ctx* ctx, const rel::JoinIndex& x);
 
 // GROUP BY fk of fact JOIN dim ON fk = pk WHERE day < day_lt through radix
 // partitioning of both sides and LDS-resident per-partition tables. Adds the
