@@ -177,21 +177,21 @@ __device__ __forceinline__ bool join_finish(const JoinView& t, int32_t key, uint
 // entry key - kmin of a plain array identifies the key's dim row, and a probe
 // is one read at a computed address; otherwise the hash table above is used.
 // The choice is made on the device, from the keys' minimum and maximum, so no
-// host round trip is needed. An entry is 0 (no key) or the dim row j + 1; with
-// an int8 payload and fewer than 2^24 dim rows the payload byte sits in the
-// top 8 bits, so the probe needs no second read.
-constexpr int64_t kDensePackedRows = 1 << 24;  // int8 payloads are packed below this many dim rows
-
+// host round trip is needed. An entry is 0 (no key) or, with an int8 payload,
+// the 16-bit 0x100 | payload byte (half the bytes, so that more of the array
+// stays in the L2 caches while fact rows probe it); otherwise the 32-bit dim
+// row j + 1. Entries are written with plain stores, so a repeated key is
+// detected by counting: m distinct keys fill exactly m entries, a repeated key
+// fewer (dense_count_entries).
 struct JoinIndex {
   JoinView hash;
-  uint32_t* dense;     // dense_cap entries
+  void* dense;         // dense_cap entries (16-byte aligned, padded to whole 16-byte words)
   const uint32_t* mm;  // {max of ~(key ^ 2^31), max of (key ^ 2^31)}: the keys' min and max, order-encoded
   int64_t dense_cap;
   const void* payload;  // the dim payload column (int32 or int8), or null for row ids
   int32_t pkind;        // relh::PayloadKind
-  int32_t packed;       // int8 payload packed into the entry
-  const int32_t* pk;    // the build keys (m of them), for the dense index's duplicate check
-  int64_t m;
+  int32_t narrow;       // 16-bit entries (int8 payload)
+  int64_t m;            // build rows
 };
 
 struct DenseRange {
@@ -200,8 +200,8 @@ struct DenseRange {
   bool dense;
 };
 
-__device__ __forceinline__ DenseRange dense_range(const JoinIndex& x) {
-  const uint32_t w0 = x.mm[0], w1 = x.mm[1];
+// From the two order-encoded words (see JoinIndex::mm).
+__device__ __forceinline__ DenseRange dense_range_of(const JoinIndex& x, uint32_t w0, uint32_t w1) {
   DenseRange r;
   r.kmin = (int32_t)(~w0 ^ 0x80000000u);
   const int32_t kmax = (int32_t)(w1 ^ 0x80000000u);
@@ -210,56 +210,59 @@ __device__ __forceinline__ DenseRange dense_range(const JoinIndex& x) {
   return r;
 }
 
+__device__ __forceinline__ DenseRange dense_range(const JoinIndex& x) { return dense_range_of(x, x.mm[0], x.mm[1]); }
+
+// 16-byte words that hold the range's entries (the last one padded with
+// entries that the clearing kernel zeroes too).
+__device__ __forceinline__ int64_t dense_words(const JoinIndex& x, const DenseRange& r) {
+  if (r.range <= 0) return 0;
+  return (r.range * (x.narrow ? 2 : 4) + 15) / 16;
+}
+
 // The dense entry of a key: 0 when the key is outside the range or absent.
 __device__ __forceinline__ uint32_t dense_entry(const JoinIndex& x, const DenseRange& r, int32_t key) {
   const int64_t off = (int64_t)key - r.kmin;
-  return (off >= 0 && off < r.range) ? x.dense[off] : 0u;
+  if (off < 0 || off >= r.range) return 0u;
+  return x.narrow ? (uint32_t)((const uint16_t*)x.dense)[off] : ((const uint32_t*)x.dense)[off];
 }
 
-// The dense entry dim row j stores: j + 1, with the int8 payload in the top
-// byte when packed.
+// The entry dim row j stores.
 __device__ __forceinline__ uint32_t dense_encode(const JoinIndex& x, int64_t j) {
-  const uint32_t e = (uint32_t)(j + 1);
-  return x.packed ? e | ((uint32_t)(uint8_t)((const int8_t*)x.payload)[j] << 24) : e;
+  if (x.narrow) return 0x100u | (uint32_t)(uint8_t)((const int8_t*)x.payload)[j];
+  return (uint32_t)(j + 1);
 }
 
-// Duplicate check of a dense index, rows [j0, j1) by NT threads: a key stored
-// twice keeps one of its rows' entries, so the other row finds an entry that
-// is not its own. Loads are issued four rows at a time.
-template <int NT>
-__device__ __forceinline__ void dense_verify_rows(const JoinIndex& x, const DenseRange& r, int64_t j0, int64_t j1,
-                                                  uint32_t* status) {
-  constexpr int U = 4;
-  for (int64_t b = j0 + threadIdx.x; b < j1; b += (int64_t)NT * U) {
-    int32_t key[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t j = b + (int64_t)u * NT;
-      key[u] = j < j1 ? x.pk[j] : 0;
-    }
-    uint32_t e[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t j = b + (int64_t)u * NT;
-      e[u] = j < j1 ? x.dense[(int64_t)key[u] - r.kmin] : 0u;
-    }
-    bool bad = false;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t j = b + (int64_t)u * NT;
-      bad |= j < j1 && e[u] != dense_encode(x, j);
-    }
-    if (bad) set_status(status, kDevDupKey);
-  }
+__device__ __forceinline__ void dense_store(const JoinIndex& x, int64_t off, uint32_t e) {
+  if (x.narrow) ((uint16_t*)x.dense)[off] = (uint16_t)e;
+  else ((uint32_t*)x.dense)[off] = e;
 }
 
 // Payload of a non-zero dense entry (PayloadKind values: 0 row id, 1 int32, 2 int8).
 __device__ __forceinline__ int32_t dense_payload(const JoinIndex& x, uint32_t e) {
-  if (x.packed) return (int32_t)(int8_t)(e >> 24);
+  if (x.narrow) return (int32_t)(int8_t)(e & 0xFFu);
   const uint32_t j = e - 1u;
   if (x.pkind == 1) return ((const int32_t*)x.payload)[j];
   if (x.pkind == 2) return (int32_t)((const int8_t*)x.payload)[j];
   return (int32_t)j;
+}
+
+// Non-zero entries among the 16-byte words [w0, w1) of a dense index, counted
+// by NT threads (the sum over all words is compared with m).
+template <int NT>
+__device__ __forceinline__ uint64_t dense_count_entries(const JoinIndex& x, int64_t w0, int64_t w1) {
+  typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+  const v4u* w = reinterpret_cast<const v4u*>(x.dense);
+  uint64_t c = 0;
+  for (int64_t i = w0 + threadIdx.x; i < w1; i += NT) {
+    const v4u v = w[i];
+    if (x.narrow) {
+      c += ((v.x & 0xFFFFu) != 0) + ((v.x >> 16) != 0) + ((v.y & 0xFFFFu) != 0) + ((v.y >> 16) != 0) +
+           ((v.z & 0xFFFFu) != 0) + ((v.z >> 16) != 0) + ((v.w & 0xFFFFu) != 0) + ((v.w >> 16) != 0);
+    } else {
+      c += (v.x != 0) + (v.y != 0) + (v.z != 0) + (v.w != 0);
+    }
+  }
+  return c;
 }
 
 // Insert (key, payload) into a join table with one 64-bit CAS per attempted

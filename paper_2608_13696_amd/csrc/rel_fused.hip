@@ -48,12 +48,11 @@ struct FusedArgs {
   JoinIndex join;
   GroupView groups;
   RowAgg* row_agg;
-  uint64_t* wg_counts;  // per workgroup: rows passed, join matches
+  uint64_t* wg_counts;  // per workgroup: rows passed, join matches, dense index entries
   // LDS variant: kStageMax group slots per workgroup (unused ones zero), and
   // a word set when any row or group went to the device table instead
   GroupSlot* stage;
   uint32_t* touched;
-  uint32_t* status;
   int32_t lds_probe;  // LDS probe budget before a row goes to device memory
 };
 
@@ -154,12 +153,14 @@ __global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
   int64_t tile = blockIdx.x;
   FusedRows cur, nxt;
   if (tile < ntiles) load_fused<MODE>(a, tile * tile_rows + (int64_t)threadIdx.x * kIPT, cur);
+  // this workgroup's share of the dense index's duplicate check (a count of
+  // its entries), while its first tile loads
+  uint64_t entries = 0;
   if (dr.dense) {
-    // this workgroup's share of the dense index's duplicate check, while its
-    // first tile loads
-    const int64_t per = (a.join.m + gridDim.x - 1) / gridDim.x;
-    const int64_t j0 = (int64_t)blockIdx.x * per;
-    dense_verify_rows<NT>(a.join, dr, j0, min(a.join.m, j0 + per), a.status);
+    const int64_t words = dense_words(a.join, dr);
+    const int64_t per = (words + gridDim.x - 1) / gridDim.x;
+    const int64_t w0 = (int64_t)blockIdx.x * per;
+    entries = dense_count_entries<NT>(a.join, w0, min(words, w0 + per));
   }
   for (; tile < ntiles; tile += gridDim.x) {
     const int64_t tn = tile + gridDim.x;
@@ -216,14 +217,16 @@ __global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
     __syncthreads();
     stage_or_flush<NT>(lds, a, dev_rows);
   }
-  // the two totals go out with plain stores, one pair per workgroup; the
-  // finalize kernel adds them up
-  __shared__ uint64_t s_red[2][NT / kWave];
+  // the totals go out with plain stores, one triple per workgroup; the merge
+  // or finalize kernel adds them up
+  __shared__ uint64_t s_red[3][NT / kWave];
   passed = block_sum_u64<NT>(passed, s_red[0]);
   matched = block_sum_u64<NT>(matched, s_red[1]);
+  entries = block_sum_u64<NT>(entries, s_red[2]);
   if (threadIdx.x == 0) {
-    a.wg_counts[2 * blockIdx.x] = passed;
-    a.wg_counts[2 * blockIdx.x + 1] = matched;
+    a.wg_counts[3 * blockIdx.x] = passed;
+    a.wg_counts[3 * blockIdx.x + 1] = matched;
+    a.wg_counts[3 * blockIdx.x + 2] = entries;
   }
 }
 
@@ -242,7 +245,31 @@ struct MergeArgs {
   int64_t* counters;
   GroupView groups;
   uint32_t* done;
+  JoinIndex join;  // for the dense index's entry count
 };
+
+// The per-workgroup counts summed by NT threads (valid in thread 0): rows
+// passed and join matches into counters[0] and [1]; a dense index with fewer
+// entries than build rows had a repeated key.
+template <int NT>
+__device__ void sum_wg_counts(const uint64_t* wg, int64_t n_wg, const JoinIndex& jx, int64_t* counters,
+                              uint32_t* status) {
+  __shared__ uint64_t s_red[3][NT / kWave];
+  uint64_t p = 0, q = 0, e = 0;
+  for (int64_t i = threadIdx.x; i < n_wg; i += NT) {
+    p += wg[3 * i];
+    q += wg[3 * i + 1];
+    e += wg[3 * i + 2];
+  }
+  p = block_sum_u64<NT>(p, s_red[0]);
+  q = block_sum_u64<NT>(q, s_red[1]);
+  e = block_sum_u64<NT>(e, s_red[2]);
+  if (threadIdx.x == 0) {
+    counters[0] = (int64_t)p;
+    counters[1] = (int64_t)q;
+    if (jx.mm != nullptr && dense_range(jx).dense && e != (uint64_t)jx.m) set_status(status, kDevDupKey);
+  }
+}
 
 struct OutArgs;
 __global__ __launch_bounds__(kLdsBlock) void k_group_merge(MergeArgs m, OutArgs o);
@@ -301,13 +328,13 @@ struct OutArgs {
   int64_t n_wg;
   int64_t* counters;
   const uint32_t* done;  // set: the merge kernel wrote the output (may be null)
+  JoinIndex join;        // for the dense index's entry count (mm null: none)
 };
 
 __global__ __launch_bounds__(kLdsBlock) void k_group_merge(MergeArgs m, OutArgs o) {
   __shared__ LdsGroups<kLdsSlots> lds;
   __shared__ uint32_t s_lost;  // a group went to the device table here
   __shared__ uint32_t s_wcnt[kLdsBlock / kWave];
-  __shared__ uint64_t s_red[2][kLdsBlock / kWave];
   const int t = threadIdx.x;
   lds.init(t, kLdsBlock);
   if (t == 0) s_lost = 0;
@@ -333,18 +360,9 @@ __global__ __launch_bounds__(kLdsBlock) void k_group_merge(MergeArgs m, OutArgs 
       }
     }
   }
-  // the streaming kernel's per-workgroup counts
-  uint64_t p = 0, q = 0;
-  for (int64_t i = t; i < m.n_wg; i += kLdsBlock) {
-    p += m.wg_counts[2 * i];
-    q += m.wg_counts[2 * i + 1];
-  }
-  p = block_sum_u64<kLdsBlock>(p, s_red[0]);  // (its barrier also ends the merge)
-  q = block_sum_u64<kLdsBlock>(q, s_red[1]);
-  if (t == 0) {
-    m.counters[0] = (int64_t)p;
-    m.counters[1] = (int64_t)q;
-  }
+  // the streaming kernel's per-workgroup counts (the barriers inside also end
+  // the merge)
+  sum_wg_counts<kLdsBlock>(m.wg_counts, m.n_wg, m.join, m.counters, o.status);
   const bool occ = lds.count[t] != 0;
   if (*m.touched != 0 || s_lost != 0) {
     if (occ) group_add(m.groups, lds.key[t], lds.sum_price[t], lds.sum_qty[t], lds.count[t]);
@@ -499,34 +517,37 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Src src, int64_t nitems, Ou
     }
     before += (total >> (16 * g)) & 0xFFFFu;
   }
-  if (group == 0 && o.n_wg > 0) {  // (as the merge kernel does when there is one)
-    __shared__ uint64_t s_red[2][kBlock / kWave];
-    uint64_t p = 0, m = 0;
-    for (int64_t i = threadIdx.x; i < o.n_wg; i += kBlock) {
-      p += o.wg_counts[2 * i];
-      m += o.wg_counts[2 * i + 1];
-    }
-    p = block_sum_u64<kBlock>(p, s_red[0]);
-    m = block_sum_u64<kBlock>(m, s_red[1]);
-    if (threadIdx.x == 0) {
-      o.counters[0] = (int64_t)p;
-      o.counters[1] = (int64_t)m;
-    }
-  }
+  // (as the merge kernel does when there is one)
+  if (group == 0 && o.n_wg > 0) sum_wg_counts<kBlock>(o.wg_counts, o.n_wg, o.join, o.counters, o.status);
 }
 
+// Tiles of the finalize kernel over nitems slots (with no items, one empty
+// tile still sums the per-workgroup counts), and its look-back state.
+int64_t finalize_tiles(int64_t nitems) { return nitems > 0 ? (nitems + kFinTile - 1) / kFinTile : 1; }
+
+rel_status finalize_state(rel_ctx* ctx, int64_t nitems, uint64_t** st) {
+  void* p;
+  rel_status s = relh::scratch(ctx, SCR_SCAN_STATE, (size_t)finalize_tiles(nitems) * 8, &p);
+  *st = (uint64_t*)p;
+  return s;
+}
+
+// zeroed: the look-back state (finalize_state) and the ticket counter are
+// already zero (an earlier kernel of the call cleared them), else they are
+// cleared here.
 template <class Src>
-rel_status finalize(rel_ctx* ctx, const Src& src, int64_t nitems, const OutArgs& o) {
+rel_status finalize(rel_ctx* ctx, const Src& src, int64_t nitems, const OutArgs& o, bool zeroed = false) {
   // (when the kernel runs, its last group of tiles writes the group count)
   if (nitems == 0 && o.n_wg == 0) return relh::fill_u64(ctx, o.d_n, 1, 0);
   rel_status s;
-  // with no items, one (empty) tile still sums the per-workgroup counts
-  const int64_t ntiles = nitems > 0 ? (nitems + kFinTile - 1) / kFinTile : 1;
-  void* st;
-  if ((s = relh::scratch(ctx, SCR_SCAN_STATE, (size_t)ntiles * 8, &st)) != REL_OK) return s;
-  if ((s = relh::fill_u64(ctx, st, (size_t)ntiles, 0)) != REL_OK) return s;
+  const int64_t ntiles = finalize_tiles(nitems);
+  uint64_t* st;
+  if ((s = finalize_state(ctx, nitems, &st)) != REL_OK) return s;
   int64_t* ticket = relh::counters(ctx) + CNT_TICKET;
-  if ((s = relh::fill_u64(ctx, ticket, 1, 0)) != REL_OK) return s;
+  if (!zeroed) {
+    if ((s = relh::fill_u64(ctx, st, (size_t)ntiles, 0)) != REL_OK) return s;
+    if ((s = relh::fill_u64(ctx, ticket, 1, 0)) != REL_OK) return s;
+  }
   relh::KernelTimer kt(ctx, "finalize");
   const int64_t ngroups = (ntiles + kFinTilesPerTicket - 1) / kFinTilesPerTicket;
   hipLaunchKernelGGL(k_finalize<Src>, dim3((unsigned)ngroups), dim3(kBlock), 0, ctx->stream, src, nitems, o,
@@ -549,7 +570,7 @@ bool out_ok(const rel_groups_out* out) {
 
 OutArgs out_args(rel_ctx* ctx, const rel_groups_out* out) {
   return OutArgs{out->key, out->sum_price, out->sum_qty, out->count, out->cap, out->d_n_groups, ctx->d_status,
-                 nullptr, 0, nullptr, nullptr};
+                 nullptr, 0, nullptr, nullptr, JoinIndex{}};
 }
 
 // Group-table capacity (power of two) for `expected` distinct keys at load `load`.
@@ -669,21 +690,6 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
     return sync_stats(ctx, fact, dim, q, plan, out, stats, cnt, m, m, REL_PLACE_PARTITIONED, REL_PLACE_PARTITIONED);
   }
 
-  // rows passed, join matches, the merge kernel's two flags, and the words
-  // that receive the keys' minimum and maximum
-  TRY(relh::fill_u64(ctx, cnt, CNT_AUX2 + 1, 0));
-  // Join index: a dense array when the dim keys span at most 2m values, else
-  // a hash table of plain sizing (2m rounded up to a power of two); both in
-  // device memory, the choice made on the device.
-  JoinIndex jx{};
-  uint32_t jl = 0;
-  if (!part) {
-    jl = relh::join_log2cap(m, nullptr);
-    const void* payload = gb == REL_GROUP_PRIO_FLAG ? (const void*)dim->prio : gb == REL_GROUP_DIM_GRP ? (const void*)dim->grp : nullptr;
-    const int pkind = gb == REL_GROUP_PRIO_FLAG ? relh::PAY_I8 : gb == REL_GROUP_DIM_GRP ? relh::PAY_I32 : relh::PAY_ROW_ID;
-    TRY(relh::join_index_build(ctx, dim->pk, payload, pkind, m, (uint32_t*)(cnt + CNT_AUX2), &jx));
-  }
-
   FusedArgs a{};
   a.fk = fact->fk;
   a.price = fact->price_cents;
@@ -692,8 +698,6 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
   a.flag = fact->flag;
   a.n = n;
   a.day_lt = q->day_lt;
-  a.join = jx;
-  a.status = ctx->d_status;
 
   int gp;
   int64_t group_cap = 0;
@@ -745,6 +749,7 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
     // the same group table behind a per-workgroup LDS table (probe budget 0:
     // none); grouping by dim.grp with more groups than LDS holds aggregates per
     // dim key first
+    TRY(relh::fill_u64(ctx, cnt, CNT_AUX2 + 1, 0));
     const bool eager = gb == REL_GROUP_DIM_GRP && (gp != G_LDS || a.lds_probe != kLdsProbe);
     TRY(relh::partitioned_join_agg(ctx, fact, dim, q->day_lt, gb, gt, gl, a.groups.max_probe,
                                    gp == G_LDS ? a.lds_probe : 0, eager, cnt));
@@ -753,16 +758,33 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
                       gp == G_LDS ? REL_PLACE_LDS : REL_PLACE_GLOBAL);
   }
 
+  // Join index: a dense array when the dim keys span at most 2m values, else
+  // a hash table of plain sizing (2m rounded up to a power of two); both in
+  // device memory, the choice made on the device. Its clearing kernel also
+  // zeroes the counter words (rows passed, join matches, the finalize ticket,
+  // the merge kernel's two flags) and the finalize kernel's look-back state.
+  const int64_t fin_items = gp == G_ROWAGG ? m : group_cap + 1;
+  uint64_t* fin_state;
+  TRY(finalize_state(ctx, fin_items, &fin_state));
+  const relh::ZeroSpans zero{{(uint64_t*)cnt, fin_state}, {CNT_AUX2, finalize_tiles(fin_items)}};
+  const uint32_t jl = relh::join_log2cap(m, nullptr);
+  const void* payload = gb == REL_GROUP_PRIO_FLAG ? (const void*)dim->prio : gb == REL_GROUP_DIM_GRP ? (const void*)dim->grp : nullptr;
+  const int pkind = gb == REL_GROUP_PRIO_FLAG ? relh::PAY_I8 : gb == REL_GROUP_DIM_GRP ? relh::PAY_I32 : relh::PAY_ROW_ID;
+  JoinIndex jx{};
+  TRY(relh::join_index_build(ctx, dim->pk, payload, pkind, m, (uint32_t*)(cnt + CNT_AUX2), zero, &jx));
+  a.join = jx;
+
   OutArgs oa = out_args(ctx, out);
   if (n > 0) {
     const unsigned grid = gp == G_LDS ? relh::grid_for(ctx, n, kLdsBlock * kIPT, 1) : relh::grid_for(ctx, n, kBlock * kIPT, 8);
     void* wc;
-    TRY(relh::scratch(ctx, SCR_WG_COUNTS, (size_t)grid * 16, &wc));
+    TRY(relh::scratch(ctx, SCR_WG_COUNTS, (size_t)grid * 24, &wc));
     a.wg_counts = (uint64_t*)wc;
     oa.wg_counts = a.wg_counts;
     oa.n_wg = grid;
     oa.counters = cnt;
-    uint32_t* flags = (uint32_t*)(cnt + CNT_AUX1);  // [0] touched, [1] done; cleared above
+    oa.join = jx;
+    uint32_t* flags = (uint32_t*)(cnt + CNT_AUX1);  // [0] touched, [1] done
     if (gp == G_LDS) {
       void* stage;
       TRY(relh::scratch(ctx, SCR_STAGE, (size_t)grid * kStageMax * sizeof(GroupSlot), &stage));
@@ -773,20 +795,21 @@ rel_status rel_filter_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_dim
     else if (gb == REL_GROUP_FK) TRY(launch_fused<M_FK>(ctx, gp, a, grid));
     else TRY(launch_fused<M_DIM_GRP>(ctx, gp, a, grid));
     if (gp == G_LDS) {
-      MergeArgs mg{a.stage, flags, (int64_t)grid, a.wg_counts, cnt, a.groups, flags + 1};
+      MergeArgs mg{a.stage, flags, (int64_t)grid, a.wg_counts, cnt, a.groups, flags + 1, jx};
       oa.n_wg = 0;  // the merge kernel sums the counts
       oa.done = flags + 1;
       relh::KernelTimer kt(ctx, "group_merge");
       hipLaunchKernelGGL(k_group_merge, dim3(1), dim3(kLdsBlock), 0, ctx->stream, mg, oa);
       REL_LAUNCH_CHECK(ctx, "group_merge");
     }
+  } else {
+    TRY(relh::join_index_verify(ctx, jx));  // (no probing kernel runs)
   }
 
-  if (n == 0) TRY(relh::join_index_verify(ctx, jx));  // (no probing kernel ran)
   if (gp == G_ROWAGG) {
-    TRY(finalize(ctx, RowAggSource{(const RowAgg*)gt, dim->pk}, m, oa));
+    TRY(finalize(ctx, RowAggSource{(const RowAgg*)gt, dim->pk}, m, oa, true));
   } else {
-    TRY(finalize(ctx, SlotSource{(GroupSlot*)gt, group_cap, true}, group_cap + 1, oa));
+    TRY(finalize(ctx, SlotSource{(GroupSlot*)gt, group_cap, true}, group_cap + 1, oa, true));
     ctx->scratch[SCR_GROUP_CLEAN].clean = clean_after;
   }
   return sync_stats(ctx, fact, dim, q, plan, out, stats, cnt, (int64_t)1 << jl, group_cap, REL_PLACE_GLOBAL,

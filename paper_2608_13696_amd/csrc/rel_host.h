@@ -35,6 +35,7 @@ enum ScratchId : int {
   SCR_WG_COUNTS,       // per-workgroup counts of a streaming kernel
   SCR_GROUP_CLEAN,     // plain path's group table, left empty by its finalize
   SCR_STAGE,           // per-workgroup staged groups for the merge kernel
+  SCR_MINMAX,          // per-workgroup key minimum and maximum of the join index build
   SCR_COUNT
 };
 

@@ -34,8 +34,9 @@ __global__ __launch_bounds__(256) void k_join_build(const int32_t* __restrict__ 
 
 // Minimum and maximum of the build keys, order-encoded so that both are
 // maxima over unsigned words that start at 0 (see JoinIndex::mm). Few, large
-// workgroups with two 16-byte loads in flight per thread: one atomic pair per
-// workgroup, and atomics on one cache line serialise.
+// workgroups with two 16-byte loads in flight per thread; each writes its pair
+// to part[2b], part[2b + 1], and the clearing kernel that follows combines
+// them (no atomics, and no word to zero first).
 constexpr int kIdxBlock = 256;
 constexpr int kMinMaxBlock = 512;
 constexpr int kMinMaxGrid = 64;
@@ -45,7 +46,7 @@ __device__ __forceinline__ void minmax_add(int32_t k, uint32_t& lo, uint32_t& hi
   hi = max(hi, o);
 }
 
-__global__ __launch_bounds__(kMinMaxBlock) void k_key_minmax(const int32_t* __restrict__ pk, int64_t m, uint32_t* mm) {
+__global__ __launch_bounds__(kMinMaxBlock) void k_key_minmax(const int32_t* __restrict__ pk, int64_t m, uint32_t* part) {
   __shared__ uint32_t s_lo[kMinMaxBlock / kWave], s_hi[kMinMaxBlock / kWave];
   uint32_t lo = 0, hi = 0;  // max of ~(key ^ 2^31), max of (key ^ 2^31)
   const int64_t nq = m / 4;  // whole 16-byte quads (pk is 16-byte aligned)
@@ -74,56 +75,103 @@ __global__ __launch_bounds__(kMinMaxBlock) void k_key_minmax(const int32_t* __re
       lo = max(lo, s_lo[w]);
       hi = max(hi, s_hi[w]);
     }
-    __hip_atomic_fetch_max(&mm[0], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_max(&mm[1], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    part[2 * blockIdx.x] = lo;
+    part[2 * blockIdx.x + 1] = hi;
   }
 }
 
-// Clears whichever structure the keys' range selects: the dense entries in
-// use, or the whole hash table.
-__global__ __launch_bounds__(kIdxBlock) void k_index_clear(JoinIndex x, int64_t hash_words) {
-  const DenseRange r = dense_range(x);
+// Combines the min/max pairs of k_key_minmax (every workgroup for itself;
+// workgroup 0 also stores the result in x.mm for the kernels that follow),
+// then clears whichever structure the keys' range selects: the 16-byte words
+// that hold the dense entries in use, or the whole hash table; and zeroes the
+// caller's spans of 64-bit words.
+__global__ __launch_bounds__(kIdxBlock) void k_index_clear(JoinIndex x, int64_t hash_words, const uint32_t* __restrict__ part,
+                                                           int32_t nparts, relh::ZeroSpans z) {
+  typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+  __shared__ uint32_t s_mm[2];
+  if (threadIdx.x < kWave) {
+    uint32_t lo = 0, hi = 0;
+    for (int i = threadIdx.x; i < nparts; i += kWave) {
+      lo = max(lo, part[2 * i]);
+      hi = max(hi, part[2 * i + 1]);
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+      lo = max(lo, (uint32_t)__shfl_xor((int)lo, d, kWave));
+      hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, kWave));
+    }
+    if (threadIdx.x == 0) {
+      s_mm[0] = lo;
+      s_mm[1] = hi;
+      if (blockIdx.x == 0) {
+        uint32_t* mm = const_cast<uint32_t*>(x.mm);
+        mm[0] = lo;
+        mm[1] = hi;
+      }
+    }
+  }
+  __syncthreads();
+  const DenseRange r = dense_range_of(x, s_mm[0], s_mm[1]);
   const int64_t stride = (int64_t)gridDim.x * kIdxBlock;
-  int64_t i = blockIdx.x * (int64_t)kIdxBlock + threadIdx.x;
+  const int64_t tid = blockIdx.x * (int64_t)kIdxBlock + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    for (int64_t i = tid; i < z.n[k]; i += stride) z.p[k][i] = 0;
+  int64_t i = tid;
   if (r.dense) {
-    for (; i < r.range; i += stride) x.dense[i] = 0u;
+    const int64_t words = dense_words(x, r);
+    for (; i < words; i += stride) reinterpret_cast<v4u*>(x.dense)[i] = v4u{0u, 0u, 0u, 0u};
   } else {
     uint64_t* slots = const_cast<uint64_t*>(x.hash.slots);
     for (; i < hash_words; i += stride) slots[i] = kJoinEmpty;
   }
 }
 
-// Dense: plain stores (a repeated key is found by the duplicate check, which
-// the probing kernel runs). The key range is cut into one slice per XCD and
-// the workgroups of XCD x (block index = x mod 8) store only the keys of slice
-// x: each reads every key, but its stores all land in a range that its own L2
-// holds, instead of random lines written back from all eight L2s.
-// Hash: one 64-bit CAS per attempted slot, over a grid-stride loop.
-// The grid is a multiple of 8.
+// Dense: plain stores (a repeated key is found by counting the entries, which
+// the probing kernel does). A thread loads kBuildQuads 16-byte quads of keys
+// (and their payloads) before it stores any entry, so its random stores do
+// not wait on one load at a time. (Cutting the key range into one slice per
+// XCD, so that each L2 takes the stores of its own slice only, measured
+// slower on 1.5M keys: 26 us against 17, each XCD then reading every key.)
+// Hash: one 64-bit CAS per attempted slot.
+constexpr int kBuildQuads = 4;
+
 template <int PK>
 __global__ __launch_bounds__(kIdxBlock) void k_index_build(const int32_t* __restrict__ pk, int64_t m, JoinIndex x,
                                                            uint32_t* __restrict__ status) {
   const DenseRange r = dense_range(x);
   if (r.dense) {
-    const int64_t slice = (r.range + kNumXcd - 1) / kNumXcd;
-    const int64_t lo = (int64_t)(blockIdx.x % kNumXcd) * slice, hi = lo + slice;
-    const int64_t per_xcd = gridDim.x / kNumXcd;
     const int64_t nq = (m + 3) / 4;
     const int4* q = reinterpret_cast<const int4*>(pk);
-    for (int64_t i = (blockIdx.x / kNumXcd) * kIdxBlock + threadIdx.x; i < nq; i += per_xcd * kIdxBlock) {
-      int32_t k4[4];
-      if (4 * i + 4 <= m) {
-        const int4 v = q[i];
-        k4[0] = v.x; k4[1] = v.y; k4[2] = v.z; k4[3] = v.w;
-      } else {
+    const int64_t step = (int64_t)gridDim.x * kIdxBlock;
+    for (int64_t i0 = blockIdx.x * (int64_t)kIdxBlock + threadIdx.x; i0 < nq; i0 += step * kBuildQuads) {
+      int32_t key[kBuildQuads * 4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) k4[u] = 4 * i + u < m ? pk[4 * i + u] : 0;
-      }
+      for (int u = 0; u < kBuildQuads; ++u) {
+        const int64_t i = i0 + u * step;
+        if (4 * i + 4 <= m) {
+          const int4 v = q[i];
+          key[4 * u] = v.x; key[4 * u + 1] = v.y; key[4 * u + 2] = v.z; key[4 * u + 3] = v.w;
+        } else {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t off = (int64_t)k4[u] - r.kmin;
-        if (off >= lo && off < hi && 4 * i + u < m) x.dense[off] = dense_encode(x, 4 * i + u);
+          for (int c = 0; c < 4; ++c) key[4 * u + c] = 4 * i + c < m ? pk[4 * i + c] : 0;
+        }
       }
+      uint32_t e[kBuildQuads * 4];
+#pragma unroll
+      for (int u = 0; u < kBuildQuads; ++u)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int64_t j = 4 * (i0 + u * step) + c;
+          e[4 * u + c] = j < m ? dense_encode(x, j) : 0u;
+        }
+#pragma unroll
+      for (int u = 0; u < kBuildQuads; ++u)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int64_t j = 4 * (i0 + u * step) + c;
+          if (j < m) dense_store(x, (int64_t)key[4 * u + c] - r.kmin, e[4 * u + c]);
+        }
     }
     return;
   }
@@ -138,13 +186,15 @@ __global__ __launch_bounds__(kIdxBlock) void k_index_build(const int32_t* __rest
 }
 
 // The dense index's duplicate check on its own, for calls whose probing
-// kernel does not run (no probe rows); a no-op for a hash table.
-__global__ __launch_bounds__(kIdxBlock) void k_index_verify(JoinIndex x, uint32_t* __restrict__ status) {
+// kernel does not run (no probe rows): one workgroup counts the entries. A
+// no-op for a hash table.
+constexpr int kVerifyBlock = 1024;
+__global__ __launch_bounds__(kVerifyBlock) void k_index_verify(JoinIndex x, uint32_t* __restrict__ status) {
+  __shared__ uint64_t s_red[kVerifyBlock / kWave];
   const DenseRange r = dense_range(x);
   if (!r.dense) return;
-  const int64_t per = (x.m + gridDim.x - 1) / gridDim.x;
-  const int64_t j0 = (int64_t)blockIdx.x * per;
-  dense_verify_rows<kIdxBlock>(x, r, j0, min(x.m, j0 + per), status);
+  const uint64_t c = block_sum_u64<kVerifyBlock>(dense_count_entries<kVerifyBlock>(x, 0, dense_words(x, r)), s_red);
+  if (threadIdx.x == 0 && c != (uint64_t)x.m) set_status(status, kDevDupKey);
 }
 
 // Probe: a wave takes 8 x 64 consecutive probe rows per step, one row of each
@@ -247,38 +297,41 @@ rel_status join_build_into(rel_ctx* ctx, const int32_t* pk, const void* payload,
 }
 
 rel_status join_index_build(rel_ctx* ctx, const int32_t* pk, const void* payload, int payload_kind, int64_t m,
-                            uint32_t* mm, rel::JoinIndex* out) {
+                            uint32_t* mm, const ZeroSpans& zero, rel::JoinIndex* out) {
   const uint32_t jl = join_log2cap(m, nullptr);
   void *jt, *dt;
   rel_status s;
   if ((s = scratch(ctx, SCR_JOIN_TABLE, ((size_t)8 << jl) + 8, &jt)) != REL_OK) return s;
   const int64_t dcap = 2 * (m > 8 ? m : 8);
-  if ((s = scratch(ctx, SCR_DENSE, (size_t)dcap * 4, &dt)) != REL_OK) return s;
+  if ((s = scratch(ctx, SCR_DENSE, (size_t)dcap * 4 + 16, &dt)) != REL_OK) return s;
+  void* part;
+  if ((s = scratch(ctx, SCR_MINMAX, (size_t)kMinMaxGrid * 8, &part)) != REL_OK) return s;
   rel::JoinIndex x{};
   x.hash = rel::JoinView{(const uint64_t*)jt, (uint32_t)((1ull << jl) - 1), 32u - jl};
-  x.dense = (uint32_t*)dt;
+  x.dense = dt;
   x.mm = mm;
   x.dense_cap = dcap;
   x.payload = payload;
   x.pkind = payload_kind;
-  x.packed = payload_kind == PAY_I8 && m < rel::kDensePackedRows;
-  x.pk = pk;
+  x.narrow = payload_kind == PAY_I8;
   x.m = m;
+  int64_t gm = (m + kMinMaxBlock * 8 - 1) / (kMinMaxBlock * 8);
+  if (gm > kMinMaxGrid) gm = kMinMaxGrid;
   {
     KernelTimer kt(ctx, "join_index_minmax");
-    int64_t gm = (m + kMinMaxBlock * 8 - 1) / (kMinMaxBlock * 8);
-    if (gm > kMinMaxGrid) gm = kMinMaxGrid;
-    if (m > 0) hipLaunchKernelGGL(k_key_minmax, dim3((unsigned)gm), dim3(kMinMaxBlock), 0, ctx->stream, pk, m, mm);
+    if (m > 0)
+      hipLaunchKernelGGL(k_key_minmax, dim3((unsigned)gm), dim3(kMinMaxBlock), 0, ctx->stream, pk, m, (uint32_t*)part);
   }
   {
     KernelTimer kt(ctx, "join_table_init");
     const int64_t words = (int64_t)(1ull << jl) + 1;
     const int64_t most = dcap > words ? dcap : words;
-    hipLaunchKernelGGL(k_index_clear, dim3(grid_for(ctx, most, kIdxBlock * 8, 4)), dim3(kIdxBlock), 0, ctx->stream, x, words);
+    hipLaunchKernelGGL(k_index_clear, dim3(grid_for(ctx, most, kIdxBlock * 8, 4)), dim3(kIdxBlock), 0, ctx->stream, x, words,
+                       (const uint32_t*)part, (int32_t)gm, zero);
   }
   REL_LAUNCH_CHECK(ctx, "join index clear");
   if (m > 0) {
-    const unsigned grid = (grid_for(ctx, m, kIdxBlock * 4, 8) + kNumXcd - 1) / kNumXcd * kNumXcd;
+    const unsigned grid = grid_for(ctx, m, kIdxBlock * 4, 8);
     {
       KernelTimer kt(ctx, "join_build");
       if (payload_kind == PAY_I32)
@@ -297,8 +350,7 @@ rel_status join_index_build(rel_ctx* ctx, const int32_t* pk, const void* payload
 rel_status join_index_verify(rel_ctx* ctx, const rel::JoinIndex& x) {
   if (x.m == 0) return REL_OK;
   KernelTimer kt(ctx, "join_index_verify");
-  hipLaunchKernelGGL(k_index_verify, dim3(grid_for(ctx, x.m, kIdxBlock * 4, 8)), dim3(kIdxBlock), 0, ctx->stream, x,
-                     ctx->d_status);
+  hipLaunchKernelGGL(k_index_verify, dim3(1), dim3(kVerifyBlock), 0, ctx->stream, x, ctx->d_status);
   REL_LAUNCH_CHECK(ctx, "join index verify");
   return REL_OK;
 }

@@ -20,12 +20,17 @@ rel_status join_build_into(rel_ctx* ctx, const int32_t* pk, const void* payload,
 uint32_t join_log2cap(int64_t m, const rel_table_opts* opts);
 // The join index over pk[0..m) (dense array when the keys' range is at most
 // 2m wide, else the plain-sized hash table; decided on the device), in the
-// context's scratch. mm: two device words, zero on entry, that receive the
-// keys' order-encoded minimum and maximum. A dense index is not yet checked
-// for repeated keys: the kernel that probes it runs dense_verify_rows over
-// the build rows, or the caller runs join_index_verify.
+// context's scratch. mm: two device words that receive the keys'
+// order-encoded minimum and maximum. The index's clearing kernel also zeroes
+// `zero`'s spans (words later kernels of the call start from). A dense index is not yet checked
+// for repeated keys: the kernel that probes it counts its entries
+// (dense_count_entries, compared with m), or the caller runs join_index_verify.
+struct ZeroSpans {
+  uint64_t* p[2];
+  int64_t n[2];
+};
 rel_status join_index_build(rel_ctx* ctx, const int32_t* pk, const void* payload, int payload_kind, int64_t m,
-                            uint32_t* mm, rel::JoinIndex* out);
+                            uint32_t* mm, const ZeroSpans& zero, rel::JoinIndex* out);
 rel_status join_index_verify(rel_ctx* ctx, const rel::JoinIndex& x);
 
 // GROUP BY fk of fact JOIN dim ON fk = pk WHERE day < day_lt through radix
