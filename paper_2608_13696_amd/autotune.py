@@ -50,7 +50,8 @@ def bucket_of(n: int) -> int:
     return len(BUCKETS) - 1
 
 
-def successive_halving(cands: list[Candidate], measure, rounds: int = 3, keep: float = 1 / 3) -> tuple[Candidate, dict]:
+def successive_halving(cands: list[Candidate], measure, rounds: int = 3, keep: float = 1 / 3,
+                       progress=None) -> tuple[Candidate, dict]:
     """Measure every candidate, keep the fastest third, measure again (times
     accumulate as a running minimum), until one is left or rounds run out."""
     best_time: dict[Candidate, float] = {}
@@ -59,6 +60,8 @@ def successive_halving(cands: list[Candidate], measure, rounds: int = 3, keep: f
         for c in alive:
             t = float(measure(c))
             best_time[c] = min(best_time.get(c, math.inf), t)
+        if progress:
+            progress(f"round {r}: {len(alive)} candidates, best {min(best_time[c] for c in alive) * 1e3:.3f} ms")
         alive.sort(key=lambda c: (best_time[c], c.items_per_thread, c.block, c.lds_groups_max, c.rows_per_item))
         if len(alive) == 1:
             break
@@ -66,7 +69,7 @@ def successive_halving(cands: list[Candidate], measure, rounds: int = 3, keep: f
     return alive[0], {f"{c.items_per_thread}/{c.block}/{c.lds_groups_max}/{c.rows_per_item}": t for c, t in best_time.items()}
 
 
-def tune(bucket_measure, buckets=BUCKETS, rounds: int = 3) -> tuple[list[dict], dict]:
+def tune(bucket_measure, buckets=BUCKETS, rounds: int = 3, progress=None) -> tuple[list[dict], dict]:
     """bucket_measure(bucket_index) -> measure(candidate) or None (empty bucket).
     Returns the tuning table (one entry per non-empty bucket, ascending, the
     last one extended to 31 bits) and the measured times."""
@@ -75,7 +78,8 @@ def tune(bucket_measure, buckets=BUCKETS, rounds: int = 3) -> tuple[list[dict], 
         meas = bucket_measure(i)
         if meas is None:
             continue
-        best, times = successive_halving(candidates(), meas, rounds=rounds)
+        best, times = successive_halving(candidates(), meas, rounds=rounds,
+                                         progress=(lambda msg, b=b: progress(f"bucket n < 2^{b}: {msg}")) if progress else None)
         table.append(best.entry(b))
         report[str(b)] = times
     if table:
