@@ -182,8 +182,8 @@ __global__ __launch_bounds__(kBlk) void k_p1_hist(PartSide s) {
 #pragma unroll
     for (int k = 0; k < V; ++k) {
       const int64_t r = r0 + 4 * (threadIdx.x + (int64_t)k * kBlk);
-      kv[k] = *reinterpret_cast<const int4*>(s.key + r);
-      dv[k] = FACT ? *reinterpret_cast<const int4*>(s.day + r) : make_int4(0, 0, 0, 0);
+      kv[k] = ld_once(reinterpret_cast<const int4*>(s.key + r));
+      dv[k] = FACT ? ld_once(reinterpret_cast<const int4*>(s.day + r)) : make_int4(0, 0, 0, 0);
     }
     __syncthreads();
 #pragma unroll
@@ -375,11 +375,11 @@ using Rows1F = TileRows<true, true, kR1>;
 // One row of a first-level tile (q < s.n).
 template <bool FACT>
 __device__ __forceinline__ void load_p1_row(const PartSide& s, int64_t q, int k, TileRows<FACT, FACT, kR1>& r) {
-  r.key[k] = s.key[q];
+  r.key[k] = ld_once(s.key + q);
   if (FACT) {
-    r.val[k] = s.qty[q];
-    r.price[k] = s.price[q];
-    r.day[k] = s.day[q];
+    r.val[k] = ld_once(s.qty + q);
+    r.price[k] = ld_once(s.price + q);
+    r.day[k] = ld_once(s.day + q);
     if (s.flag) r.flags[k / 4] |= (uint32_t)(uint8_t)s.flag[q] << (8 * (k % 4));
   } else {
     r.val[k] = s.pkind == relh::PAY_ROW_ID ? (int32_t)q
@@ -606,9 +606,9 @@ __device__ __forceinline__ void load_p2(const PartSide& s, const Tile2& x, bool 
 #pragma unroll
     for (int k = 0; k < kR2; ++k) {
       const int64_t q = r0 + (int64_t)k * kSBlk;
-      r.key[k] = s.key1[q];
-      if (FACT) r.price[k] = s.price1[q];
-      r.val[k] = FACT ? s.qty1[q] : pay ? s.pay1[q] : 0;
+      r.key[k] = ld_once(s.key1 + q);
+      if (FACT) r.price[k] = ld_once(s.price1 + q);
+      r.val[k] = FACT ? ld_once(s.qty1 + q) : pay ? ld_once(s.pay1 + q) : 0;
       if (FACT && s.flag1) r.flags[k / 4] |= (uint32_t)(uint8_t)s.flag1[q] << (8 * (k % 4));
     }
     r.valid = (1u << kR2) - 1;
