@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_join_build(const int32_t* __restrict__ 
 // them (no atomics, and no word to zero first).
 constexpr int kIdxBlock = 256;
 constexpr int kMinMaxBlock = 512;
-constexpr int kMinMaxGrid = 64;
+constexpr int kMinMaxGrid = relh::kKeyMinMaxParts;
 __device__ __forceinline__ void minmax_add(int32_t k, uint32_t& lo, uint32_t& hi) {
   const uint32_t o = (uint32_t)k ^ 0x80000000u;
   lo = max(lo, ~o);
@@ -51,13 +51,19 @@ __global__ __launch_bounds__(kMinMaxBlock) void k_key_minmax(const int32_t* __re
   uint32_t lo = 0, hi = 0;  // max of ~(key ^ 2^31), max of (key ^ 2^31)
   const int64_t nq = m / 4;  // whole 16-byte quads (pk is 16-byte aligned)
   const int4* q = reinterpret_cast<const int4*>(pk);
-  const int64_t stride = (int64_t)gridDim.x * kMinMaxBlock * 2;
-  for (int64_t i = blockIdx.x * (int64_t)kMinMaxBlock * 2 + threadIdx.x; i < nq; i += stride) {
-    const int64_t i2 = i + kMinMaxBlock;
-    const int4 a = q[i];
-    const int4 b = i2 < nq ? q[i2] : a;
-    minmax_add(a.x, lo, hi); minmax_add(a.y, lo, hi); minmax_add(a.z, lo, hi); minmax_add(a.w, lo, hi);
-    minmax_add(b.x, lo, hi); minmax_add(b.y, lo, hi); minmax_add(b.z, lo, hi); minmax_add(b.w, lo, hi);
+  constexpr int kQ = 4;  // quads in flight per thread
+  const int64_t stride = (int64_t)gridDim.x * kMinMaxBlock * kQ;
+  for (int64_t i = blockIdx.x * (int64_t)kMinMaxBlock * kQ + threadIdx.x; i < nq; i += stride) {
+    int4 v[kQ];
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+      const int64_t j = i + (int64_t)k * kMinMaxBlock;
+      v[k] = q[j < nq ? j : i];
+    }
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+      minmax_add(v[k].x, lo, hi); minmax_add(v[k].y, lo, hi); minmax_add(v[k].z, lo, hi); minmax_add(v[k].w, lo, hi);
+    }
   }
   if (blockIdx.x == 0 && threadIdx.x < (m & 3)) minmax_add(pk[nq * 4 + threadIdx.x], lo, hi);
 #pragma unroll
@@ -315,7 +321,7 @@ rel_status join_index_build(rel_ctx* ctx, const int32_t* pk, const void* payload
   x.pkind = payload_kind;
   x.narrow = payload_kind == PAY_I8;
   x.m = m;
-  int64_t gm = (m + kMinMaxBlock * 8 - 1) / (kMinMaxBlock * 8);
+  int64_t gm = (m + kMinMaxBlock * 16 - 1) / (kMinMaxBlock * 16);
   if (gm > kMinMaxGrid) gm = kMinMaxGrid;
   {
     KernelTimer kt(ctx, "join_index_minmax");
@@ -345,6 +351,16 @@ rel_status join_index_build(rel_ctx* ctx, const int32_t* pk, const void* payload
   }
   *out = x;
   return REL_OK;
+}
+
+int32_t key_minmax_partials(rel_ctx* ctx, const int32_t* pk, int64_t m, uint32_t* part) {
+  int64_t gm = (m + kMinMaxBlock * 16 - 1) / (kMinMaxBlock * 16);
+  if (gm > kMinMaxGrid) gm = kMinMaxGrid;
+  if (m > 0) {
+    KernelTimer kt(ctx, "key_minmax");
+    hipLaunchKernelGGL(k_key_minmax, dim3((unsigned)gm), dim3(kMinMaxBlock), 0, ctx->stream, pk, m, part);
+  }
+  return (int32_t)gm;
 }
 
 rel_status join_index_verify(rel_ctx* ctx, const rel::JoinIndex& x) {

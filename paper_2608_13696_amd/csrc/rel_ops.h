@@ -32,6 +32,12 @@ struct ZeroSpans {
 rel_status join_index_build(rel_ctx* ctx, const int32_t* pk, const void* payload, int payload_kind, int64_t m,
                             uint32_t* mm, const ZeroSpans& zero, rel::JoinIndex* out);
 rel_status join_index_verify(rel_ctx* ctx, const rel::JoinIndex& x);
+// Order-encoded minimum and maximum of pk[0..m) per workgroup: pair i is
+// {max of ~(key ^ 2^31), max of (key ^ 2^31)} over workgroup i's keys, so the
+// maxima over all pairs encode the keys' minimum and maximum. part holds
+// kKeyMinMaxParts pairs; returns the number written (0 when m == 0).
+constexpr int32_t kKeyMinMaxParts = 256;
+int32_t key_minmax_partials(rel_ctx* ctx, const int32_t* pk, int64_t m, uint32_t* part);
 
 // GROUP BY fk of fact JOIN dim ON fk = pk WHERE day < day_lt through radix
 // partitioning of both sides and LDS-resident per-partition tables. Adds the

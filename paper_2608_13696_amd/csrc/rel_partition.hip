@@ -9,13 +9,17 @@
 // sees only sequential partition reads and writes.
 //
 // Passes (each side; fact rows are filtered by the predicate in pass 1):
-//   1. histogram of the top B1 hash bits per input tile; column scan;
-//      scatter into 2^B1 partitions (long runs per tile, so writes coalesce);
+//   1. histogram of the top B1 bits of each key's position in the key order
+//      per input tile; column scan; scatter into 2^B1 partitions (long runs
+//      per tile, so writes coalesce);
 //   2. per first-level partition, the same on the next B2 bits.
-// Then one work unit per (partition, chunk of at most kJChunk dim keys),
-// ordered by decreasing fact-row count, builds an LDS table, streams the
-// partition's fact rows through it, and appends its groups to the output
-// with one atomic offset reservation per unit. The same partitions and units
+// The key order is a multiplicative hash, or, for GROUP BY fk over dim keys
+// that span a narrow enough range, a bijection of that range (KeyMap), which
+// turns every unit's table into a direct-mapped one.
+// Then one work unit per (partition, or 2^merge consecutive partitions in
+// the dense order; chunk of dim keys), ordered by decreasing fact-row count,
+// builds an LDS table, streams the unit's fact rows through it, and appends
+// its groups to the output with one atomic offset reservation per unit. The same partitions and units
 // serve grouping by a dim attribute: k_part_join_agg (few groups, an LDS
 // group table per workgroup) and k_part_join_eager (many groups, partials per
 // dim key added to a device-memory table at the end of each unit).
@@ -42,9 +46,77 @@ constexpr int kJSlots = 1 << kJSlotBits;
 constexpr int kJChunk = 1400;  // dim keys per unit: LDS load factor <= 0.69
 constexpr int kCombineMin = 8; // lanes sharing a slot before a wave pre-sums them
 
-__device__ __forceinline__ uint32_t phash(int32_t key) { return (uint32_t)key * 2654435769u; }
 // LDS slot: an independent multiplicative hash, so slot bits do not repeat the partition bits.
 __device__ __forceinline__ uint32_t slot_hash(int32_t key) { return ((uint32_t)key * 0x85EBCA6Bu) >> (32 - kJSlotBits); }
+
+// The key order of the partition passes: bin bits are the top bits of
+// ((key - sub) * mul) << sh.
+//
+// Hash order (sub 0, mul = 2^32 / golden ratio, sh 0): the multiplicative hash.
+//
+// Dense order, for GROUP BY fk when the dim keys span at most 2^(P + 11)
+// values (P the partition bits; kmin the smallest dim key, L = max(P,
+// ceil(log2(range)))): key -> (key - kmin) * mul mod 2^L with mul odd is a
+// bijection of [0, 2^L), so a partition (its top P bits) holds exactly the
+// keys whose low L - P = `slot_bits` bits differ, and those bits index a
+// direct-mapped LDS table: no hashing, probing or key compares in the
+// groupjoin. mul is the golden-ratio fraction of 2^L, so consecutive keys
+// (the hot ranks of a Zipf key column) fall in far-apart partitions.
+struct KeyMap {
+  uint32_t sub, mul, sh;
+  uint32_t dense;      // 1: dense order
+  uint32_t slot_bits;  // dense: slot bits per partition (<= kJSlotBits)
+  uint32_t range;      // dense: kmax - kmin + 1 (fact keys outside it match nothing)
+  uint32_t merge;      // dense: log2 of the partitions per groupjoin unit
+};
+
+__device__ __forceinline__ uint32_t key_hash(uint32_t sub, uint32_t mul, uint32_t sh, int32_t key) {
+  return (((uint32_t)key - sub) * mul) << sh;
+}
+
+// Bin of a key at a level: `shift` drops the low bits of the key's position
+// in the key order, `mask` keeps the level's bits.
+struct BinOf {
+  uint32_t sub, mul, sh, shift, mask;
+  __device__ BinOf(const KeyMap* km, uint32_t shift_, uint32_t mask_)
+      : sub(km->sub), mul(km->mul), sh(km->sh), shift(shift_), mask(mask_) {}
+  __device__ uint32_t operator()(int32_t key) const { return (key_hash(sub, mul, sh, key) >> shift) & mask; }
+};
+
+// One wave: combines the key min/max pairs of the dim keys (nparts of them;
+// none for grouping other than by fk) and writes the key map.
+__global__ __launch_bounds__(kWave) void k_keymap(const uint32_t* __restrict__ part, int32_t nparts, uint32_t pbits,
+                                                  KeyMap* __restrict__ km) {
+  uint32_t lo = 0, hi = 0;
+  for (int i = threadIdx.x; i < nparts; i += kWave) {
+    lo = max(lo, part[2 * i]);
+    hi = max(hi, part[2 * i + 1]);
+  }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    lo = max(lo, (uint32_t)__shfl_xor((int)lo, d, kWave));
+    hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, kWave));
+  }
+  if (threadIdx.x != 0) return;
+  KeyMap k{0u, 2654435769u, 0u, 0u, 0u, 0u, 0u};
+  if (nparts > 0) {
+    const int64_t kmin = (int32_t)(~lo ^ 0x80000000u), kmax = (int32_t)(hi ^ 0x80000000u);
+    const int64_t range = kmax - kmin + 1;  // >= 1
+    uint32_t L = 0;
+    while (((int64_t)1 << L) < range) ++L;
+    if (L < pbits) L = pbits;
+    if (L - pbits <= (uint32_t)kJSlotBits) {
+      k.sub = (uint32_t)kmin;
+      k.mul = (uint32_t)(2654435769ull >> (32 - L)) | 1u;
+      k.sh = 32 - L;
+      k.dense = 1;
+      k.slot_bits = L - pbits;
+      k.range = (uint32_t)range;
+      k.merge = min((uint32_t)kJSlotBits - k.slot_bits, pbits);
+    }
+  }
+  *km = k;
+}
 
 struct PartSide {
   // first-level inputs
@@ -78,6 +150,7 @@ struct PartSide {
   uint4* tdesc2;     // [max tiles2] second-level tile: {first-level partition, row lo, row hi, 0}
   int64_t* ntiles2;  // number of second-level tiles
   int64_t* zero2;    // nullable: two int64 counters that the first-level histogram clears
+  const KeyMap* km;  // the key order of the bins
   uint32_t b1, b2;
 };
 
@@ -166,7 +239,8 @@ __device__ __forceinline__ bool row_passes(const PartSide& s, int64_t r) {
 template <bool FACT>
 __global__ __launch_bounds__(kBlk) void k_p1_hist(PartSide s) {
   __shared__ uint32_t h[kMaxBins];
-  const uint32_t nb1 = 1u << s.b1, shift = 32u - s.b1;
+  const uint32_t nb1 = 1u << s.b1;
+  const BinOf bin_of(s.km, 32u - s.b1, nb1 - 1);
   if (s.zero2 && blockIdx.x == 0 && threadIdx.x == 0) {  // for the kernels that follow
     s.zero2[0] = 0;
     s.zero2[1] = 0;
@@ -192,12 +266,12 @@ __global__ __launch_bounds__(kBlk) void k_p1_hist(PartSide s) {
       const int32_t ds[4] = {dv[k].x, dv[k].y, dv[k].z, dv[k].w};
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (!FACT || ds[e] < s.day_lt) atomicAdd(&h[phash(ks[e]) >> shift], 1u);
+        if (!FACT || ds[e] < s.day_lt) atomicAdd(&h[bin_of(ks[e])], 1u);
     }
   } else {
     __syncthreads();
     for (int64_t q = r0 + threadIdx.x; q < r1; q += kBlk)
-      if (row_passes<FACT>(s, q)) atomicAdd(&h[phash(s.key[q]) >> shift], 1u);
+      if (row_passes<FACT>(s, q)) atomicAdd(&h[bin_of(s.key[q])], 1u);
   }
   __syncthreads();
   // bin-major [nb1][ntiles], so that each bin's column scan reads contiguously
@@ -287,11 +361,6 @@ struct TileRows {
   uint32_t valid;
 };
 
-// Bin of a key at a level: `shift` drops the low hash bits, `mask` keeps the level's bits.
-struct BinOf {
-  uint32_t shift, mask;
-  __device__ uint32_t operator()(int32_t key) const { return (phash(key) >> shift) & mask; }
-};
 
 // Sorts the workgroup's rows by bin in LDS and writes each to its bin's output
 // run at gbase[bin] + rank within the bin. Three barriers per tile:
@@ -394,7 +463,7 @@ template <bool FACT>
 __global__ __launch_bounds__(kSBlk) void k_p1_scatter(PartSide s) {
   __shared__ Stage<FACT, (int)kTile1> st;
   const uint32_t nb1 = 1u << s.b1;
-  const BinOf bin_of{32u - s.b1, nb1 - 1};
+  const BinOf bin_of(s.km, 32u - s.b1, nb1 - 1);
   const int64_t ntiles = gridDim.x;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   TileRows<FACT, FACT, kR1> r;
@@ -505,7 +574,7 @@ __global__ __launch_bounds__(kBlk) void k_p2_hist(PartSide s) {
   __shared__ uint32_t h[kMaxBins];
   build_l2map<kBlk>(s, mp, scr);
   const uint32_t nb1 = 1u << s.b1, nb2 = 1u << s.b2;
-  const BinOf bin_of{32u - s.b1 - s.b2, nb2 - 1};
+  const BinOf bin_of(s.km, 32u - s.b1 - s.b2, nb2 - 1);
   TileWalk w(mp.ntiles);
   int64_t t = w.take();
   int32_t cur[kHR], nxt[kHR];
@@ -638,7 +707,7 @@ __global__ __launch_bounds__(kSBlk) void k_p2_scatter(PartSide s) {
   const uint32_t t = xcd_tile(blockIdx.x, (uint32_t)ntiles);
   const uint4 td = s.tdesc2[t];
   const uint32_t nb2 = 1u << s.b2;
-  const BinOf bin_of{32u - s.b1 - s.b2, nb2 - 1};
+  const BinOf bin_of(s.km, 32u - s.b1 - s.b2, nb2 - 1);
   const bool pay = !FACT && s.pkind != relh::PAY_NONE;
   Tile2 x;
   x.p = td.x;
@@ -733,20 +802,49 @@ struct UnitArgs {
   int64_t* n_units;
   int64_t* ticket;  // the join kernel's unit ticket: zeroed here
   int64_t* out_n;   // nullable: the output group count, zeroed here
+  const KeyMap* km;
 };
+
+// A unit covers 2^merge consecutive partitions. In the dense key order their
+// key ranges are consecutive, so together they index one direct-mapped table
+// of 2^(slot_bits + merge) <= kJSlots slots, which holds every dim key it can
+// meet: the chunk limit is the table size. Hash order: one partition, at most
+// kJChunk keys per chunk (table load <= 0.69).
+struct UnitShape {
+  uint32_t merge, chunk;
+};
+__device__ __forceinline__ UnitShape unit_shape(const KeyMap* km) {
+  return km->dense ? UnitShape{km->merge, (uint32_t)kJSlots} : UnitShape{0u, (uint32_t)kJChunk};
+}
+
+struct UnitGroup {
+  uint32_t fc, dc, fs, ds;  // fact rows, dim keys and their first positions
+};
+__device__ __forceinline__ UnitGroup unit_group(const UnitArgs& a, uint32_t q, uint32_t merge) {
+  const uint32_t p0 = q << merge, p1 = p0 + (1u << merge);
+  UnitGroup g{0u, 0u, a.fstart[p0], a.dstart[p0]};
+  for (uint32_t p = p0; p < p1; ++p) {
+    g.fc += a.fcount[p];
+    g.dc += a.dcount[p];
+  }
+  return g;
+}
 
 __global__ __launch_bounds__(kUBlk) void k_unit_count(UnitArgs a) {
   __shared__ uint32_t cls_n[kClasses];
   if (threadIdx.x < kClasses) cls_n[threadIdx.x] = 0;
   __syncthreads();
-  const uint32_t p = blockIdx.x * kUBlk + threadIdx.x;
-  const uint32_t fc = p < a.nparts ? a.fcount[p] : 0u, dc = p < a.nparts ? a.dcount[p] : 0u;
-  const uint64_t mean4 = 4 * (uint64_t)*a.rows_passed / a.nparts;
+  const UnitShape us = unit_shape(a.km);
+  const uint32_t ngroups = a.nparts >> us.merge;
+  const uint32_t q = blockIdx.x * kUBlk + threadIdx.x;
+  const UnitGroup g = q < ngroups ? unit_group(a, q, us.merge) : UnitGroup{0u, 0u, 0u, 0u};
+  const uint32_t fc = g.fc, dc = g.dc;
+  const uint64_t mean4 = 4 * (uint64_t)*a.rows_passed / ngroups;
   const uint32_t thr = mean4 > kSplitMin ? (uint32_t)(mean4 < 0xffffffffull ? mean4 : 0xffffffffull) : kSplitMin;
   const bool live = fc != 0 && dc != 0;
   uint32_t sb = kNoSplit, units = 0, cls = 0;
   if (live) {
-    const uint32_t chunks = (dc + kJChunk - 1) / kJChunk;
+    const uint32_t chunks = (dc + us.chunk - 1) / us.chunk;
     uint32_t nsub = 1;
     if (chunks == 1 && fc > thr) {
       const uint32_t id = dev_add_ret<uint32_t>(a.split_ctr, 1u);
@@ -759,7 +857,7 @@ __global__ __launch_bounds__(kUBlk) void k_unit_count(UnitArgs a) {
     cls = size_class(nsub > 1 ? kSubRows : fc);
   }
   wave_grouped_add(cls_n, cls, units, live);
-  if (p < a.nparts) a.sbase[p] = sb;
+  if (q < ngroups) a.sbase[q] = sb;
   __syncthreads();
   if (threadIdx.x < kClasses) a.wg_cls[blockIdx.x * kClasses + threadIdx.x] = cls_n[threadIdx.x];
 }
@@ -795,13 +893,14 @@ __global__ __launch_bounds__(kUBlk) void k_unit_emit(UnitArgs a) {
     }
   }
   __syncthreads();
-  const uint32_t p = blockIdx.x * kUBlk + threadIdx.x;
-  const bool in = p < a.nparts;
-  const uint32_t fc = in ? a.fcount[p] : 0u, dc = in ? a.dcount[p] : 0u;
-  const uint32_t ds = in ? a.dstart[p] : 0u, fs = in ? a.fstart[p] : 0u, sb = in ? a.sbase[p] : kNoSplit;
+  const UnitShape us = unit_shape(a.km);
+  const uint32_t q = blockIdx.x * kUBlk + threadIdx.x;
+  const bool in = q < (a.nparts >> us.merge);
+  const UnitGroup g = in ? unit_group(a, q, us.merge) : UnitGroup{0u, 0u, 0u, 0u};
+  const uint32_t fc = g.fc, dc = g.dc, ds = g.ds, fs = g.fs, sb = in ? a.sbase[q] : kNoSplit;
   const bool live = fc != 0 && dc != 0;
   const bool splitp = sb != kNoSplit;
-  const uint32_t chunks = (dc + kJChunk - 1) / kJChunk;
+  const uint32_t chunks = (dc + us.chunk - 1) / us.chunk;
   const uint32_t nsub = splitp ? (fc + kSubRows - 1) / kSubRows : 1u;
   const uint32_t cls = size_class(splitp ? kSubRows : fc);
   const uint32_t pos = wave_grouped_add(cur, cls, live ? chunks * nsub : 0u, live);
@@ -821,8 +920,8 @@ __global__ __launch_bounds__(kUBlk) void k_unit_emit(UnitArgs a) {
   }
   if (!live || splitp) return;
   for (uint32_t c = 0; c < chunks; ++c) {
-    const uint32_t dlo = ds + c * kJChunk;
-    a.desc[pos + c] = make_uint4(dlo, dlo + kJChunk < ds + dc ? dlo + kJChunk : ds + dc, fs, fs + fc);
+    const uint32_t dlo = ds + c * us.chunk;
+    a.desc[pos + c] = make_uint4(dlo, dlo + us.chunk < ds + dc ? dlo + us.chunk : ds + dc, fs, fs + fc);
     a.split[pos + c] = make_uint2(0, ds + dc);
   }
 }
@@ -837,7 +936,7 @@ struct JoinArgs {
   const int32_t* fkey;
   const int64_t* fprice;
   const int32_t* fqty;
-  SplitAcc* split_acc;    // [kMaxSplit][kJChunk], zero between calls
+  SplitAcc* split_acc;    // [kMaxSplit][kJSlots], zero between calls
   uint32_t* split_done;   // [kMaxSplit], zero between calls
   int64_t* ticket;
   int64_t* matched;
@@ -848,13 +947,14 @@ struct JoinArgs {
   int64_t* out_cnt;
   int64_t out_cap;
   int64_t* d_n;
+  const KeyMap* km;
   uint32_t zero;  // 0 at run time; see take_ticket
 };
 
 constexpr uint64_t kLdsEmpty = ~0ull;
 constexpr int kJR = 4;                                   // fact rows per thread per step (dim-attribute kernels)
 constexpr int kGR = 4;                                   // fact rows per thread per step (groupjoin)
-constexpr int kJDK = (kJChunk + kJBlock - 1) / kJBlock;  // dim keys per thread
+constexpr int kJDK = kJSlots / kJBlock;                  // dim keys per thread (a dense unit fills the table)
 constexpr int kJPer = kJSlots / kJBlock;                 // LDS slots per thread at emission
 
 // An offset of zero that the compiler cannot prove uniform (zero is a
@@ -979,19 +1079,48 @@ __device__ __forceinline__ void check_later_chunks(const uint64_t* tkey, const i
   }
 }
 
+// The same for a direct-mapped (dense order) table: a later chunk's key is
+// repeated when its slot is marked present.
+template <int NT>
+__device__ __forceinline__ void check_later_chunks_dense(const uint64_t* tkc, const int32_t* dkey, uint32_t from,
+                                                         uint32_t to, uint32_t sub, uint32_t mul, uint32_t mask,
+                                                         uint32_t* status) {
+  for (uint32_t j = from + threadIdx.x; j < to; j += NT)
+    if ((uint32_t)tkc[(((uint32_t)dkey[j] - sub) * mul) & mask] == 0u) set_status(status, kDevDupKey);
+}
+
 // A slot is one 64-bit word {key, count}: the key in the low half, the rows
 // matched so far in the high half (for a sub-unit of a split chunk, the key's
 // position in its chunk sits above bit kPosShift of that half: sub-units have
 // at most kSubRows rows); all ones = empty. 48 KB of LDS per workgroup, so
 // three 256-thread workgroups fit on a CU.
+//
+// DENSE (the partitions follow the dense key order): the table is direct-
+// mapped, slot = the key's slot bits; the word's low half is 0 when a dim key
+// of the unit owns the slot and all ones when none does (a fact row's count
+// increment, 2^32, never changes the low half), so a fact row needs no probe
+// and no compare, only a range check. Emission walks the unit's dim keys
+// rather than the slots. The host launches both instances; the one that does
+// not match the key map returns at once.
 constexpr uint32_t kPosShift = 20;
 
+template <bool DENSE>
 __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
+  if ((a.km->dense != 0) != DENSE) return;
+  uint32_t dsub = 0, dmul = 0, dmask = 0, drange = 0;
+  if (DENSE) {
+    dsub = a.km->sub;
+    dmul = a.km->mul;
+    dmask = (1u << (a.km->slot_bits + a.km->merge)) - 1;
+    drange = a.km->range;
+  }
+  auto dslot = [&](int32_t key) { return (((uint32_t)key - dsub) * dmul) & dmask; };
   __shared__ uint64_t tkc[kJSlots];
   __shared__ uint64_t tsp[kJSlots];
   __shared__ uint64_t tsq[kJSlots];
   __shared__ uint32_t scr[kJBlock / kWave];
   __shared__ uint32_t s_wk[kJPer][kJBlock / kWave];  // occupied slots per (slot round, wave)
+  static_assert(kJDK <= kJPer, "dense emission rounds share s_wk");
   __shared__ uint64_t s_excl;
   __shared__ uint4 s_desc;
   __shared__ uint2 s_split;
@@ -1045,7 +1174,17 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
     // always exists. Every key's first compare-and-swap is issued before any
     // result is examined (one LDS round trip for most keys); keys whose home
     // slot was taken walk on one slot at a time.
-    {
+    if constexpr (DENSE) {
+#pragma unroll
+      for (int k = 0; k < kJDK; ++k) {
+        if (dlo + tid + k * kJBlock >= dhi) continue;
+        const uint32_t h = dslot(dkeys[k]);
+        const uint64_t old = atomicExch((unsigned long long*)&tkc[h], 0ull);
+        if ((uint32_t)old == 0u) set_status(a.status, kDevDupKey);  // the slot's key came twice
+        tsp[h] = 0;
+        tsq[h] = 0;
+      }
+    } else {
       uint32_t h[kJDK];
       uint64_t old[kJDK];
 #pragma unroll
@@ -1082,7 +1221,10 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
       }
     }
     __syncthreads();
-    if (sp.x == 0 && sp.y > dhi) check_later_chunks<kJBlock>(tkc, a.dkey, dhi, sp.y, a.status);
+    if (sp.x == 0 && sp.y > dhi) {
+      if (DENSE) check_later_chunks_dense<kJBlock>(tkc, a.dkey, dhi, sp.y, dsub, dmul, dmask, a.status);
+      else check_later_chunks<kJBlock>(tkc, a.dkey, dhi, sp.y, a.status);
+    }
     int32_t ndkeys[kJDK];
     // probe and aggregate in LDS; long units stream further steps through nxt
     const uint32_t nrows = fhi - flo;
@@ -1103,7 +1245,16 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
       // the finds.
       bool fnd[kGR];
       int slt[kGR];
-      {
+      if constexpr (DENSE) {
+        // every row in the key range has its slot (whether a dim key owns it
+        // is read at emission)
+#pragma unroll
+        for (int k = 0; k < kGR; ++k) {
+          const uint32_t off = (uint32_t)ck.key[k] - dsub;
+          fnd[k] = i0 + k * kJBlock < fhi && off < drange;
+          slt[k] = (int)((off * dmul) & dmask);
+        }
+      } else {
         uint64_t c[kGR];
 #pragma unroll
         for (int k = 0; k < kGR; ++k) {
@@ -1132,7 +1283,7 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
       for (int k = 0; k < kGR; ++k) {
         bool found = fnd[k];
         const int slot = slt[k];
-        matched += found;
+        if (!DENSE) matched += found;
         // Hot keys: when many lanes of the wave hit one slot, pre-sum them so the
         // LDS sees one update instead of a serialised run of same-address atomics.
         // Only sub-units of split chunks check: the hottest keys are what makes
@@ -1180,19 +1331,28 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
       // thread 0 waits for it. Slots go out in round-major order (round k
       // holds slots k * kJBlock + thread), so each wave's stores of a round
       // land on consecutive output rows.
-      uint32_t occ[kJPer];
-      uint64_t bal[kJPer];
+      // (DENSE: round k holds the thread's k-th dim key)
+      constexpr int kRounds = DENSE ? kJDK : kJPer;
+      uint32_t occ[kRounds];
+      uint64_t bal[kRounds];
+      int sl[kRounds];
 #pragma unroll
-      for (int k = 0; k < kJPer; ++k) {
-        const uint64_t c = tkc[k * kJBlock + tid];
-        occ[k] = c == kLdsEmpty ? 0u : (uint32_t)(c >> 32);
+      for (int k = 0; k < kRounds; ++k) {
+        if constexpr (DENSE) {
+          sl[k] = (int)dslot(dkeys[k]);
+          occ[k] = dlo + tid + k * kJBlock < dhi ? (uint32_t)(tkc[sl[k]] >> 32) : 0u;
+        } else {
+          sl[k] = k * kJBlock + tid;
+          const uint64_t c = tkc[sl[k]];
+          occ[k] = c == kLdsEmpty ? 0u : (uint32_t)(c >> 32);
+        }
         bal[k] = wave_ballot(occ[k] != 0);
         if (lane == 0) s_wk[k][wave] = (uint32_t)__popcll(bal[k]);
       }
       __syncthreads();
-      uint32_t total = 0, base[kJPer];
+      uint32_t total = 0, base[kRounds];
 #pragma unroll
-      for (int k = 0; k < kJPer; ++k) {
+      for (int k = 0; k < kRounds; ++k) {
 #pragma unroll
         for (int w = 0; w < kJBlock / kWave; ++w) {
           if (w == (int)wave) base[k] = total;
@@ -1206,17 +1366,40 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
       __syncthreads();
       const int64_t o0 = (int64_t)s_excl;
 #pragma unroll
-      for (int k = 0; k < kJPer; ++k) {
-        const int s = k * kJBlock + tid;
+      for (int k = 0; k < kRounds; ++k) {
+        const int s = sl[k];
         if (occ[k] != 0)
-          put_group(a, o0 + base[k] + mask_rank(bal[k]), (int64_t)(int32_t)(uint32_t)tkc[s], tsp[s], tsq[s], occ[k]);
-        tkc[s] = kLdsEmpty;
+          put_group(a, o0 + base[k] + mask_rank(bal[k]), DENSE ? (int64_t)dkeys[k] : (int64_t)(int32_t)(uint32_t)tkc[s],
+                    tsp[s], tsq[s], occ[k]);
+        if constexpr (DENSE) {
+          matched += occ[k];
+          if (dlo + tid + k * kJBlock < dhi) tkc[s] = kLdsEmpty;
+        } else {
+          tkc[s] = kLdsEmpty;
+        }
       }
     } else {
       // Sub-unit of a split chunk: add the partial sums into the chunk's
       // accumulator; the last sub-unit to finish emits and clears it.
       prefetch_unit(a, pd, ndkeys, nk);
-      SplitAcc* acc = a.split_acc + (size_t)(sp.x - 1) * kJChunk;
+      SplitAcc* acc = a.split_acc + (size_t)(sp.x - 1) * kJSlots;
+      if constexpr (DENSE) {
+#pragma unroll
+        for (int k = 0; k < kJDK; ++k) {
+          const uint32_t pos = tid + k * kJBlock;
+          if (dlo + pos >= dhi) continue;
+          const uint32_t h = dslot(dkeys[k]);
+          const uint64_t w = tkc[h];
+          tkc[h] = kLdsEmpty;
+          const uint32_t c = (uint32_t)(w >> 32);
+          matched += c;
+          if (c == 0) continue;
+          SplitAcc* e = acc + pos;
+          dev_add<uint64_t>(&e->sp, tsp[h]);
+          dev_add<uint64_t>(&e->sq, tsq[h]);
+          dev_add<uint64_t>(&e->cnt, (uint64_t)c);
+        }
+      } else {
 #pragma unroll
       for (int k = 0; k < kJPer; ++k) {
         const int s = tid * kJPer + k;
@@ -1229,6 +1412,7 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
         dev_add<uint64_t>(&e->sp, tsp[s]);
         dev_add<uint64_t>(&e->sq, tsq[s]);
         dev_add<uint64_t>(&e->cnt, (uint64_t)c);
+      }
       }
       __threadfence();
       __syncthreads();
@@ -1802,8 +1986,11 @@ struct Partitioned {
   uint32_t* split_done;
 };
 
+// dense_ok: the key order may be the dense one (GROUP BY fk), decided on the
+// device from the dim keys' range; otherwise the hash order.
 rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim, int32_t day_lt, int pkind,
-                          const void* payload, bool with_flag, int64_t* counters, int64_t* out_n, Partitioned* P) {
+                          const void* payload, bool with_flag, bool dense_ok, int64_t* counters, int64_t* out_n,
+                          Partitioned* P) {
   const int64_t n = fact->n, m = dim->m;
   uint32_t b1, b2;
   split_bits(m, &b1, &b2);
@@ -1823,16 +2010,16 @@ rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim
   const size_t book = ((size_t)fnt1 * nb1 + (size_t)dnt1 * nb1 + (size_t)fnt2 * nb2 + (size_t)dnt2 * nb2 + 2 * nb1 +
                        5 * (size_t)nparts + ((size_t)nparts / kUBlk + 1) * kClasses) * 4 +
                       (size_t)max_units * (sizeof(uint4) + sizeof(uint2)) + (size_t)(fnt2 + dnt2) * sizeof(uint4) +
-                      64 * 256;
+                      sizeof(KeyMap) + 8 * (size_t)kKeyMinMaxParts + 64 * 256;
   TRY(scratch(ctx, SCR_PART_D, book, &pd));
   // split-chunk accumulators and their done counters: zero when allocated, and
   // left zero by every call (the last sub-unit of a chunk clears what it emits)
   void* pe;
-  const size_t split_bytes = (size_t)kMaxSplit * kJChunk * sizeof(SplitAcc) + (kMaxSplit + 1) * sizeof(uint32_t);
+  const size_t split_bytes = (size_t)kMaxSplit * kJSlots * sizeof(SplitAcc) + (kMaxSplit + 1) * sizeof(uint32_t);
   const bool fresh = ctx->scratch[SCR_PART_E].bytes < split_bytes;
   TRY(scratch(ctx, SCR_PART_E, split_bytes, &pe));
   if (fresh) TRY(fill_u32(ctx, pe, split_bytes / 4, 0));
-  uint32_t* split_done = (uint32_t*)((char*)pe + (size_t)kMaxSplit * kJChunk * sizeof(SplitAcc));
+  uint32_t* split_done = (uint32_t*)((char*)pe + (size_t)kMaxSplit * kJSlots * sizeof(SplitAcc));
   uint32_t* split_ctr = split_done + kMaxSplit;
 
   PartSide F{};
@@ -1887,6 +2074,18 @@ rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim
   uint32_t* sbase = cd.take<uint32_t>(nparts);
   const uint32_t unit_wgs = (nparts + kUBlk - 1) / kUBlk;
   uint32_t* wg_cls = cd.take<uint32_t>((size_t)unit_wgs * kClasses);
+  KeyMap* km = cd.take<KeyMap>(1);
+  uint32_t* mm_part = cd.take<uint32_t>(2 * (size_t)kKeyMinMaxParts);
+  F.km = km;
+  D.km = km;
+
+  // the key order of both sides' bins, from the dim keys' range (dense_ok)
+  const int32_t n_mm = dense_ok ? key_minmax_partials(ctx, dim->pk, m, mm_part) : 0;
+  {
+    KernelTimer kt(ctx, "keymap");
+    hipLaunchKernelGGL(k_keymap, dim3(1), dim3(kWave), 0, ctx->stream, mm_part, n_mm, b1 + b2, km);
+  }
+  REL_LAUNCH_CHECK(ctx, "keymap");
 
   // The two sides are independent until the join: the dim side (small,
   // latency-bound kernels) runs on the auxiliary stream beside the fact side.
@@ -1916,6 +2115,7 @@ rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim
   ua.n_units = counters + CNT_AUX0;
   ua.ticket = counters + CNT_TICKET;
   ua.out_n = out_n;
+  ua.km = km;
   {
     KernelTimer kt(ctx, "unit_count");
     hipLaunchKernelGGL(k_unit_count, dim3(unit_wgs), dim3(kUBlk), 0, ctx->stream, ua);
@@ -1945,7 +2145,7 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
                                  rel_groups_out* out, int64_t* counters) {
   Partitioned P;
   // the group key is the join key: no dim payload travels
-  TRY(partition_both(ctx, fact, dim, day_lt, PAY_NONE, nullptr, false, counters, out->d_n_groups, &P));
+  TRY(partition_both(ctx, fact, dim, day_lt, PAY_NONE, nullptr, false, true, counters, out->d_n_groups, &P));
   KernelTimer kt(ctx, "part_groupjoin");
   JoinArgs a{};
   a.unit_desc = P.unit_desc;
@@ -1967,8 +2167,11 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   a.out_cnt = out->count;
   a.out_cap = out->cap;
   a.d_n = out->d_n_groups;
+  a.km = P.F.km;
   const unsigned grid = (unsigned)ctx->num_cus * 3;  // 48 KB of LDS each: three per CU
-  hipLaunchKernelGGL(k_part_groupjoin, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
+  // the key map decides which of the two runs (the other returns at once)
+  hipLaunchKernelGGL(k_part_groupjoin<true>, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
+  hipLaunchKernelGGL(k_part_groupjoin<false>, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
   REL_LAUNCH_CHECK(ctx, "part_groupjoin");
   return REL_OK;
 }
@@ -1983,7 +2186,8 @@ rel_status partitioned_join_agg(rel_ctx* ctx, const rel_fact* fact, const rel_di
   Partitioned P;
   const bool prio_flag = group_by == REL_GROUP_PRIO_FLAG;
   TRY(partition_both(ctx, fact, dim, day_lt, prio_flag ? PAY_I8 : PAY_I32,
-                     prio_flag ? (const void*)dim->prio : (const void*)dim->grp, prio_flag, counters, nullptr, &P));
+                     prio_flag ? (const void*)dim->prio : (const void*)dim->grp, prio_flag, false, counters, nullptr,
+                     &P));
   KernelTimer kt(ctx, "part_join_agg");
   AggArgs a{};
   a.unit_desc = P.unit_desc;

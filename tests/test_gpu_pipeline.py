@@ -312,6 +312,28 @@ def test_partitioned_groupjoin(ctx, n, m, zipf):
     assert st["join_placement"] == "partitioned"
 
 
+@pytest.mark.parametrize("layout", ["from_int32_min", "to_int32_max", "stride3", "stride40"])
+def test_partitioned_key_layouts(ctx, layout):
+    # The partitions follow the dense key order when the dim keys span at most
+    # 2048 x the partition count (a bijection of the key range, direct-mapped
+    # LDS tables), else the hash order. Keys at either end of int32, a range
+    # three times the key count (dense order, half-empty slots) and forty times
+    # (hash order); about 1 in 7 fact keys lie outside the dim keys' range.
+    m = 300_000
+    perm = datagen.permutation(m, 0, 81, 1).astype(np.int64)
+    pk = {"from_int32_min": perm - 2 ** 31, "to_int32_max": perm + (2 ** 31 - m), "stride3": 3 * perm - 7,
+          "stride40": 40 * perm + 11}[layout]
+    T = datagen.make_tables(1_500_000, m, 82, day_lt=1500, group_by="fk", fk_zipf=0.9)
+    T.pk = pk.astype(np.int32)
+    fk = T.pk[T.fk.astype(np.int64)].astype(np.int64)
+    off = datagen.uniform(T.n, -3 * m, 3 * m, np.int64, 82, 5)
+    out = datagen.unit(T.n, 82, 6) < 0.15
+    fk = np.where(out, np.clip(fk + np.where(off >= 0, off + 1, off), -2 ** 31, 2 ** 31 - 1), fk)
+    T.fk = fk.astype(np.int32)
+    st = run_both(ctx, T, plan=_partitioned(), repeats=2)
+    assert st["join_placement"] == "partitioned"
+
+
 def test_partitioned_oversized_partition_is_chunked(ctx):
     # 3000 keys in one partition exceed one LDS chunk (1400 keys): the partition
     # is processed as several units that each see all of its fact rows.
