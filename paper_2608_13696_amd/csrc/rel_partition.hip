@@ -1015,16 +1015,16 @@ __device__ __forceinline__ void load_payload(const JoinArgs& a, uint32_t i0, uin
   }
 }
 
-// The next unit's dim keys and the keys of its first step of fact rows (its
-// prices and quantities follow at the start of the unit, so they do not hold
-// registers through this unit).
-__device__ __forceinline__ void prefetch_unit(const JoinArgs& a, uint4 u, int32_t (&dk)[kJDK], KeyRegs& r) {
+// The next unit's dim keys and its first step of fact rows (keys, prices and
+// quantities), loaded while the current unit emits its groups.
+__device__ __forceinline__ void prefetch_unit(const JoinArgs& a, uint4 u, int32_t (&dk)[kJDK], KeyRegs& r, PayRegs& p) {
 #pragma unroll
   for (int k = 0; k < kJDK; ++k) {
     const uint32_t j = u.x + threadIdx.x + k * kJBlock;
     dk[k] = a.dkey[j < u.y ? j : u.y - 1];
   }
   load_keys(a, u.z + threadIdx.x, u.w, r);
+  load_payload(a, u.z + threadIdx.x, u.w, p);
 }
 
 // Output room for `total` groups. The address is not provably uniform (see
@@ -1155,11 +1155,10 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
   uint2 sp = s_split;
   int32_t dkeys[kJDK];
   KeyRegs ck, nk;  // this step's keys; the next step's (or the next unit's first step's)
-  PayRegs pay;
-  if (u < n_units) prefetch_unit(a, d, dkeys, nk);
+  PayRegs pay, npay;
+  if (u < n_units) prefetch_unit(a, d, dkeys, nk, npay);
   while (u < n_units) {
     const uint32_t dlo = d.x, dhi = d.y, flo = d.z, fhi = d.w;
-    load_payload(a, flo + tid, fhi, pay);
     int64_t t_req = 0;
     uint4 nd = make_uint4(0, 0, 0, 0);
     uint2 ns = make_uint2(0, 0);
@@ -1236,8 +1235,11 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
     for (uint32_t it = 0; it < iters; ++it) {
       const uint32_t i0 = flo + it * (kGR * kJBlock) + tid;
       ck = nk;
-      if (it > 0) load_payload(a, i0, fhi, pay);
-      if (it + 1 < iters) load_keys(a, i0 + kGR * kJBlock, fhi, nk);
+      pay = npay;
+      if (it + 1 < iters) {  // the next step's rows travel during this step's updates
+        load_keys(a, i0 + kGR * kJBlock, fhi, nk);
+        load_payload(a, i0 + kGR * kJBlock, fhi, npay);
+      }
       // find every row's slot first, then update: all rows' home slots are
       // read before any is examined (one LDS round trip for most rows), so
       // the finds are not a chain of dependent reads; rows whose home slot
@@ -1361,7 +1363,7 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
       }
       int64_t resv = 0;
       if (tid == 0 && total) resv = reserve_nowait(a, total);
-      prefetch_unit(a, pd, ndkeys, nk);
+      prefetch_unit(a, pd, ndkeys, nk, npay);
       if (tid == 0) s_excl = (uint64_t)resv;
       __syncthreads();
       const int64_t o0 = (int64_t)s_excl;
@@ -1381,7 +1383,7 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
     } else {
       // Sub-unit of a split chunk: add the partial sums into the chunk's
       // accumulator; the last sub-unit to finish emits and clears it.
-      prefetch_unit(a, pd, ndkeys, nk);
+      prefetch_unit(a, pd, ndkeys, nk, npay);
       SplitAcc* acc = a.split_acc + (size_t)(sp.x - 1) * kJSlots;
       if constexpr (DENSE) {
 #pragma unroll
