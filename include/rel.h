@@ -328,6 +328,8 @@ typedef struct rel_batch_tuning {
   int32_t block;            /* workgroup size: 64, 128, 256 or 512 */
   int32_t lds_groups_max;   /* LDS group table when the instance's group bound is at most this (<= 512); 0 = never */
   int32_t rows_per_item;    /* fact rows per work item (multiple of block * items_per_thread) */
+  int32_t lds_join_max;     /* LDS join table (built per work item from the dim columns) when the instance's dim
+                               has at most this many keys (<= 1024); 0 = never: the device-memory table */
 } rel_batch_tuning;
 
 typedef struct rel_batch rel_batch;

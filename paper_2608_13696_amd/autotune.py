@@ -1,6 +1,7 @@
 """Autotuner for the batched form: per size bucket, pick rows per thread,
 workgroup size, LDS-or-device-memory group tables and rows per work item by
-measuring candidates on the bucket's own instances (successive halving).
+measuring candidates on the bucket's own instances (successive halving), then
+LDS-or-device-memory join tables for the winner (every option measured).
 
 The search logic takes a `measure(bucket, candidate) -> seconds` callable, so
 it runs unchanged against the GPU (`gpu_measure`) or against fake timings.
@@ -11,7 +12,7 @@ import itertools
 import json
 import math
 import os
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 
 # Size buckets: instances with n < 2^b go to the first bucket whose bound exceeds n.
 BUCKETS = (12, 15, 18, 31)
@@ -19,6 +20,7 @@ IPT = (1, 2, 4, 8)
 BLOCK = (128, 256, 512)
 LDS_GROUPS = (0, 128, 512)
 ROWS_PER_ITEM = (4096, 16384, 65536)
+LDS_JOIN = (0, 1024)  # dim keys up to which a work item builds its join table in LDS
 
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "batch_mi355x.json")
 
@@ -29,10 +31,15 @@ class Candidate:
     block: int
     lds_groups_max: int
     rows_per_item: int
+    lds_join_max: int = 0
 
     def entry(self, log2_rows_below: int) -> dict:
         return dict(log2_rows_below=log2_rows_below, items_per_thread=self.items_per_thread, block=self.block,
-                    lds_groups_max=self.lds_groups_max, rows_per_item=self.rows_per_item)
+                    lds_groups_max=self.lds_groups_max, rows_per_item=self.rows_per_item,
+                    lds_join_max=self.lds_join_max)
+
+    def name(self) -> str:
+        return f"{self.items_per_thread}/{self.block}/{self.lds_groups_max}/{self.rows_per_item}/{self.lds_join_max}"
 
 
 def candidates() -> list[Candidate]:
@@ -62,11 +69,12 @@ def successive_halving(cands: list[Candidate], measure, rounds: int = 3, keep: f
             best_time[c] = min(best_time.get(c, math.inf), t)
         if progress:
             progress(f"round {r}: {len(alive)} candidates, best {min(best_time[c] for c in alive) * 1e3:.3f} ms")
-        alive.sort(key=lambda c: (best_time[c], c.items_per_thread, c.block, c.lds_groups_max, c.rows_per_item))
+        alive.sort(key=lambda c: (best_time[c], c.items_per_thread, c.block, c.lds_groups_max, c.rows_per_item,
+                                  c.lds_join_max))
         if len(alive) == 1:
             break
         alive = alive[:max(1, int(math.ceil(len(alive) * keep)))]
-    return alive[0], {f"{c.items_per_thread}/{c.block}/{c.lds_groups_max}/{c.rows_per_item}": t for c, t in best_time.items()}
+    return alive[0], {c.name(): t for c, t in best_time.items()}
 
 
 def tune(bucket_measure, buckets=BUCKETS, rounds: int = 3, progress=None) -> tuple[list[dict], dict]:
@@ -78,10 +86,13 @@ def tune(bucket_measure, buckets=BUCKETS, rounds: int = 3, progress=None) -> tup
         meas = bucket_measure(i)
         if meas is None:
             continue
-        best, times = successive_halving(candidates(), meas, rounds=rounds,
-                                         progress=(lambda msg, b=b: progress(f"bucket n < 2^{b}: {msg}")) if progress else None)
+        prog = (lambda msg, b=b: progress(f"bucket n < 2^{b}: {msg}")) if progress else None
+        best, times = successive_halving(candidates(), meas, rounds=rounds, progress=prog)
+        # the join table's placement for the winner: every option, measured alike
+        best, jtimes = successive_halving([replace(best, lds_join_max=j) for j in LDS_JOIN], meas, rounds=rounds,
+                                          keep=1.0, progress=prog)
         table.append(best.entry(b))
-        report[str(b)] = times
+        report[str(b)] = {**times, **{f"join {k}": t for k, t in jtimes.items()}}
     if table:
         table[-1]["log2_rows_below"] = 31
     return table, report

@@ -9,8 +9,8 @@
 // run is one graph launch.
 //
 // Per-bucket configuration (rows per thread, workgroup size, LDS or
-// device-memory group table, rows per work item) comes from a tuning table
-// that the autotuner measures.
+// device-memory group table, LDS or device-memory join table, rows per work
+// item) comes from a tuning table that the autotuner measures.
 #include <algorithm>
 #include <numeric>
 
@@ -30,6 +30,10 @@ constexpr int kBLdsProbe = 32;
 // of one per row), and a short probe budget bounds the cost for the others.
 constexpr int kBLdsCacheProbe = 4;
 constexpr int64_t kFinItemSlots = 8192;
+// LDS join table: 2048 packed slots (and the side slot of key -1, as in the
+// device-memory table), for instances of at most 1024 dim keys (load <= 0.5).
+constexpr int kBLdsJoinBits = 11;
+constexpr int kBLdsJoinSlots = 1 << kBLdsJoinBits;
 constexpr uint32_t kHintProbe = 256;
 
 // Device view of one instance (all pointers device memory).
@@ -48,7 +52,8 @@ struct BInst {
   uint32_t jmask, jshift;
   GroupSlot* gslots;
   uint32_t gmask, gshift, gprobe;
-  int32_t lds;  // aggregate through the workgroup's LDS table first
+  int32_t lds;    // aggregate through the workgroup's LDS table first
+  int32_t ljoin;  // probe a join table built in the workgroup's LDS for each work item
   int64_t* out_key;
   int64_t* out_sp;
   int64_t* out_sq;
@@ -63,6 +68,11 @@ struct BItem {
   int32_t pad;
   int64_t lo, hi;
 };
+
+// The join payload of dim row j (the group attribute, or the row id for GROUP BY fk).
+__device__ __forceinline__ int32_t batch_payload(const BInst& I, int64_t j) {
+  return I.group_by == REL_GROUP_PRIO_FLAG ? (int32_t)I.prio[j] : I.group_by == REL_GROUP_DIM_GRP ? I.grp[j] : (int32_t)j;
+}
 
 __global__ void k_batch_zero_outputs(const BInst* __restrict__ inst, int32_t k) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) *inst[i].d_n = 0;
@@ -82,10 +92,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_build(const BInst* __restrict__
     const BItem w = items[it];
     const BInst& I = inst[w.inst];
     for (int64_t j = w.lo + threadIdx.x; j < w.hi; j += BLOCK) {
-      const int32_t pl = I.group_by == REL_GROUP_PRIO_FLAG ? (int32_t)I.prio[j]
-                         : I.group_by == REL_GROUP_DIM_GRP ? I.grp[j]
-                                                           : (int32_t)j;
-      join_insert(I.jslots, I.jmask, I.jshift, I.pk[j], pl, status);
+      join_insert(I.jslots, I.jmask, I.jshift, I.pk[j], batch_payload(I, j), status);
     }
   }
 }
@@ -96,11 +103,67 @@ __device__ __forceinline__ int64_t batch_key(const BInst& I, int32_t pl, int32_t
   return (int64_t)fk;
 }
 
-template <int BLOCK, int IPT>
+// An instance's join table in LDS, in the packed format of the device-memory
+// table (key in the low word, payload in the high word, key -1 in the side
+// slot). The workgroup builds it from the dim columns at the start of each
+// work item of a small-dim instance, so the probes of the item's rows are LDS
+// reads instead of device-memory reads. A repeated key is reported by the
+// instance's device-memory build, which every instance still runs.
+struct LdsJoin {
+  uint64_t slot[kBLdsJoinSlots + 1];
+
+  __device__ void init(int tid, int nthreads) {
+    for (int s = tid; s <= kBLdsJoinSlots; s += nthreads) slot[s] = kJoinEmpty;
+  }
+  // At most kBLdsJoinSlots / 2 keys, so a free slot always exists.
+  __device__ void insert(int32_t key, int32_t pl) {
+    if (key == -1) {
+      atomicCAS((unsigned long long*)&slot[kBLdsJoinSlots], (unsigned long long)kJoinEmpty, (unsigned long long)(uint32_t)pl);
+      return;
+    }
+    const uint64_t want = (uint64_t)(uint32_t)key | ((uint64_t)(uint32_t)pl << 32);
+    uint32_t h = hash32(key, 32 - kBLdsJoinBits);
+    for (int step = 0; step < kBLdsJoinSlots; ++step) {
+      const uint64_t old = atomicCAS((unsigned long long*)&slot[h], (unsigned long long)kJoinEmpty, (unsigned long long)want);
+      if (old == kJoinEmpty || (uint32_t)old == (uint32_t)key) return;
+      h = (h + 1) & (kBLdsJoinSlots - 1);
+    }
+  }
+  __device__ __forceinline__ bool lookup(int32_t key, int32_t* pl) const {
+    if (key == -1) {
+      const uint64_t s = slot[kBLdsJoinSlots];
+      *pl = (int32_t)(uint32_t)s;
+      return s != kJoinEmpty;
+    }
+    uint32_t h = hash32(key, 32 - kBLdsJoinBits);
+    for (int step = 0; step < kBLdsJoinSlots; ++step) {
+      const uint64_t s = slot[h];
+      if (s == kJoinEmpty) return false;
+      if ((uint32_t)s == (uint32_t)key) {
+        *pl = (int32_t)(s >> 32);
+        return true;
+      }
+      h = (h + 1) & (kBLdsJoinSlots - 1);
+    }
+    return false;
+  }
+};
+
+// LJ: the instance of the kernel that carries the LDS join table (16 KB more
+// LDS per workgroup); only buckets whose tuning enables it launch it.
+template <bool LJ>
+struct LdsJoinStore {
+  LdsJoin t;
+};
+template <>
+struct LdsJoinStore<false> {};
+
+template <int BLOCK, int IPT, bool LJ>
 __global__ __launch_bounds__(BLOCK) void k_batch_probe(const BInst* __restrict__ inst, const BItem* __restrict__ items,
                                                        int64_t n_items, int64_t* __restrict__ ticket,
                                                        uint32_t* __restrict__ status) {
   __shared__ LdsGroups<kBLdsSlots> lds;
+  __shared__ LdsJoinStore<LJ> ljs;
   __shared__ int64_t s_item;
   for (;;) {
     if (threadIdx.x == 0) s_item = (int64_t)dev_add_ret<unsigned long long>((unsigned long long*)ticket, 1ull);
@@ -112,6 +175,15 @@ __global__ __launch_bounds__(BLOCK) void k_batch_probe(const BInst* __restrict__
     const int lds_probe = I.lds != 0 ? kBLdsProbe : kBLdsCacheProbe;
     const JoinView jv{I.jslots, I.jmask, I.jshift};
     const GroupView gv{I.gslots, I.gmask, I.gshift, status, I.gprobe};
+    bool lj = false;  // uniform over the workgroup (one item)
+    if constexpr (LJ) {
+      lj = I.ljoin != 0;
+      if (lj) {
+        ljs.t.init(threadIdx.x, BLOCK);
+        __syncthreads();
+        for (int64_t j = threadIdx.x; j < I.m; j += BLOCK) ljs.t.insert(I.pk[j], batch_payload(I, j));
+      }
+    }
     lds.init(threadIdx.x, BLOCK);
     __syncthreads();
     uint64_t passed = 0, matched = 0;
@@ -134,7 +206,10 @@ __global__ __launch_bounds__(BLOCK) void k_batch_probe(const BInst* __restrict__
         if (r0 + (int64_t)k * BLOCK >= w.hi || !(d[k] < I.day_lt)) continue;
         ++passed;
         int32_t pl;
-        if (!join_lookup(jv, f[k], &pl)) continue;
+        bool hit;
+        if constexpr (LJ) hit = lj ? ljs.t.lookup(f[k], &pl) : join_lookup(jv, f[k], &pl);
+        else hit = join_lookup(jv, f[k], &pl);
+        if (!hit) continue;
         ++matched;
         const int64_t key = batch_key(I, pl, f[k], fl[k]);
         const uint64_t sp = (uint64_t)p[k], sq = (uint64_t)(int64_t)q[k];
@@ -221,16 +296,17 @@ __global__ void k_batch_fill(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
 }
 
 const rel_batch_tuning kDefaultTuning[] = {
-    {12, 4, 256, 512, 1024},
-    {16, 4, 256, 512, 8192},
-    {20, 4, 256, 512, 16384},
-    {31, 4, 256, 512, 65536},
+    {12, 4, 256, 512, 1024, 0},
+    {16, 4, 256, 512, 8192, 0},
+    {20, 4, 256, 512, 16384, 0},
+    {31, 4, 256, 512, 65536, 0},
 };
 
 bool tuning_ok(const rel_batch_tuning& t) {
   const bool ipt = t.items_per_thread == 1 || t.items_per_thread == 2 || t.items_per_thread == 4 || t.items_per_thread == 8;
   const bool blk = t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512;
-  return ipt && blk && t.lds_groups_max >= 0 && t.lds_groups_max <= kBLdsSlots / 2 && t.rows_per_item > 0 &&
+  return ipt && blk && t.lds_groups_max >= 0 && t.lds_groups_max <= kBLdsSlots / 2 && t.lds_join_max >= 0 &&
+         t.lds_join_max <= kBLdsJoinSlots / 2 && t.rows_per_item > 0 &&
          t.rows_per_item % (t.block * t.items_per_thread) == 0 && t.log2_rows_below > 0 && t.log2_rows_below <= 31;
 }
 
@@ -265,14 +341,14 @@ struct rel_batch {
 
 namespace {
 
-template <int BLOCK>
+template <int BLOCK, bool LJ>
 void launch_probe(hipStream_t s, unsigned grid, int ipt, const BInst* inst, const BItem* items, int64_t n,
                   int64_t* ticket, uint32_t* status) {
   switch (ipt) {
-    case 1: hipLaunchKernelGGL((k_batch_probe<BLOCK, 1>), dim3(grid), dim3(BLOCK), 0, s, inst, items, n, ticket, status); break;
-    case 2: hipLaunchKernelGGL((k_batch_probe<BLOCK, 2>), dim3(grid), dim3(BLOCK), 0, s, inst, items, n, ticket, status); break;
-    case 4: hipLaunchKernelGGL((k_batch_probe<BLOCK, 4>), dim3(grid), dim3(BLOCK), 0, s, inst, items, n, ticket, status); break;
-    default: hipLaunchKernelGGL((k_batch_probe<BLOCK, 8>), dim3(grid), dim3(BLOCK), 0, s, inst, items, n, ticket, status); break;
+    case 1: hipLaunchKernelGGL((k_batch_probe<BLOCK, 1, LJ>), dim3(grid), dim3(BLOCK), 0, s, inst, items, n, ticket, status); break;
+    case 2: hipLaunchKernelGGL((k_batch_probe<BLOCK, 2, LJ>), dim3(grid), dim3(BLOCK), 0, s, inst, items, n, ticket, status); break;
+    case 4: hipLaunchKernelGGL((k_batch_probe<BLOCK, 4, LJ>), dim3(grid), dim3(BLOCK), 0, s, inst, items, n, ticket, status); break;
+    default: hipLaunchKernelGGL((k_batch_probe<BLOCK, 8, LJ>), dim3(grid), dim3(BLOCK), 0, s, inst, items, n, ticket, status); break;
   }
 }
 
@@ -286,14 +362,21 @@ void launch_build(hipStream_t s, unsigned grid, int block, const BInst* inst, co
   }
 }
 
-void launch_probe_any(hipStream_t s, unsigned grid, int block, int ipt, const BInst* inst, const BItem* items,
+template <bool LJ>
+void launch_probe_blk(hipStream_t s, unsigned grid, int block, int ipt, const BInst* inst, const BItem* items,
                       int64_t n, int64_t* ticket, uint32_t* status) {
   switch (block) {
-    case 64: launch_probe<64>(s, grid, ipt, inst, items, n, ticket, status); break;
-    case 128: launch_probe<128>(s, grid, ipt, inst, items, n, ticket, status); break;
-    case 256: launch_probe<256>(s, grid, ipt, inst, items, n, ticket, status); break;
-    default: launch_probe<512>(s, grid, ipt, inst, items, n, ticket, status); break;
+    case 64: launch_probe<64, LJ>(s, grid, ipt, inst, items, n, ticket, status); break;
+    case 128: launch_probe<128, LJ>(s, grid, ipt, inst, items, n, ticket, status); break;
+    case 256: launch_probe<256, LJ>(s, grid, ipt, inst, items, n, ticket, status); break;
+    default: launch_probe<512, LJ>(s, grid, ipt, inst, items, n, ticket, status); break;
   }
+}
+
+void launch_probe_any(hipStream_t s, unsigned grid, int block, int ipt, bool lj, const BInst* inst,
+                      const BItem* items, int64_t n, int64_t* ticket, uint32_t* status) {
+  if (lj) launch_probe_blk<true>(s, grid, block, ipt, inst, items, n, ticket, status);
+  else launch_probe_blk<false>(s, grid, block, ipt, inst, items, n, ticket, status);
 }
 
 // Workgroups for a persistent kernel: enough to fill the chip, never more than the items.
@@ -386,6 +469,7 @@ rel_status rel_batch_create(rel_ctx* ctx, const rel_batch_item* items, int32_t k
     I.gshift = 32u - gl;
     I.gprobe = hinted ? kHintProbe : (uint32_t)(1ull << gl);
     I.lds = (t.lds_groups_max > 0 && ub <= t.lds_groups_max) ? 1 : 0;
+    I.ljoin = (t.lds_join_max > 0 && m <= t.lds_join_max) ? 1 : 0;
     I.out_key = it.out.key;
     I.out_sp = it.out.sum_price;
     I.out_sq = it.out.sum_qty;
@@ -491,8 +575,9 @@ rel_status rel_batch_create(rel_ctx* ctx, const rel_batch_item* items, int32_t k
     for (size_t t = 0; t < b->buckets.size(); ++t) {
       const BucketPlan& bp = b->buckets[t];
       if (bp.probe_n)
-        launch_probe_any(s, persistent_grid(ctx, bp.probe_n, bp.t.block), bp.t.block, bp.t.items_per_thread, b->d_inst,
-                         b->d_items + bp.probe_lo, bp.probe_n, b->d_tickets + 2 * t + 1, b->d_status);
+        launch_probe_any(s, persistent_grid(ctx, bp.probe_n, bp.t.block), bp.t.block, bp.t.items_per_thread,
+                         bp.t.lds_join_max > 0, b->d_inst, b->d_items + bp.probe_lo, bp.probe_n,
+                         b->d_tickets + 2 * t + 1, b->d_status);
     }
     if (b->fin_n)
       hipLaunchKernelGGL(k_batch_finalize, dim3(persistent_grid(ctx, b->fin_n, 256)), dim3(256), 0, s, b->d_inst,
@@ -538,7 +623,7 @@ rel_status rel_batch_sync(rel_batch* b, rel_stats* stats) {
       s.groups = h[3 * i + 2];
       s.join_capacity = (int64_t)hi[i].jmask + 1;
       s.group_capacity = (int64_t)hi[i].gmask + 1;
-      s.join_placement = REL_PLACE_GLOBAL;
+      s.join_placement = hi[i].ljoin ? REL_PLACE_LDS : REL_PLACE_GLOBAL;
       s.group_placement = hi[i].lds ? REL_PLACE_LDS : REL_PLACE_GLOBAL;
       s.overflowed = 0;
       s.fell_back = 0;

@@ -95,7 +95,7 @@ class BatchItem(ctypes.Structure):
 
 class BatchTuning(ctypes.Structure):
     _fields_ = [("log2_rows_below", _i32), ("items_per_thread", _i32), ("block", _i32), ("lds_groups_max", _i32),
-                ("rows_per_item", _i32)]
+                ("rows_per_item", _i32), ("lds_join_max", _i32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

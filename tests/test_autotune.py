@@ -43,6 +43,18 @@ def test_tune_builds_ascending_table_and_skips_empty_buckets():
     table, report = autotune.tune(bucket_measure)
     assert [e["log2_rows_below"] for e in table] == [12, 18, 31]
     assert all(e["block"] == 512 and e["items_per_thread"] == 1 for e in table)
+    assert all(e["lds_join_max"] == 0 for e in table)  # equal times: the smaller option
+
+
+def test_tune_picks_the_faster_join_placement():
+    # the main search runs with device-memory join tables; then every join
+    # option is measured for the winner, and the faster one is kept
+    def bucket_measure(i):
+        return lambda c: 1.0 / c.block + (0.0 if c.lds_join_max == 1024 else 0.5)
+
+    table, report = autotune.tune(bucket_measure)
+    assert all(e["lds_join_max"] == 1024 and e["block"] == 512 for e in table)
+    assert all(any(k.startswith("join ") for k in r) for r in report.values())
 
 
 def test_bucket_of_matches_library_rule():

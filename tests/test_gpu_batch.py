@@ -75,12 +75,45 @@ def test_batch_graph_replays_with_eager_work_between(ctx):
     [dict(log2_rows_below=31, items_per_thread=1, block=64, lds_groups_max=0, rows_per_item=512)],
     [dict(log2_rows_below=14, items_per_thread=8, block=512, lds_groups_max=512, rows_per_item=4096),
      dict(log2_rows_below=31, items_per_thread=2, block=128, lds_groups_max=64, rows_per_item=1024)],
+    [dict(log2_rows_below=31, items_per_thread=4, block=256, lds_groups_max=512, rows_per_item=4096, lds_join_max=1024)],
+    [dict(log2_rows_below=13, items_per_thread=1, block=64, lds_groups_max=0, rows_per_item=512, lds_join_max=1024),
+     dict(log2_rows_below=31, items_per_thread=8, block=512, lds_groups_max=128, rows_per_item=8192, lds_join_max=256)],
 ])
 def test_batch_tuning_variants_agree(ctx, tuning):
     tables, insts = _instances(16, seed=9)
     b = rel.Batch(ctx, insts, tuning=tuning)
     b.run()
     _check(b, tables, b.sync())
+    b.close()
+
+
+@pytest.mark.parametrize("group_by", ["fk", "dim_grp", "prio_flag"])
+def test_batch_lds_join_tables(ctx, group_by):
+    """Instances of at most 1024 dim keys probe a join table that each work
+    item builds in LDS: a dim key of -1 (the side slot) and payloads of -1
+    included, fact keys outside the dim keys, one instance past the limit
+    (device-memory table)."""
+    tables, insts = [], []
+    for i, (n, m) in enumerate([(3000, 1024), (70_000, 700), (20_000, 1), (5000, 1025), (900, 300)]):
+        T = datagen.make_tables(n, m, 40 + i, day_lt=1500, group_by=group_by, grp_card=50 if group_by == "dim_grp" else None)
+        if m > 2:
+            T.pk[m // 2] = -1
+            if T.grp is not None:
+                T.grp[m // 3] = -1
+            T.prio[m // 4] = -1
+        T.fk[::5] = T.pk[datagen.uniform((n + 4) // 5, 0, m - 1, np.int64, 40 + i, 9)]
+        T.fk[::11] = -1
+        T.fk[::13] = 5_000_000 + i
+        fact, dim = to_dev(T)
+        tables.append(T)
+        insts.append((fact, dim, T.day_lt, T.group_by, 0))
+    tuning = [dict(log2_rows_below=31, items_per_thread=4, block=256, lds_groups_max=512, rows_per_item=4096,
+                   lds_join_max=1024)]
+    b = rel.Batch(ctx, insts, tuning=tuning)
+    b.run()
+    st = b.sync()
+    _check(b, tables, st)
+    assert [s["join_placement"] for s in st] == ["lds", "lds", "lds", "global", "lds"]
     b.close()
 
 
