@@ -324,7 +324,7 @@ rel_status join_index_build(rel_ctx* ctx, const int32_t* pk, const void* payload
   int64_t gm = (m + kMinMaxBlock * 16 - 1) / (kMinMaxBlock * 16);
   if (gm > kMinMaxGrid) gm = kMinMaxGrid;
   {
-    KernelTimer kt(ctx, "join_index_minmax");
+    KernelTimer kt(ctx, "key_minmax");
     if (m > 0)
       hipLaunchKernelGGL(k_key_minmax, dim3((unsigned)gm), dim3(kMinMaxBlock), 0, ctx->stream, pk, m, (uint32_t*)part);
   }

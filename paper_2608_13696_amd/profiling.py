@@ -67,7 +67,9 @@ def timer_name(kernel: str) -> str:
              "k_fused": "probe_agg", "k_finalize": "finalize", "k_join_build": "join_build",
              "k_join_probe": "join_probe", "k_join_gather": "join_gather", "k_filter_compact": "filter_compact",
              "k_pred_compiled": "pred_compiled", "k_pred_interpreted": "pred_interpreted", "k_bw_copy": "bw_copy",
-             "k_bw_read": "bw_read", "k_bw_write": "bw_write"}
+             "k_bw_read": "bw_read", "k_bw_write": "bw_write", "k_key_minmax": "key_minmax", "k_keymap": "keymap",
+             "k_index_clear": "join_table_init", "k_index_build": "join_build", "k_group_merge": "group_merge",
+             "k_init_groups": "group_table_init", "k_index_verify": "join_index_verify"}
     return names.get(base, base)
 
 
