@@ -31,7 +31,15 @@ namespace {
 // Rows per thread, written in front of the program text: 32 for generated
 // masks (two groups of 16-byte loads per column), 16 for the interpreter,
 // whose rows are evaluated one after another.
-int rows_per_thread(int32_t mode) { return mode == REL_PRED_COMPILED ? 32 : 16; }
+// Rows per thread. Compiled: 32 when the predicate reads at most 8 bytes per
+// row, else 16 (a thread's loads for 32 rows of wide columns hold so many
+// registers that fewer waves fit; measured on 60M rows: the 4-term predicate
+// over 17 B per row 0.370 ms at 32, 0.316 ms at 16; day < 1200 alone 0.104 ms
+// at 32, 0.117 ms at 16). The interpreter evaluates its rows one after
+// another and keeps 16.
+int rows_per_thread(int32_t mode, int bytes_per_row) {
+  return mode == REL_PRED_COMPILED && bytes_per_row <= 8 ? 32 : 16;
+}
 
 // Bytes of one element of a rel_dtype (I8, I16, I32, I64, F32, F64).
 int dtype_bytes(int dt) {
@@ -271,6 +279,7 @@ struct rel_pred {
   hipFunction_t fn = nullptr;
   void* d_terms = nullptr;  // the term list, for the interpreter
   int tiles_per_ticket = 4;  // consecutive tiles per ticket (one look-back per group of them)
+  int ipt = 16;              // rows per thread
 };
 
 namespace {
@@ -347,7 +356,8 @@ rel_status rel_pred_create(rel_ctx* ctx, const rel_pred_term* terms, int32_t n_t
   for (size_t c = 0; c < col_dtype.size(); ++c)
     if (col_dtype[c] >= 0) bytes_per_row += dtype_bytes(col_dtype[c]);
   p->tiles_per_ticket = bytes_per_row <= 8 ? 4 : 1;
-  const std::string src = "#define IPT " + std::to_string(rows_per_thread(mode)) + "\n#define TILES_PER_TICKET " +
+  p->ipt = rows_per_thread(mode, bytes_per_row);
+  const std::string src = "#define IPT " + std::to_string(p->ipt) + "\n#define TILES_PER_TICKET " +
                           std::to_string(p->tiles_per_ticket) + "\n#define PRED_KERNEL " +
                           kernel_name(mode) + "\n" + kSkeleton +
                           (mode == REL_PRED_COMPILED ? compiled_mask(terms, n_terms) : std::string(kInterpreter));
@@ -385,7 +395,7 @@ rel_status rel_pred_filter(rel_pred* p, const void* const* columns, int32_t n_co
   rel_status s = relh::ensure_counters(ctx);
   if (s != REL_OK) return s;
   if (n == 0) return relh::fill_u64(ctx, d_out_count, 1, 0);
-  const int64_t tile_rows = 256 * rows_per_thread(p->mode);
+  const int64_t tile_rows = 256 * (int64_t)p->ipt;
   const long long ntiles = (n + tile_rows - 1) / tile_rows;
   long long ngroups = (ntiles + p->tiles_per_ticket - 1) / p->tiles_per_ticket;
   void* st;
