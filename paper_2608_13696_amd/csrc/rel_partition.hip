@@ -1100,13 +1100,27 @@ __device__ __forceinline__ void check_later_chunks_dense(const uint64_t* tkc, co
 // of the unit owns the slot and all ones when none does (a fact row's count
 // increment, 2^32, never changes the low half), so a fact row needs no probe
 // and no compare, only a range check. Emission walks the unit's dim keys
-// rather than the slots. The host launches both instances; the one that does
-// not match the key map returns at once.
+// rather than the slots. One kernel holds the code of both orders and takes
+// the one the key map names (a branch on one word, uniform over the grid).
 constexpr uint32_t kPosShift = 20;
 
+// The groupjoin's LDS, shared by both key orders' code (one kernel holds both).
+struct GroupjoinLds {
+  uint64_t tkc[kJSlots];
+  uint64_t tsp[kJSlots];
+  uint64_t tsq[kJSlots];
+  uint32_t scr[kJBlock / kWave];
+  uint32_t s_wk[kJPer][kJBlock / kWave];  // occupied slots per (slot round, wave)
+  uint64_t s_excl;
+  uint4 s_desc;
+  uint2 s_split;
+  int64_t s_u;
+  uint32_t s_last;
+  uint64_t s_matched[kJBlock / kWave];
+};
+
 template <bool DENSE>
-__global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
-  if ((a.km->dense != 0) != DENSE) return;
+__device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds& sh) {
   uint32_t dsub = 0, dmul = 0, dmask = 0, drange = 0;
   if (DENSE) {
     dsub = a.km->sub;
@@ -1115,17 +1129,17 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
     drange = a.km->range;
   }
   auto dslot = [&](int32_t key) { return (((uint32_t)key - dsub) * dmul) & dmask; };
-  __shared__ uint64_t tkc[kJSlots];
-  __shared__ uint64_t tsp[kJSlots];
-  __shared__ uint64_t tsq[kJSlots];
-  __shared__ uint32_t scr[kJBlock / kWave];
-  __shared__ uint32_t s_wk[kJPer][kJBlock / kWave];  // occupied slots per (slot round, wave)
+  uint64_t* const tkc = sh.tkc;
+  uint64_t* const tsp = sh.tsp;
+  uint64_t* const tsq = sh.tsq;
+  uint32_t* const scr = sh.scr;
+  auto& s_wk = sh.s_wk;
   static_assert(kJDK <= kJPer, "dense emission rounds share s_wk");
-  __shared__ uint64_t s_excl;
-  __shared__ uint4 s_desc;
-  __shared__ uint2 s_split;
-  __shared__ int64_t s_u;
-  __shared__ uint32_t s_last;
+  uint64_t& s_excl = sh.s_excl;
+  uint4& s_desc = sh.s_desc;
+  uint2& s_split = sh.s_split;
+  int64_t& s_u = sh.s_u;
+  uint32_t& s_last = sh.s_last;
   const int64_t n_units = *a.n_units;
   const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   uint64_t matched = 0;
@@ -1454,9 +1468,14 @@ __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
 #pragma unroll
     for (int k = 0; k < kJDK; ++k) dkeys[k] = ndkeys[k];
   }
-  __shared__ uint64_t s_matched[kJBlock / kWave];
-  matched = block_sum_u64<kJBlock>(matched, s_matched);
+  matched = block_sum_u64<kJBlock>(matched, sh.s_matched);
   if (threadIdx.x == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
+}
+
+__global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
+  __shared__ GroupjoinLds sh;
+  if (a.km->dense != 0) groupjoin_units<true>(a, sh);
+  else groupjoin_units<false>(a, sh);
 }
 
 // ---- partitioned join + aggregate ------------------------------------------------------------------------------------
@@ -2171,9 +2190,7 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   a.d_n = out->d_n_groups;
   a.km = P.F.km;
   const unsigned grid = (unsigned)ctx->num_cus * 3;  // 48 KB of LDS each: three per CU
-  // the key map decides which of the two runs (the other returns at once)
-  hipLaunchKernelGGL(k_part_groupjoin<true>, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
-  hipLaunchKernelGGL(k_part_groupjoin<false>, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
+  hipLaunchKernelGGL(k_part_groupjoin, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
   REL_LAUNCH_CHECK(ctx, "part_groupjoin");
   return REL_OK;
 }

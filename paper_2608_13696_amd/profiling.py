@@ -112,11 +112,11 @@ def read_csv(d: str, suffix: str) -> list[dict]:
     return rows
 
 
-# Kernels that one library call launches as several instances under one
-# name (the groupjoin's dense-order and hash-order instances; the one that
-# does not match the key map returns at once): their counters and durations
-# are summed per call, as the library's own timer spans both launches.
-LAUNCHES_PER_CALL = {"part_groupjoin": 2}
+# Kernels that one library call launches several times under one name: their
+# counters and durations are summed per call, as the library's own timer spans
+# all the launches. (None at present; the table keeps the summaries honest if
+# a kernel is ever split into instances again.)
+LAUNCHES_PER_CALL: dict = {}
 
 
 def counter_means(d: str) -> dict:
