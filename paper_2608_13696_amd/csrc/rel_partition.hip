@@ -1080,13 +1080,15 @@ __device__ __forceinline__ void check_later_chunks(const uint64_t* tkey, const i
 }
 
 // The same for a direct-mapped (dense order) table: a later chunk's key is
-// repeated when its slot is marked present.
+// repeated when a dim key of this unit owns its slot.
 template <int NT>
-__device__ __forceinline__ void check_later_chunks_dense(const uint64_t* tkc, const int32_t* dkey, uint32_t from,
+__device__ __forceinline__ void check_later_chunks_dense(const uint32_t* own, const int32_t* dkey, uint32_t from,
                                                          uint32_t to, uint32_t sub, uint32_t mul, uint32_t mask,
                                                          uint32_t* status) {
-  for (uint32_t j = from + threadIdx.x; j < to; j += NT)
-    if ((uint32_t)tkc[(((uint32_t)dkey[j] - sub) * mul) & mask] == 0u) set_status(status, kDevDupKey);
+  for (uint32_t j = from + threadIdx.x; j < to; j += NT) {
+    const uint32_t h = (((uint32_t)dkey[j] - sub) * mul) & mask;
+    if ((own[h >> 5] >> (h & 31)) & 1u) set_status(status, kDevDupKey);
+  }
 }
 
 // A slot is one 64-bit word {key, count}: the key in the low half, the rows
@@ -1096,17 +1098,24 @@ __device__ __forceinline__ void check_later_chunks_dense(const uint64_t* tkc, co
 // three 256-thread workgroups fit on a CU.
 //
 // DENSE (the partitions follow the dense key order): the table is direct-
-// mapped, slot = the key's slot bits; the word's low half is 0 when a dim key
-// of the unit owns the slot and all ones when none does (a fact row's count
-// increment, 2^32, never changes the low half), so a fact row needs no probe
-// and no compare, only a range check. Emission walks the unit's dim keys
-// rather than the slots. One kernel holds the code of both orders and takes
+// mapped, slot = the key's slot bits, with a 32-bit count per slot and a
+// bitmap of the slots the unit's dim keys own (which finds a repeated key);
+// a fact row needs no probe and no compare, only a range check. Emission
+// walks the unit's dim keys rather than the slots, so the slots no dim key
+// owns are never read (their counts and sums are reset when a dim key takes
+// them). One kernel holds the code of both orders and takes
 // the one the key map names (a branch on one word, uniform over the grid).
 constexpr uint32_t kPosShift = 20;
 
 // The groupjoin's LDS, shared by both key orders' code (one kernel holds both).
 struct GroupjoinLds {
-  uint64_t tkc[kJSlots];
+  union {
+    uint64_t tkc[kJSlots];  // hash order: {key, count} words
+    struct {
+      uint32_t cnt[kJSlots];       // dense order: rows per slot
+      uint32_t own[kJSlots / 32];  // dense order: slots owned by a dim key of the unit
+    } d;
+  } t;
   uint64_t tsp[kJSlots];
   uint64_t tsq[kJSlots];
   uint32_t scr[kJBlock / kWave];
@@ -1129,7 +1138,9 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
     drange = a.km->range;
   }
   auto dslot = [&](int32_t key) { return (((uint32_t)key - dsub) * dmul) & dmask; };
-  uint64_t* const tkc = sh.tkc;
+  uint64_t* const tkc = sh.t.tkc;
+  uint32_t* const dcnt = sh.t.d.cnt;
+  uint32_t* const down = sh.t.d.own;
   uint64_t* const tsp = sh.tsp;
   uint64_t* const tsq = sh.tsq;
   uint32_t* const scr = sh.scr;
@@ -1162,7 +1173,11 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
   // The table starts empty once; after that each unit's emission leaves the
   // slots it read empty again, and an insert zeroes its slot's sums, so no
   // unit spends a phase and a barrier clearing it.
-  for (int s = tid; s < kJSlots; s += kJBlock) tkc[s] = kLdsEmpty;
+  if (DENSE) {
+    for (int s = tid; s < kJSlots / 32; s += kJBlock) down[s] = 0u;
+  } else {
+    for (int s = tid; s < kJSlots; s += kJBlock) tkc[s] = kLdsEmpty;
+  }
   __syncthreads();
   int64_t u = s_u;
   uint4 d = s_desc;
@@ -1191,9 +1206,9 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
 #pragma unroll
       for (int k = 0; k < kJDK; ++k) {
         if (dlo + tid + k * kJBlock >= dhi) continue;
-        const uint32_t h = dslot(dkeys[k]);
-        const uint64_t old = atomicExch((unsigned long long*)&tkc[h], 0ull);
-        if ((uint32_t)old == 0u) set_status(a.status, kDevDupKey);  // the slot's key came twice
+        const uint32_t h = dslot(dkeys[k]), bit = 1u << (h & 31);
+        if (atomicOr(&down[h >> 5], bit) & bit) set_status(a.status, kDevDupKey);  // the slot's key came twice
+        dcnt[h] = 0;
         tsp[h] = 0;
         tsq[h] = 0;
       }
@@ -1235,7 +1250,7 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
     }
     __syncthreads();
     if (sp.x == 0 && sp.y > dhi) {
-      if (DENSE) check_later_chunks_dense<kJBlock>(tkc, a.dkey, dhi, sp.y, dsub, dmul, dmask, a.status);
+      if (DENSE) check_later_chunks_dense<kJBlock>(down, a.dkey, dhi, sp.y, dsub, dmul, dmask, a.status);
       else check_later_chunks<kJBlock>(tkc, a.dkey, dhi, sp.y, a.status);
     }
     int32_t ndkeys[kJDK];
@@ -1317,7 +1332,8 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
           if ((int)lane == first) {
             atomicAdd((unsigned long long*)&tsp[s0], (unsigned long long)tsum_p);
             atomicAdd((unsigned long long*)&tsq[s0], (unsigned long long)tsum_q);
-            atomicAdd((unsigned long long*)&tkc[s0], (unsigned long long)__popcll(same) << 32);
+            if (DENSE) atomicAdd(&dcnt[s0], (uint32_t)__popcll(same));
+            else atomicAdd((unsigned long long*)&tkc[s0], (unsigned long long)__popcll(same) << 32);
           }
           found = found && !mine;
         }
@@ -1325,7 +1341,8 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
         if (found) {
           atomicAdd((unsigned long long*)&tsp[slot], (unsigned long long)pay.sp[k]);
           atomicAdd((unsigned long long*)&tsq[slot], (unsigned long long)(int64_t)pay.qty[k]);
-          atomicAdd((unsigned long long*)&tkc[slot], 1ull << 32);
+          if (DENSE) atomicAdd(&dcnt[slot], 1u);
+          else atomicAdd((unsigned long long*)&tkc[slot], 1ull << 32);
         }
       }
     }
@@ -1338,6 +1355,7 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
     const int64_t un = s_u;
     const uint4 dn = s_desc;
     const uint2 sn = s_split;
+    if (DENSE && tid < kJSlots / 32) down[tid] = 0u;  // for the next unit's build
     // past the last unit the loads read the current unit again (discarded)
     const uint4 pd = un < n_units ? dn : d;
     if (sp.x == 0) {
@@ -1356,7 +1374,7 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
       for (int k = 0; k < kRounds; ++k) {
         if constexpr (DENSE) {
           sl[k] = (int)dslot(dkeys[k]);
-          occ[k] = dlo + tid + k * kJBlock < dhi ? (uint32_t)(tkc[sl[k]] >> 32) : 0u;
+          occ[k] = dlo + tid + k * kJBlock < dhi ? dcnt[sl[k]] : 0u;
         } else {
           sl[k] = k * kJBlock + tid;
           const uint64_t c = tkc[sl[k]];
@@ -1387,12 +1405,8 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
         if (occ[k] != 0)
           put_group(a, o0 + base[k] + mask_rank(bal[k]), DENSE ? (int64_t)dkeys[k] : (int64_t)(int32_t)(uint32_t)tkc[s],
                     tsp[s], tsq[s], occ[k]);
-        if constexpr (DENSE) {
-          matched += occ[k];
-          if (dlo + tid + k * kJBlock < dhi) tkc[s] = kLdsEmpty;
-        } else {
-          tkc[s] = kLdsEmpty;
-        }
+        if constexpr (DENSE) matched += occ[k];
+        else tkc[s] = kLdsEmpty;
       }
     } else {
       // Sub-unit of a split chunk: add the partial sums into the chunk's
@@ -1405,9 +1419,7 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
           const uint32_t pos = tid + k * kJBlock;
           if (dlo + pos >= dhi) continue;
           const uint32_t h = dslot(dkeys[k]);
-          const uint64_t w = tkc[h];
-          tkc[h] = kLdsEmpty;
-          const uint32_t c = (uint32_t)(w >> 32);
+          const uint32_t c = dcnt[h];
           matched += c;
           if (c == 0) continue;
           SplitAcc* e = acc + pos;
