@@ -57,6 +57,23 @@ def test_headline_60m_group_by_fk(ctx):
     assert st["join_placement"] == "partitioned" and st["groups"] > 8_000_000
 
 
+def test_large_uniform_60m_group_by_fk(ctx):
+    """The headline's sizes with fk uniform over the 15M dim keys (12.7M groups):
+    every partition and unit is full, no partition is split."""
+    st = _compare_full(ctx, datagen.large_uniform())
+    assert st["join_placement"] == "partitioned" and st["groups"] > 12_000_000
+
+
+def test_headline_sizes_sparse_keys_hash_order(ctx):
+    """The headline's sizes with the dim keys spread 40 times their count, so
+    the partitions follow the hash order (not the dense one) at full size."""
+    T = datagen.large()
+    T.pk = (T.pk.astype(np.int64) * 40 + 3).astype(np.int32)
+    T.fk = (T.fk.astype(np.int64) * 40 + 3).astype(np.int32)
+    st = _compare_full(ctx, T)
+    assert st["join_placement"] == "partitioned" and st["groups"] > 8_000_000
+
+
 def test_medium_6m_default_path(ctx):
     """fact 6M x dim 1.5M, fk uniform, day < 1800, GROUP BY (prio, flag): the
     library's default placement for it (radix-partitioned)."""
