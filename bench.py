@@ -143,6 +143,9 @@ def pipeline_binding(kt: dict, steps: int, compulsory: float, ms: float, workloa
                  "ridge_insts_per_byte": dev.ridge_byte},
         "traffic_bytes_per_step": traffic or None,
         "traffic_over_compulsory": (traffic / compulsory) if traffic else None,
+        # the counted HBM traffic of the step over its time, against the peak:
+        # how busy HBM is, re-reads and round trips included
+        "traffic_frac": (traffic / (ms / 1e3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
         "counter_coverage": (covered_ms / total_ms) if total_ms else None,
         "counters": "profiles/traffic_<kernel>_<workload>.json, used only while the kernel sources are unchanged",
     }
