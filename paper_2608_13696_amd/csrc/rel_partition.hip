@@ -19,7 +19,9 @@
 // Then one work unit per (partition, or 2^merge consecutive partitions in
 // the dense order; chunk of dim keys), ordered by decreasing fact-row count,
 // builds an LDS table, streams the unit's fact rows through it, and appends
-// its groups to the output with one atomic offset reservation per unit. The same partitions and units
+// its groups to the output with one atomic offset reservation per unit. In
+// the dense order the dim side stops after its first level and hands the
+// units a presence bitmap over the key positions instead of its keys. The same partitions and units
 // serve grouping by a dim attribute: k_part_join_agg (few groups, an LDS
 // group table per workgroup) and k_part_join_eager (many groups, partials per
 // dim key added to a device-memory table at the end of each unit).
@@ -68,6 +70,8 @@ struct KeyMap {
   uint32_t slot_bits;  // dense: slot bits per partition (<= kJSlotBits)
   uint32_t range;      // dense: kmax - kmin + 1 (fact keys outside it match nothing)
   uint32_t merge;      // dense: log2 of the partitions per groupjoin unit
+  uint32_t lbits;      // dense: L, the key positions are [0, 2^L)
+  uint32_t inv;        // dense: mul^-1 mod 2^32 (key - kmin = position * inv mod 2^L)
 };
 
 __device__ __forceinline__ uint32_t key_hash(uint32_t sub, uint32_t mul, uint32_t sh, int32_t key) {
@@ -98,7 +102,7 @@ __global__ __launch_bounds__(kWave) void k_keymap(const uint32_t* __restrict__ p
     hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, kWave));
   }
   if (threadIdx.x != 0) return;
-  KeyMap k{0u, 2654435769u, 0u, 0u, 0u, 0u, 0u};
+  KeyMap k{0u, 2654435769u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
   if (nparts > 0) {
     const int64_t kmin = (int32_t)(~lo ^ 0x80000000u), kmax = (int32_t)(hi ^ 0x80000000u);
     const int64_t range = kmax - kmin + 1;  // >= 1
@@ -113,6 +117,10 @@ __global__ __launch_bounds__(kWave) void k_keymap(const uint32_t* __restrict__ p
       k.slot_bits = L - pbits;
       k.range = (uint32_t)range;
       k.merge = min((uint32_t)kJSlotBits - k.slot_bits, pbits);
+      k.lbits = L;
+      uint32_t x = k.mul;  // Newton's iteration for the inverse of an odd number mod 2^32: 3, 6, 12, 24, 48 bits
+      for (int i = 0; i < 4; ++i) x *= 2u - k.mul * x;
+      k.inv = x;
     }
   }
   *km = k;
@@ -151,6 +159,7 @@ struct PartSide {
   int64_t* ntiles2;  // number of second-level tiles
   int64_t* zero2;    // nullable: two int64 counters that the first-level histogram clears
   const KeyMap* km;  // the key order of the bins
+  uint32_t dense_stop;  // dim side of GROUP BY fk: in the dense order, no second level (see k_dim_bitmap)
   uint32_t b1, b2;
 };
 
@@ -569,6 +578,7 @@ __device__ __forceinline__ Tile2 find_tile(const L2Map& mp, uint32_t nb1, int64_
 constexpr int kHR = (int)(kTile / kBlk);
 constexpr uint32_t kScanTilesMax = 128;
 __global__ __launch_bounds__(kBlk) void k_p2_hist(PartSide s) {
+  if (s.dense_stop && s.km->dense) return;
   __shared__ L2Map mp;
   __shared__ uint32_t scr[kBlk / kWave];
   __shared__ uint32_t h[kMaxBins];
@@ -624,6 +634,7 @@ __global__ __launch_bounds__(kBlk) void k_p2_hist(PartSide s) {
 // starts and counts; then p's entries of the tile table.
 constexpr int kScanBatch = 8;
 __global__ __launch_bounds__(kBlk) void k_p2_scan(PartSide s) {
+  if (s.dense_stop && s.km->dense) return;
   __shared__ L2Map mp;
   __shared__ uint32_t scr[kBlk / kWave];
   build_l2map<kBlk>(s, mp, scr);
@@ -701,6 +712,7 @@ __device__ __forceinline__ void load_p2(const PartSide& s, const Tile2& x, bool 
 // xcd_tile(b, tiles), so each XCD holds a contiguous range of tiles.
 template <bool FACT>
 __global__ __launch_bounds__(kSBlk) void k_p2_scatter(PartSide s) {
+  if (s.dense_stop && s.km->dense) return;
   __shared__ Stage<FACT, (int)kTile> st;
   const int64_t ntiles = *s.ntiles2;
   if ((int64_t)blockIdx.x >= ntiles) return;
@@ -720,6 +732,57 @@ __global__ __launch_bounds__(kSBlk) void k_p2_scatter(PartSide s) {
   __syncthreads();
   stage_and_write<FACT, false, kSBlk, (int)kTile>(st, r, 0, bin_of, nb2, pay, s.key2, s.price2, FACT ? s.qty2 : s.pay2,
                                                   FACT ? s.flag2 : nullptr);
+}
+
+// ---- dense order: the dim side's presence bitmap ---------------------------------------------------------------------
+//
+// In the dense order a groupjoin unit is a range of key positions, and all it
+// needs from the dim side is which positions hold a dim key. One workgroup per
+// first-level partition sets those bits in LDS (a bit already set is a
+// repeated key) and stores the partition's words of a bitmap over all 2^L
+// positions; the dim side stops after its first level. With fewer than 32
+// positions per partition, one workgroup builds the whole (small) bitmap.
+constexpr int kBmBlock = 1024;
+__global__ __launch_bounds__(kBmBlock) void k_dim_bitmap(PartSide s, uint32_t* __restrict__ bitmap,
+                                                         uint32_t* __restrict__ status) {
+  HIP_DYNAMIC_SHARED(uint32_t, lb)
+  __shared__ uint32_t s_red[kBmBlock / kWave];
+  if (!s.km->dense) return;
+  const uint32_t sub = s.km->sub, mul = s.km->mul, L = s.km->lbits;
+  const uint32_t lmask = L >= 32 ? ~0u : (1u << L) - 1u;
+  const uint32_t pbw = L - s.b1;  // position bits inside a first-level partition
+  const uint32_t tid = threadIdx.x;
+  if (pbw < 5) {
+    if (blockIdx.x != 0) return;
+    const uint32_t nw = ((1u << L) + 31) / 32;
+    for (uint32_t w = tid; w < nw; w += kBmBlock) lb[w] = 0u;
+    __syncthreads();
+    for (int64_t j = tid; j < s.n; j += kBmBlock) {
+      const uint32_t kp = (((uint32_t)s.key1[j] - sub) * mul) & lmask, bit = 1u << (kp & 31);
+      if (atomicOr(&lb[kp >> 5], bit) & bit) set_status(status, kDevDupKey);
+    }
+    __syncthreads();
+    for (uint32_t w = tid; w < nw; w += kBmBlock) bitmap[w] = lb[w];
+    return;
+  }
+  const uint32_t p = blockIdx.x, nw = 1u << (pbw - 5), pmask = (1u << pbw) - 1u;
+  for (uint32_t w = tid; w < nw; w += kBmBlock) lb[w] = 0u;
+  // the partition's first row: the totals of the partitions before it (nb1 <= kBmBlock)
+  uint32_t before = tid < p ? s.tot1[tid] : 0u;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) before += (uint32_t)__shfl_xor((int)before, o, kWave);
+  if (lane_id() == 0) s_red[tid / kWave] = before;
+  __syncthreads();
+  uint32_t start = 0;
+#pragma unroll
+  for (int w = 0; w < kBmBlock / kWave; ++w) start += s_red[w];
+  const uint32_t cnt = s.tot1[p];
+  for (uint32_t j = tid; j < cnt; j += kBmBlock) {
+    const uint32_t kp = (((uint32_t)s.key1[(int64_t)start + j] - sub) * mul) & pmask, bit = 1u << (kp & 31);
+    if (atomicOr(&lb[kp >> 5], bit) & bit) set_status(status, kDevDupKey);
+  }
+  __syncthreads();
+  for (uint32_t w = tid; w < nw; w += kBmBlock) bitmap[(size_t)p * nw + w] = lb[w];
 }
 
 // ---- work units -----------------------------------------------------------------------------------------------------------
@@ -807,9 +870,9 @@ struct UnitArgs {
 
 // A unit covers 2^merge consecutive partitions. In the dense key order their
 // key ranges are consecutive, so together they index one direct-mapped table
-// of 2^(slot_bits + merge) <= kJSlots slots, which holds every dim key it can
-// meet: the chunk limit is the table size. Hash order: one partition, at most
-// kJChunk keys per chunk (table load <= 0.69).
+// of 2^(slot_bits + merge) <= kJSlots slots, and the unit reads its dim side
+// from the presence bitmap (one chunk, whatever the dim keys). Hash order: one
+// partition, at most kJChunk keys per chunk (table load <= 0.69).
 struct UnitShape {
   uint32_t merge, chunk;
 };
@@ -820,12 +883,15 @@ __device__ __forceinline__ UnitShape unit_shape(const KeyMap* km) {
 struct UnitGroup {
   uint32_t fc, dc, fs, ds;  // fact rows, dim keys and their first positions
 };
-__device__ __forceinline__ UnitGroup unit_group(const UnitArgs& a, uint32_t q, uint32_t merge) {
+// Dense order: the dim side has no second level, so a unit's dim "range" is
+// its own index (the groupjoin reads the unit's positions from the presence
+// bitmap) and every unit with fact rows is live.
+__device__ __forceinline__ UnitGroup unit_group(const UnitArgs& a, uint32_t q, uint32_t merge, bool dense) {
   const uint32_t p0 = q << merge, p1 = p0 + (1u << merge);
-  UnitGroup g{0u, 0u, a.fstart[p0], a.dstart[p0]};
+  UnitGroup g{0u, dense ? 1u : 0u, a.fstart[p0], dense ? q : a.dstart[p0]};
   for (uint32_t p = p0; p < p1; ++p) {
     g.fc += a.fcount[p];
-    g.dc += a.dcount[p];
+    if (!dense) g.dc += a.dcount[p];
   }
   return g;
 }
@@ -837,7 +903,7 @@ __global__ __launch_bounds__(kUBlk) void k_unit_count(UnitArgs a) {
   const UnitShape us = unit_shape(a.km);
   const uint32_t ngroups = a.nparts >> us.merge;
   const uint32_t q = blockIdx.x * kUBlk + threadIdx.x;
-  const UnitGroup g = q < ngroups ? unit_group(a, q, us.merge) : UnitGroup{0u, 0u, 0u, 0u};
+  const UnitGroup g = q < ngroups ? unit_group(a, q, us.merge, a.km->dense != 0) : UnitGroup{0u, 0u, 0u, 0u};
   const uint32_t fc = g.fc, dc = g.dc;
   const uint64_t mean4 = 4 * (uint64_t)*a.rows_passed / ngroups;
   const uint32_t thr = mean4 > kSplitMin ? (uint32_t)(mean4 < 0xffffffffull ? mean4 : 0xffffffffull) : kSplitMin;
@@ -896,7 +962,7 @@ __global__ __launch_bounds__(kUBlk) void k_unit_emit(UnitArgs a) {
   const UnitShape us = unit_shape(a.km);
   const uint32_t q = blockIdx.x * kUBlk + threadIdx.x;
   const bool in = q < (a.nparts >> us.merge);
-  const UnitGroup g = in ? unit_group(a, q, us.merge) : UnitGroup{0u, 0u, 0u, 0u};
+  const UnitGroup g = in ? unit_group(a, q, us.merge, a.km->dense != 0) : UnitGroup{0u, 0u, 0u, 0u};
   const uint32_t fc = g.fc, dc = g.dc, ds = g.ds, fs = g.fs, sb = in ? a.sbase[q] : kNoSplit;
   const bool live = fc != 0 && dc != 0;
   const bool splitp = sb != kNoSplit;
@@ -948,13 +1014,14 @@ struct JoinArgs {
   int64_t out_cap;
   int64_t* d_n;
   const KeyMap* km;
+  const uint32_t* bitmap;  // dense order: the dim keys' presence bits over all key positions
   uint32_t zero;  // 0 at run time; see take_ticket
 };
 
 constexpr uint64_t kLdsEmpty = ~0ull;
 constexpr int kJR = 4;                                   // fact rows per thread per step (dim-attribute kernels)
 constexpr int kGR = 4;                                   // fact rows per thread per step (groupjoin)
-constexpr int kJDK = kJSlots / kJBlock;                  // dim keys per thread (a dense unit fills the table)
+constexpr int kJDK = (kJChunk + kJBlock - 1) / kJBlock;  // dim keys per thread
 constexpr int kJPer = kJSlots / kJBlock;                 // LDS slots per thread at emission
 
 // An offset of zero that the compiler cannot prove uniform (zero is a
@@ -1079,32 +1146,14 @@ __device__ __forceinline__ void check_later_chunks(const uint64_t* tkey, const i
   }
 }
 
-// The same for a direct-mapped (dense order) table: a later chunk's key is
-// repeated when a dim key of this unit owns its slot.
-template <int NT>
-__device__ __forceinline__ void check_later_chunks_dense(const uint32_t* own, const int32_t* dkey, uint32_t from,
-                                                         uint32_t to, uint32_t sub, uint32_t mul, uint32_t mask,
-                                                         uint32_t* status) {
-  for (uint32_t j = from + threadIdx.x; j < to; j += NT) {
-    const uint32_t h = (((uint32_t)dkey[j] - sub) * mul) & mask;
-    if ((own[h >> 5] >> (h & 31)) & 1u) set_status(status, kDevDupKey);
-  }
-}
 
 // A slot is one 64-bit word {key, count}: the key in the low half, the rows
 // matched so far in the high half (for a sub-unit of a split chunk, the key's
 // position in its chunk sits above bit kPosShift of that half: sub-units have
 // at most kSubRows rows); all ones = empty. 48 KB of LDS per workgroup, so
-// three 256-thread workgroups fit on a CU.
-//
-// DENSE (the partitions follow the dense key order): the table is direct-
-// mapped, slot = the key's slot bits, with a 32-bit count per slot and a
-// bitmap of the slots the unit's dim keys own (which finds a repeated key);
-// a fact row needs no probe and no compare, only a range check. Emission
-// walks the unit's dim keys rather than the slots, so the slots no dim key
-// owns are never read (their counts and sums are reset when a dim key takes
-// them). One kernel holds the code of both orders and takes
-// the one the key map names (a branch on one word, uniform over the grid).
+// three 256-thread workgroups fit on a CU. (The dense key order's units are
+// in groupjoin_dense below; one kernel holds both and takes the one the key
+// map names, a branch on one word that is uniform over the grid.)
 constexpr uint32_t kPosShift = 20;
 
 // The groupjoin's LDS, shared by both key orders' code (one kernel holds both).
@@ -1128,24 +1177,13 @@ struct GroupjoinLds {
   uint64_t s_matched[kJBlock / kWave];
 };
 
-template <bool DENSE>
+// The groupjoin in the hash order.
 __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds& sh) {
-  uint32_t dsub = 0, dmul = 0, dmask = 0, drange = 0;
-  if (DENSE) {
-    dsub = a.km->sub;
-    dmul = a.km->mul;
-    dmask = (1u << (a.km->slot_bits + a.km->merge)) - 1;
-    drange = a.km->range;
-  }
-  auto dslot = [&](int32_t key) { return (((uint32_t)key - dsub) * dmul) & dmask; };
   uint64_t* const tkc = sh.t.tkc;
-  uint32_t* const dcnt = sh.t.d.cnt;
-  uint32_t* const down = sh.t.d.own;
   uint64_t* const tsp = sh.tsp;
   uint64_t* const tsq = sh.tsq;
   uint32_t* const scr = sh.scr;
   auto& s_wk = sh.s_wk;
-  static_assert(kJDK <= kJPer, "dense emission rounds share s_wk");
   uint64_t& s_excl = sh.s_excl;
   uint4& s_desc = sh.s_desc;
   uint2& s_split = sh.s_split;
@@ -1173,11 +1211,7 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
   // The table starts empty once; after that each unit's emission leaves the
   // slots it read empty again, and an insert zeroes its slot's sums, so no
   // unit spends a phase and a barrier clearing it.
-  if (DENSE) {
-    for (int s = tid; s < kJSlots / 32; s += kJBlock) down[s] = 0u;
-  } else {
-    for (int s = tid; s < kJSlots; s += kJBlock) tkc[s] = kLdsEmpty;
-  }
+  for (int s = tid; s < kJSlots; s += kJBlock) tkc[s] = kLdsEmpty;
   __syncthreads();
   int64_t u = s_u;
   uint4 d = s_desc;
@@ -1202,17 +1236,7 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
     // always exists. Every key's first compare-and-swap is issued before any
     // result is examined (one LDS round trip for most keys); keys whose home
     // slot was taken walk on one slot at a time.
-    if constexpr (DENSE) {
-#pragma unroll
-      for (int k = 0; k < kJDK; ++k) {
-        if (dlo + tid + k * kJBlock >= dhi) continue;
-        const uint32_t h = dslot(dkeys[k]), bit = 1u << (h & 31);
-        if (atomicOr(&down[h >> 5], bit) & bit) set_status(a.status, kDevDupKey);  // the slot's key came twice
-        dcnt[h] = 0;
-        tsp[h] = 0;
-        tsq[h] = 0;
-      }
-    } else {
+    {
       uint32_t h[kJDK];
       uint64_t old[kJDK];
 #pragma unroll
@@ -1249,10 +1273,7 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
       }
     }
     __syncthreads();
-    if (sp.x == 0 && sp.y > dhi) {
-      if (DENSE) check_later_chunks_dense<kJBlock>(down, a.dkey, dhi, sp.y, dsub, dmul, dmask, a.status);
-      else check_later_chunks<kJBlock>(tkc, a.dkey, dhi, sp.y, a.status);
-    }
+    if (sp.x == 0 && sp.y > dhi) check_later_chunks<kJBlock>(tkc, a.dkey, dhi, sp.y, a.status);
     int32_t ndkeys[kJDK];
     // probe and aggregate in LDS; long units stream further steps through nxt
     const uint32_t nrows = fhi - flo;
@@ -1276,16 +1297,7 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
       // the finds.
       bool fnd[kGR];
       int slt[kGR];
-      if constexpr (DENSE) {
-        // every row in the key range has its slot (whether a dim key owns it
-        // is read at emission)
-#pragma unroll
-        for (int k = 0; k < kGR; ++k) {
-          const uint32_t off = (uint32_t)ck.key[k] - dsub;
-          fnd[k] = i0 + k * kJBlock < fhi && off < drange;
-          slt[k] = (int)((off * dmul) & dmask);
-        }
-      } else {
+      {
         uint64_t c[kGR];
 #pragma unroll
         for (int k = 0; k < kGR; ++k) {
@@ -1314,7 +1326,7 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
       for (int k = 0; k < kGR; ++k) {
         bool found = fnd[k];
         const int slot = slt[k];
-        if (!DENSE) matched += found;
+        matched += found;
         // Hot keys: when many lanes of the wave hit one slot, pre-sum them so the
         // LDS sees one update instead of a serialised run of same-address atomics.
         // Only sub-units of split chunks check: the hottest keys are what makes
@@ -1332,8 +1344,7 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
           if ((int)lane == first) {
             atomicAdd((unsigned long long*)&tsp[s0], (unsigned long long)tsum_p);
             atomicAdd((unsigned long long*)&tsq[s0], (unsigned long long)tsum_q);
-            if (DENSE) atomicAdd(&dcnt[s0], (uint32_t)__popcll(same));
-            else atomicAdd((unsigned long long*)&tkc[s0], (unsigned long long)__popcll(same) << 32);
+            atomicAdd((unsigned long long*)&tkc[s0], (unsigned long long)__popcll(same) << 32);
           }
           found = found && !mine;
         }
@@ -1341,8 +1352,7 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
         if (found) {
           atomicAdd((unsigned long long*)&tsp[slot], (unsigned long long)pay.sp[k]);
           atomicAdd((unsigned long long*)&tsq[slot], (unsigned long long)(int64_t)pay.qty[k]);
-          if (DENSE) atomicAdd(&dcnt[slot], 1u);
-          else atomicAdd((unsigned long long*)&tkc[slot], 1ull << 32);
+          atomicAdd((unsigned long long*)&tkc[slot], 1ull << 32);
         }
       }
     }
@@ -1355,7 +1365,6 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
     const int64_t un = s_u;
     const uint4 dn = s_desc;
     const uint2 sn = s_split;
-    if (DENSE && tid < kJSlots / 32) down[tid] = 0u;  // for the next unit's build
     // past the last unit the loads read the current unit again (discarded)
     const uint4 pd = un < n_units ? dn : d;
     if (sp.x == 0) {
@@ -1365,21 +1374,15 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
       // thread 0 waits for it. Slots go out in round-major order (round k
       // holds slots k * kJBlock + thread), so each wave's stores of a round
       // land on consecutive output rows.
-      // (DENSE: round k holds the thread's k-th dim key)
-      constexpr int kRounds = DENSE ? kJDK : kJPer;
+      constexpr int kRounds = kJPer;
       uint32_t occ[kRounds];
       uint64_t bal[kRounds];
       int sl[kRounds];
 #pragma unroll
       for (int k = 0; k < kRounds; ++k) {
-        if constexpr (DENSE) {
-          sl[k] = (int)dslot(dkeys[k]);
-          occ[k] = dlo + tid + k * kJBlock < dhi ? dcnt[sl[k]] : 0u;
-        } else {
-          sl[k] = k * kJBlock + tid;
-          const uint64_t c = tkc[sl[k]];
-          occ[k] = c == kLdsEmpty ? 0u : (uint32_t)(c >> 32);
-        }
+        sl[k] = k * kJBlock + tid;
+        const uint64_t c = tkc[sl[k]];
+        occ[k] = c == kLdsEmpty ? 0u : (uint32_t)(c >> 32);
         bal[k] = wave_ballot(occ[k] != 0);
         if (lane == 0) s_wk[k][wave] = (uint32_t)__popcll(bal[k]);
       }
@@ -1403,31 +1406,14 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
       for (int k = 0; k < kRounds; ++k) {
         const int s = sl[k];
         if (occ[k] != 0)
-          put_group(a, o0 + base[k] + mask_rank(bal[k]), DENSE ? (int64_t)dkeys[k] : (int64_t)(int32_t)(uint32_t)tkc[s],
-                    tsp[s], tsq[s], occ[k]);
-        if constexpr (DENSE) matched += occ[k];
-        else tkc[s] = kLdsEmpty;
+          put_group(a, o0 + base[k] + mask_rank(bal[k]), (int64_t)(int32_t)(uint32_t)tkc[s], tsp[s], tsq[s], occ[k]);
+        tkc[s] = kLdsEmpty;
       }
     } else {
       // Sub-unit of a split chunk: add the partial sums into the chunk's
       // accumulator; the last sub-unit to finish emits and clears it.
       prefetch_unit(a, pd, ndkeys, nk, npay);
       SplitAcc* acc = a.split_acc + (size_t)(sp.x - 1) * kJSlots;
-      if constexpr (DENSE) {
-#pragma unroll
-        for (int k = 0; k < kJDK; ++k) {
-          const uint32_t pos = tid + k * kJBlock;
-          if (dlo + pos >= dhi) continue;
-          const uint32_t h = dslot(dkeys[k]);
-          const uint32_t c = dcnt[h];
-          matched += c;
-          if (c == 0) continue;
-          SplitAcc* e = acc + pos;
-          dev_add<uint64_t>(&e->sp, tsp[h]);
-          dev_add<uint64_t>(&e->sq, tsq[h]);
-          dev_add<uint64_t>(&e->cnt, (uint64_t)c);
-        }
-      } else {
 #pragma unroll
       for (int k = 0; k < kJPer; ++k) {
         const int s = tid * kJPer + k;
@@ -1440,7 +1426,6 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
         dev_add<uint64_t>(&e->sp, tsp[s]);
         dev_add<uint64_t>(&e->sq, tsq[s]);
         dev_add<uint64_t>(&e->cnt, (uint64_t)c);
-      }
       }
       __threadfence();
       __syncthreads();
@@ -1484,10 +1469,243 @@ __device__ __forceinline__ void groupjoin_units(const JoinArgs& a, GroupjoinLds&
   if (threadIdx.x == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
 }
 
+// The groupjoin in the dense key order. A unit is 2^ubits consecutive key
+// positions (ubits = slot bits + merge <= kJSlotBits) and slot s of its
+// direct-mapped table is position (unit << ubits) | s; the dim side gives
+// only the unit's bitmap words (which positions hold a dim key), so a unit
+// loads one word per 32 slots instead of its dim keys, and emission walks the
+// slots, computing each group's key back from its position (key = kmin +
+// position * mul^-1 mod 2^L). Counts and sums of every slot start at zero and
+// emission leaves them so; fact rows outside the key range match nothing and
+// are skipped, rows at a position no dim key holds are counted into its slot
+// and never emitted. Otherwise the unit loop is the hash order's below
+// (prefetch, tickets, reservation, split sub-units).
+__device__ __forceinline__ void groupjoin_dense(const JoinArgs& a, GroupjoinLds& sh) {
+  const uint32_t sub = a.km->sub, mul = a.km->mul, inv = a.km->inv, range = a.km->range;
+  const uint32_t ubits = a.km->slot_bits + a.km->merge, L = a.km->lbits;
+  const uint32_t lmask = L >= 32 ? ~0u : (1u << L) - 1u;
+  const uint32_t nslots = 1u << ubits, smask = nslots - 1u;
+  const uint32_t nw = ubits >= 5 ? nslots >> 5 : 1u;  // bitmap words of a unit
+  uint32_t* const cnt = sh.t.d.cnt;
+  uint32_t* const own = sh.t.d.own;
+  uint64_t* const tsp = sh.tsp;
+  uint64_t* const tsq = sh.tsq;
+  uint32_t* const scr = sh.scr;
+  auto& s_wk = sh.s_wk;
+  uint64_t& s_excl = sh.s_excl;
+  uint4& s_desc = sh.s_desc;
+  uint2& s_split = sh.s_split;
+  int64_t& s_u = sh.s_u;
+  uint32_t& s_last = sh.s_last;
+  const int64_t n_units = *a.n_units;
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  uint64_t matched = 0;
+  int64_t t_ahead = 0;  // thread 0: the next unit
+  int64_t seq = blockIdx.x;
+  if (tid == 0) {
+    const int64_t t = blockIdx.x;
+    t_ahead = take_ticket(a, seq);
+    s_u = t;
+    if (t < n_units) {
+      s_desc = a.unit_desc[t];
+      s_split = a.unit_split[t];
+    }
+  }
+  for (int s = tid; s < kJSlots; s += kJBlock) {
+    cnt[s] = 0u;
+    tsp[s] = 0;
+    tsq[s] = 0;
+  }
+  __syncthreads();
+  int64_t u = s_u;
+  uint4 d = s_desc;
+  uint2 sp = s_split;
+  uint32_t own_w = 0;  // threads < nw: a bitmap word of the unit (then of the next unit)
+  KeyRegs ck, nk;
+  PayRegs pay, npay;
+  // a unit's bitmap words and its first step of fact rows (d.x is the unit's index)
+  auto prefetch = [&](uint4 x) {
+    if (tid < nw) own_w = a.bitmap[((x.x << ubits) >> 5) + tid];
+    load_keys(a, x.z + tid, x.w, nk);
+    load_payload(a, x.z + tid, x.w, npay);
+  };
+  if (u < n_units) prefetch(d);
+  while (u < n_units) {
+    const uint32_t kbase = d.x << ubits, flo = d.z, fhi = d.w;
+    int64_t t_req = 0;
+    uint4 nd = make_uint4(0, 0, 0, 0);
+    uint2 ns = make_uint2(0, 0);
+    if (tid == 0) {
+      if (t_ahead < n_units) {
+        nd = a.unit_desc[t_ahead];
+        ns = a.unit_split[t_ahead];
+      }
+      t_req = take_ticket(a, seq);
+    }
+    if (tid < nw) own[tid] = own_w;
+    // Every thread has read s_u, s_desc and s_split for this unit before
+    // thread 0 overwrites them at the end of the probe.
+    __syncthreads();
+    const uint32_t nrows = fhi - flo;
+    const uint32_t iters = (nrows + kGR * kJBlock - 1) / (kGR * kJBlock);
+    const bool combine = sp.x != 0;
+    for (uint32_t it = 0; it < iters; ++it) {
+      const uint32_t i0 = flo + it * (kGR * kJBlock) + tid;
+      ck = nk;
+      pay = npay;
+      if (it + 1 < iters) {  // the next step's rows travel during this step's updates
+        load_keys(a, i0 + kGR * kJBlock, fhi, nk);
+        load_payload(a, i0 + kGR * kJBlock, fhi, npay);
+      }
+#pragma unroll
+      for (int k = 0; k < kGR; ++k) {
+        const uint32_t off = (uint32_t)ck.key[k] - sub;
+        bool found = i0 + k * kJBlock < fhi && off < range;
+        const int slot = (int)((off * mul) & smask);
+        // hot keys (split sub-units): lanes of the wave on one slot are summed first
+        if (combine) {
+          const uint64_t act = wave_ballot(found);
+          if (act == 0) continue;
+          const int first = __ffsll((long long)act) - 1;
+          const int s0 = __shfl(slot, first, kWave);
+          const uint64_t same = wave_ballot(found && slot == s0);
+          if (__popcll(same) >= kCombineMin) {
+            const bool mine = found && slot == s0;
+            const uint64_t tsum_p = wave_sum_u64(mine ? pay.sp[k] : 0);
+            const uint64_t tsum_q = wave_sum_u64(mine ? (uint64_t)(int64_t)pay.qty[k] : 0);
+            if ((int)lane == first) {
+              atomicAdd((unsigned long long*)&tsp[s0], (unsigned long long)tsum_p);
+              atomicAdd((unsigned long long*)&tsq[s0], (unsigned long long)tsum_q);
+              atomicAdd(&cnt[s0], (uint32_t)__popcll(same));
+            }
+            found = found && !mine;
+          }
+        }
+        if (found) {
+          atomicAdd((unsigned long long*)&tsp[slot], (unsigned long long)pay.sp[k]);
+          atomicAdd((unsigned long long*)&tsq[slot], (unsigned long long)(int64_t)pay.qty[k]);
+          atomicAdd(&cnt[slot], 1u);
+        }
+      }
+    }
+    if (tid == 0) {  // the next unit, read by everyone after the barrier
+      s_u = t_ahead;
+      s_desc = nd;
+      s_split = ns;
+    }
+    __syncthreads();
+    const int64_t un = s_u;
+    const uint4 dn = s_desc;
+    const uint2 sn = s_split;
+    const uint4 pd = un < n_units ? dn : d;  // past the last unit the loads read this one again (discarded)
+    // whether a dim key holds slot s of this unit
+    auto owned = [&](uint32_t s) {
+      const uint32_t g = kbase | s;
+      return s < nslots && ((own[(g >> 5) - (kbase >> 5)] >> (g & 31)) & 1u) != 0u;
+    };
+    auto key_at = [&](uint32_t s) { return (int64_t)(int32_t)(sub + ((((kbase | s) * inv)) & lmask)); };
+    if (sp.x == 0) {
+      // Whole unit: emit its owned slots with rows, round k holding slots k * kJBlock + thread.
+      uint32_t occ[kJPer];
+      uint64_t bal[kJPer];
+#pragma unroll
+      for (int k = 0; k < kJPer; ++k) {
+        const uint32_t s = k * kJBlock + tid;
+        occ[k] = owned(s) ? cnt[s] : 0u;
+        bal[k] = wave_ballot(occ[k] != 0);
+        if (lane == 0) s_wk[k][wave] = (uint32_t)__popcll(bal[k]);
+      }
+      __syncthreads();
+      uint32_t total = 0, base[kJPer];
+#pragma unroll
+      for (int k = 0; k < kJPer; ++k) {
+#pragma unroll
+        for (int w = 0; w < kJBlock / kWave; ++w) {
+          if (w == (int)wave) base[k] = total;
+          total += s_wk[k][w];
+        }
+      }
+      int64_t resv = 0;
+      if (tid == 0 && total) resv = reserve_nowait(a, total);
+      prefetch(pd);
+      if (tid == 0) s_excl = (uint64_t)resv;
+      __syncthreads();
+      const int64_t o0 = (int64_t)s_excl;
+#pragma unroll
+      for (int k = 0; k < kJPer; ++k) {
+        const uint32_t s = k * kJBlock + tid;
+        if (occ[k] != 0) put_group(a, o0 + base[k] + mask_rank(bal[k]), key_at(s), tsp[s], tsq[s], occ[k]);
+        matched += occ[k];
+        if (s < nslots) {
+          cnt[s] = 0u;
+          tsp[s] = 0;
+          tsq[s] = 0;
+        }
+      }
+    } else {
+      // Sub-unit of a split unit: partial sums into the unit's accumulator
+      // (one entry per slot); the last sub-unit to finish emits and clears it.
+      prefetch(pd);
+      SplitAcc* acc = a.split_acc + (size_t)(sp.x - 1) * kJSlots;
+#pragma unroll
+      for (int k = 0; k < kJPer; ++k) {
+        const uint32_t s = k * kJBlock + tid;
+        if (s >= nslots) continue;
+        const uint32_t c = owned(s) ? cnt[s] : 0u;
+        if (c != 0) {
+          matched += c;
+          dev_add<uint64_t>(&acc[s].sp, tsp[s]);
+          dev_add<uint64_t>(&acc[s].sq, tsq[s]);
+          dev_add<uint64_t>(&acc[s].cnt, (uint64_t)c);
+        }
+        cnt[s] = 0u;
+        tsp[s] = 0;
+        tsq[s] = 0;
+      }
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) s_last = dev_add_ret<uint32_t>(&a.split_done[sp.x - 1], 1u) + 1 == sp.y;
+      __syncthreads();
+      if (s_last) {
+        __threadfence();
+        uint32_t vc[kJPer];
+        uint32_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < kJPer; ++k) {
+          const uint32_t s = k * kJBlock + tid;
+          vc[k] = s < nslots ? (uint32_t)__hip_atomic_load(&acc[s].cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+          mine += vc[k] != 0;
+        }
+        if (tid == 0) a.split_done[sp.x - 1] = 0;
+        int64_t o = reserve_out(a, mine, scr, &s_excl);
+#pragma unroll
+        for (int k = 0; k < kJPer; ++k) {
+          if (vc[k] == 0) continue;
+          const uint32_t s = k * kJBlock + tid;
+          SplitAcc* e = acc + s;
+          const uint64_t vp = __hip_atomic_load(&e->sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const uint64_t vq = __hip_atomic_load(&e->sq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          put_group(a, o++, key_at(s), vp, vq, vc[k]);
+          e->sp = 0;
+          e->sq = 0;
+          e->cnt = 0;
+        }
+      }
+    }
+    __syncthreads();  // the table, s_excl and s_last are reused by the next unit
+    t_ahead = t_req;
+    u = un;
+    d = dn;
+    sp = sn;
+  }
+  matched = block_sum_u64<kJBlock>(matched, sh.s_matched);
+  if (threadIdx.x == 0 && matched) dev_add<unsigned long long>((unsigned long long*)a.matched, (unsigned long long)matched);
+}
+
 __global__ __launch_bounds__(kJBlock, 3) void k_part_groupjoin(JoinArgs a) {
   __shared__ GroupjoinLds sh;
-  if (a.km->dense != 0) groupjoin_units<true>(a, sh);
-  else groupjoin_units<false>(a, sh);
+  if (a.km->dense != 0) groupjoin_dense(a, sh);
+  else groupjoin_units(a, sh);
 }
 
 // ---- partitioned join + aggregate ------------------------------------------------------------------------------------
@@ -2017,6 +2235,7 @@ struct Partitioned {
   int64_t* ticket;
   void* split_scratch;
   uint32_t* split_done;
+  uint32_t* bitmap;  // dense order (GROUP BY fk): the dim keys' presence bits
 };
 
 // dense_ok: the key order may be the dense one (GROUP BY fk), decided on the
@@ -2039,7 +2258,10 @@ rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim
   const size_t fact_bytes = (size_t)(n > 0 ? n : 1) * 17 + 4 * 256;  // fk, qty, price, flag
   TRY(scratch(ctx, SCR_PART_A, fact_bytes, &pa));
   TRY(scratch(ctx, SCR_PART_B, fact_bytes, &pb));
-  TRY(scratch(ctx, SCR_PART_C, (size_t)(m > 0 ? m : 1) * 16 + 4 * 256, &pc));
+  // dim copies, and (GROUP BY fk) the presence bitmap of the dense order: at
+  // most 2^(P + 11) key positions, one bit each
+  const size_t bitmap_bytes = dense_ok ? ((size_t)1 << (b1 + b2 + kJSlotBits)) / 8 + 256 : 0;
+  TRY(scratch(ctx, SCR_PART_C, (size_t)(m > 0 ? m : 1) * 16 + 4 * 256 + bitmap_bytes, &pc));
   const size_t book = ((size_t)fnt1 * nb1 + (size_t)dnt1 * nb1 + (size_t)fnt2 * nb2 + (size_t)dnt2 * nb2 + 2 * nb1 +
                        5 * (size_t)nparts + ((size_t)nparts / kUBlk + 1) * kClasses) * 4 +
                       (size_t)max_units * (sizeof(uint4) + sizeof(uint2)) + (size_t)(fnt2 + dnt2) * sizeof(uint4) +
@@ -2094,6 +2316,8 @@ rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim
   D.pay1 = cc.take<int32_t>(m);
   D.key2 = cc.take<int32_t>(m);
   D.pay2 = cc.take<int32_t>(m);
+  uint32_t* bitmap = dense_ok ? cc.take<uint32_t>(bitmap_bytes / 4) : nullptr;
+  D.dense_stop = dense_ok ? 1u : 0u;
   D.hist1 = cd.take<uint32_t>((size_t)dnt1 * nb1);
   D.tot1 = cd.take<uint32_t>(nb1);
   D.hist2 = cd.take<uint32_t>((size_t)dnt2 * nb2);
@@ -2126,7 +2350,17 @@ rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim
   {
     hipStream_t main = ctx->stream;
     ctx->stream = ctx->aux;
-    const rel_status sd = partition_side(ctx, D, false, nullptr);
+    rel_status sd = partition_side(ctx, D, false, nullptr);
+    if (sd == REL_OK && dense_ok) {
+      // dense order: the presence bitmap instead of the dim side's second level
+      KernelTimer kt(ctx, "dim_bitmap");
+      const uint32_t pbw_max = b1 + b2 + kJSlotBits - b1;
+      const size_t lds = std::max<size_t>(((size_t)1 << pbw_max) / 8, 256);
+      if (lds > 32768)  // past the default dynamic LDS limit (at most 64 KB: 2^19 positions per partition)
+        (void)hipFuncSetAttribute((const void*)k_dim_bitmap, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(k_dim_bitmap, dim3(1u << b1), dim3(kBmBlock), lds, ctx->stream, D, bitmap, ctx->d_status);
+      if (hipGetLastError() != hipSuccess) sd = fail(ctx, REL_HIP, "dim_bitmap launch");
+    }
     ctx->stream = main;
     if (sd != REL_OK) return sd;
   }
@@ -2170,6 +2404,7 @@ rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim
   P->ticket = counters + CNT_TICKET;
   P->split_scratch = pe;
   P->split_done = split_done;
+  P->bitmap = bitmap;
   return REL_OK;
 }
 
@@ -2201,6 +2436,7 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   a.out_cap = out->cap;
   a.d_n = out->d_n_groups;
   a.km = P.F.km;
+  a.bitmap = P.bitmap;
   const unsigned grid = (unsigned)ctx->num_cus * 3;  // 48 KB of LDS each: three per CU
   hipLaunchKernelGGL(k_part_groupjoin, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
   REL_LAUNCH_CHECK(ctx, "part_groupjoin");
