@@ -334,6 +334,20 @@ def test_partitioned_key_layouts(ctx, layout):
     assert st["join_placement"] == "partitioned"
 
 
+def test_partitioned_dense_order_widest_partitions(ctx):
+    # 33M dim keys at stride 4 (a range of 2^27 less a little): the deepest
+    # partitioning (16 bits over two levels of 8) with the widest dense order
+    # (2^11 key positions per final partition, 2^19 per first-level partition),
+    # so the presence bitmap's kernel fills the largest LDS block it asks for.
+    m = 33_000_000
+    perm = datagen.permutation(m, 0, 91, 1).astype(np.int64)
+    T = datagen.make_tables(2_000_000, m, 92, day_lt=1500, group_by="fk", fk_zipf=0.7)
+    T.pk = (4 * perm + 5).astype(np.int32)
+    T.fk = T.pk[T.fk.astype(np.int64)]
+    st = run_both(ctx, T, plan=_partitioned())
+    assert st["join_placement"] == "partitioned"
+
+
 def test_partitioned_oversized_partition_is_chunked(ctx):
     # 3000 keys in one partition exceed one LDS chunk (1400 keys): the partition
     # is processed as several units that each see all of its fact rows.
