@@ -743,6 +743,7 @@ __global__ __launch_bounds__(kSBlk) void k_p2_scatter(PartSide s) {
 // positions; the dim side stops after its first level. With fewer than 32
 // positions per partition, one workgroup builds the whole (small) bitmap.
 constexpr int kBmBlock = 1024;
+constexpr int kBmRows = 8;  // keys per thread per step
 __global__ __launch_bounds__(kBmBlock) void k_dim_bitmap(PartSide s, uint32_t* __restrict__ bitmap,
                                                          uint32_t* __restrict__ status) {
   HIP_DYNAMIC_SHARED(uint32_t, lb)
@@ -777,9 +778,20 @@ __global__ __launch_bounds__(kBmBlock) void k_dim_bitmap(PartSide s, uint32_t* _
 #pragma unroll
   for (int w = 0; w < kBmBlock / kWave; ++w) start += s_red[w];
   const uint32_t cnt = s.tot1[p];
-  for (uint32_t j = tid; j < cnt; j += kBmBlock) {
-    const uint32_t kp = (((uint32_t)s.key1[(int64_t)start + j] - sub) * mul) & pmask, bit = 1u << (kp & 31);
-    if (atomicOr(&lb[kp >> 5], bit) & bit) set_status(status, kDevDupKey);
+  const int32_t* const keys = s.key1 + start;
+  for (uint32_t j0 = tid; j0 < cnt; j0 += kBmBlock * kBmRows) {  // kBmRows keys in flight per thread
+    int32_t kv[kBmRows];
+#pragma unroll
+    for (int r = 0; r < kBmRows; ++r) {
+      const uint32_t j = j0 + r * kBmBlock;
+      kv[r] = j < cnt ? keys[j] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kBmRows; ++r) {
+      if (j0 + r * kBmBlock >= cnt) break;
+      const uint32_t kp = (((uint32_t)kv[r] - sub) * mul) & pmask, bit = 1u << (kp & 31);
+      if (atomicOr(&lb[kp >> 5], bit) & bit) set_status(status, kDevDupKey);
+    }
   }
   __syncthreads();
   for (uint32_t w = tid; w < nw; w += kBmBlock) bitmap[(size_t)p * nw + w] = lb[w];

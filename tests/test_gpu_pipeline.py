@@ -304,11 +304,27 @@ def _same_partition_keys(count: int, top16: int) -> np.ndarray:
     return ((h * np.uint64(inv)) & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.int32)
 
 
+# (3M, 2000): a single groupjoin unit that takes all 1.4M fact rows that pass.
 @pytest.mark.parametrize("n,m,zipf", [(1, 1, 0.0), (1000, 17, 0.0), (100_003, 25_001, 0.0), (2_000_000, 500_000, 1.2),
-                                      (3_000_000, 700_000, 0.8)])
+                                      (3_000_000, 700_000, 0.8), (3_000_000, 2000, 0.0)])
 def test_partitioned_groupjoin(ctx, n, m, zipf):
     T = datagen.make_tables(n, m, 500 + n, day_lt=1200, group_by="fk", fk_zipf=zipf, fk_domain=m + m // 5)
     st = run_both(ctx, T, plan=_partitioned(), repeats=2)
+    assert st["join_placement"] == "partitioned"
+
+
+@pytest.mark.parametrize("n,m,zipf", [(2_000_000, 200_000, 1.1), (3_000_000, 2000, 0.0)])
+def test_partitioned_extreme_quantities(ctx, n, m, zipf):
+    # Quantities over the whole int32 range, a third of them at its ends: the
+    # per-group quantity sums reach about rows x 2^31 in either sign, in
+    # split sub-units (Zipf 1.1) and in one unit of 1.8M rows (2000 dim keys).
+    T = datagen.make_tables(n, m, 700 + m, day_lt=1500, group_by="fk", fk_zipf=zipf)
+    rng = np.random.default_rng(m)
+    q = rng.integers(-(2 ** 31), 2 ** 31, size=n, dtype=np.int64)
+    ends = rng.random(n)
+    q = np.where(ends < 1 / 6, -(2 ** 31), np.where(ends < 1 / 3, 2 ** 31 - 1, q))
+    T.qty = q.astype(np.int32)
+    st = run_both(ctx, T, plan=_partitioned())
     assert st["join_placement"] == "partitioned"
 
 
