@@ -152,6 +152,7 @@ struct PartSide {
   // bookkeeping
   uint32_t* hist1;   // [ntiles1][nb1]
   uint32_t* tot1;    // [nb1]
+  uint32_t* pass1;   // fact only: bit r of word r / 32 set when row r passes the filter (the histogram writes it)
   uint32_t* hist2;   // [max tiles2][nb2]
   uint32_t* pstart;  // [nb1 * nb2]
   uint32_t* pcount;  // [nb1 * nb2]
@@ -273,14 +274,37 @@ __global__ __launch_bounds__(kBlk) void k_p1_hist(PartSide s) {
     for (int k = 0; k < V; ++k) {
       const int32_t ks[4] = {kv[k].x, kv[k].y, kv[k].z, kv[k].w};
       const int32_t ds[4] = {dv[k].x, dv[k].y, dv[k].z, dv[k].w};
+      uint32_t nib = 0;  // this thread's four rows' pass bits
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (!FACT || ds[e] < s.day_lt) atomicAdd(&h[bin_of(ks[e])], 1u);
+        if (!FACT || ds[e] < s.day_lt) {
+          atomicAdd(&h[bin_of(ks[e])], 1u);
+          nib |= 1u << e;
+        }
+      if (FACT) {
+        // eight consecutive lanes hold the 32 rows of one word
+        uint32_t w = nib << (4 * (lane_id() & 7));
+        w |= (uint32_t)__shfl_xor((int)w, 1, kWave);
+        w |= (uint32_t)__shfl_xor((int)w, 2, kWave);
+        w |= (uint32_t)__shfl_xor((int)w, 4, kWave);
+        if ((lane_id() & 7) == 0) s.pass1[(r0 + 4 * (threadIdx.x + (int64_t)k * kBlk)) >> 5] = w;
+      }
     }
   } else {
     __syncthreads();
-    for (int64_t q = r0 + threadIdx.x; q < r1; q += kBlk)
-      if (row_passes<FACT>(s, q)) atomicAdd(&h[bin_of(s.key[q])], 1u);
+    // rows q .. q + 63 of a wave start on a multiple of 64 (tiles are multiples of 256 rows)
+    for (int64_t q0 = r0 + (threadIdx.x & ~(kWave - 1)); q0 < r1; q0 += kBlk) {
+      const int64_t q = q0 + lane_id();
+      const bool pass = q < r1 && row_passes<FACT>(s, q);
+      if (pass) atomicAdd(&h[bin_of(s.key[q])], 1u);
+      if (FACT) {
+        const uint64_t b = wave_ballot(pass);
+        if (lane_id() == 0) {
+          s.pass1[q0 >> 5] = (uint32_t)b;
+          if (q0 + 32 < r1) s.pass1[(q0 >> 5) + 1] = (uint32_t)(b >> 32);
+        }
+      }
+    }
   }
   __syncthreads();
   // bin-major [nb1][ntiles], so that each bin's column scan reads contiguously
@@ -357,15 +381,16 @@ struct Stage {
 };
 
 // The rows one thread holds for one tile. valid: bit k set when row k is in
-// range; with DAY (fact rows at the first level) the predicate on day[k] is
-// applied only when the rows are used, so a prefetched tile's loads are not
-// waited for early.
-template <bool FACT, bool DAY, int R>
+// range; with PASS (fact rows at the first level) the filter's outcome comes
+// from the pass bits that the histogram pass stored (one bit per row read
+// instead of the 4-byte day), applied only when the rows are used, so a
+// prefetched tile's loads are not waited for early.
+template <bool FACT, bool PASS, int R>
 struct TileRows {
   int32_t key[R];
   int32_t val[R];
   int64_t price[FACT ? R : 1];
-  int32_t day[DAY ? R : 1];
+  uint32_t pass[PASS ? R : 1];  // the word of pass bits that holds row k's (bit threadIdx.x % 32)
   uint32_t flags[FACT ? (R + 3) / 4 : 1];  // fact flag bytes, four per word (when carried)
   uint32_t valid;
 };
@@ -378,15 +403,15 @@ struct TileRows {
 // Callers write st.gbase before the call (it is read after the first barrier)
 // and clear st.lcnt once before the first tile. No barrier at the end: the
 // next tile's first barrier orders its scan after this tile's write-out.
-template <bool FACT, bool DAY, int NT, int TILE>
-__device__ __forceinline__ void stage_and_write(Stage<FACT, TILE>& st, TileRows<FACT, DAY, TILE / NT>& r, int32_t day_lt,
+template <bool FACT, bool PASS, int NT, int TILE>
+__device__ __forceinline__ void stage_and_write(Stage<FACT, TILE>& st, TileRows<FACT, PASS, TILE / NT>& r,
                                                 BinOf bin_of, uint32_t nb, bool with_val, int32_t* dkey,
                                                 int64_t* dprice, int32_t* dval, int8_t* dflag) {
   constexpr int R = TILE / NT;
-  if (DAY) {
+  if (PASS) {
 #pragma unroll
     for (int k = 0; k < R; ++k)
-      if (r.day[k] >= day_lt) r.valid &= ~(1u << k);
+      if (((r.pass[k] >> (threadIdx.x & 31)) & 1u) == 0) r.valid &= ~(1u << k);
   }
   uint32_t rank[R];
 #pragma unroll
@@ -457,7 +482,7 @@ __device__ __forceinline__ void load_p1_row(const PartSide& s, int64_t q, int k,
   if (FACT) {
     r.val[k] = ld_once(s.qty + q);
     r.price[k] = ld_once(s.price + q);
-    r.day[k] = ld_once(s.day + q);
+    r.pass[k] = s.pass1[q >> 5];  // q % 32 == threadIdx.x % 32
     if (s.flag) r.flags[k / 4] |= (uint32_t)(uint8_t)s.flag[q] << (8 * (k % 4));
   } else {
     r.val[k] = s.pkind == relh::PAY_ROW_ID ? (int32_t)q
@@ -497,7 +522,7 @@ __global__ __launch_bounds__(kSBlk) void k_p1_scatter(PartSide s) {
         r.val[k] = 0;
         if (FACT) {
           r.price[k] = 0;
-          r.day[k] = 0;
+          r.pass[k] = 0;
         }
       }
     }
@@ -509,7 +534,7 @@ __global__ __launch_bounds__(kSBlk) void k_p1_scatter(PartSide s) {
   if (threadIdx.x < kMaxBins) st.lcnt[threadIdx.x] = 0;
   if (threadIdx.x < nb1) st.gbase[threadIdx.x] = pbase + h;
   __syncthreads();
-  stage_and_write<FACT, FACT, kSBlk, (int)kTile1>(st, r, s.day_lt, bin_of, nb1, s.pkind != relh::PAY_NONE, s.key1,
+  stage_and_write<FACT, FACT, kSBlk, (int)kTile1>(st, r, bin_of, nb1, s.pkind != relh::PAY_NONE, s.key1,
                                                   s.price1, FACT ? s.qty1 : s.pay1, FACT ? s.flag1 : nullptr);
 }
 
@@ -730,7 +755,7 @@ __global__ __launch_bounds__(kSBlk) void k_p2_scatter(PartSide s) {
   if (threadIdx.x < kMaxBins) st.lcnt[threadIdx.x] = 0;
   if (threadIdx.x < nb2) st.gbase[threadIdx.x] = s.pstart[x.p * nb2 + threadIdx.x] + s.hist2[(size_t)t * nb2 + threadIdx.x];
   __syncthreads();
-  stage_and_write<FACT, false, kSBlk, (int)kTile>(st, r, 0, bin_of, nb2, pay, s.key2, s.price2, FACT ? s.qty2 : s.pay2,
+  stage_and_write<FACT, false, kSBlk, (int)kTile>(st, r, bin_of, nb2, pay, s.key2, s.price2, FACT ? s.qty2 : s.pay2,
                                                   FACT ? s.flag2 : nullptr);
 }
 
@@ -2277,7 +2302,7 @@ rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim
   const size_t book = ((size_t)fnt1 * nb1 + (size_t)dnt1 * nb1 + (size_t)fnt2 * nb2 + (size_t)dnt2 * nb2 + 2 * nb1 +
                        5 * (size_t)nparts + ((size_t)nparts / kUBlk + 1) * kClasses) * 4 +
                       (size_t)max_units * (sizeof(uint4) + sizeof(uint2)) + (size_t)(fnt2 + dnt2) * sizeof(uint4) +
-                      sizeof(KeyMap) + 8 * (size_t)kKeyMinMaxParts + 64 * 256;
+                      sizeof(KeyMap) + 8 * (size_t)kKeyMinMaxParts + ((size_t)n / 64 + 1) * 8 + 64 * 256;
   TRY(scratch(ctx, SCR_PART_D, book, &pd));
   // split-chunk accumulators and their done counters: zero when allocated, and
   // left zero by every call (the last sub-unit of a chunk clears what it emits)
@@ -2309,6 +2334,7 @@ rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim
   F.price2 = cb.take<int64_t>(n);
   F.flag2 = with_flag ? cb.take<int8_t>(n) : nullptr;
   F.hist1 = cd.take<uint32_t>((size_t)fnt1 * nb1);
+  F.pass1 = cd.take<uint32_t>(((size_t)n / 64 + 1) * 2);
   F.tot1 = cd.take<uint32_t>(nb1);
   F.hist2 = cd.take<uint32_t>((size_t)fnt2 * nb2);
   F.pstart = cd.take<uint32_t>(nparts);
