@@ -40,11 +40,30 @@ OUT_BYTES_PER_GROUP = 32  # key, SUM(price), SUM(qty), COUNT as int64
 PART_ROW_BYTES = 16  # a partitioned fact row: fk 4 + price 8 + qty 4
 
 
-def kernel_alg_bytes(kernel: str, n: int, m: int, r: int, g: int, group_by: str):
+def dense_positions(pk) -> int | None:
+    """Key positions of the partitioned groupjoin's dense key order for these
+    dim keys (2^L, L = max(partition bits, bits of the key range)), or None
+    when the keys take the hash order (a range wider than 2^11 x the
+    partition count). Partition bits as the library picks them: about 1000
+    dim keys per partition, 2 to 16 bits."""
+    m = int(pk.shape[0])
+    if m == 0:
+        return None
+    pb = 0
+    while pb < 16 and (m >> pb) > 1000:
+        pb += 1
+    pb = max(pb, 2)
+    span = int(pk.max()) - int(pk.min()) + 1
+    lb = max((span - 1).bit_length(), pb)
+    return 1 << lb if lb - pb <= 11 else None
+
+
+def kernel_alg_bytes(kernel: str, n: int, m: int, r: int, g: int, group_by: str, positions: int | None = None):
     """Algorithmic bytes of one launch of `kernel`: each input byte the kernel
     must read once plus each output byte it must write once (no table or
     re-read traffic). n fact rows, m dim rows, r rows passing the predicate,
-    g groups. Returns (bytes, description) or (None, None)."""
+    g groups; positions: the dense key order's key positions (None: hash
+    order). Returns (bytes, description) or (None, None)."""
     fb, db = FACT_BYTES[group_by], DIM_BYTES[group_by]
     # partitioned rows: fact 16 B (+1 flag byte when the key needs it); dim key
     # 4 B (+4 B payload when the group key comes from the dim side)
@@ -56,16 +75,20 @@ def kernel_alg_bytes(kernel: str, n: int, m: int, r: int, g: int, group_by: str)
         "join_build": (db * m, f"{db} B per dim row"),
         "finalize": (OUT_BYTES_PER_GROUP * g, "32 B per output group"),
         # radix-partitioned pipeline
-        "fact_p1_hist": (8 * n, "8 B per fact row (day, fk)"),
-        "fact_p1_scatter": (fb * n + pf * r, f"{fb} B per fact row read + {pf} B per passing row written"),
+        "fact_p1_hist": (8 * n + n / 8, "8 B per fact row read (day, fk) + its pass bit written"),
+        "fact_p1_scatter": ((fb - 4) * n + n / 8 + pf * r,
+                            f"{fb - 4} B per fact row read (all but day) + its pass bit + {pf} B per passing row written"),
         "fact_p2_hist": (4 * r, "4 B per passing row (fk)"),
         "fact_p2_scatter": (2 * pf * r, f"{pf} B per passing row read + {pf} B written"),
         "dim_p1_hist": (4 * m, "4 B per dim row"),
         "dim_p1_scatter": ((db + pd) * m, f"{db} B per dim row read + {pd} B written"),
         "dim_p2_hist": (4 * m, "4 B per dim row"),
         "dim_p2_scatter": (2 * pd * m, f"{pd} B per dim row read + {pd} B written"),
-        "part_groupjoin": (PART_ROW_BYTES * r + 4 * m + OUT_BYTES_PER_GROUP * g,
-                           "16 B per passing row + 4 B per dim key + 32 B per group"),
+        "part_groupjoin": ((PART_ROW_BYTES * r + positions / 8 + OUT_BYTES_PER_GROUP * g,
+                            "16 B per passing row + 1 bit per key position (presence bitmap) + 32 B per group")
+                           if positions else
+                           (PART_ROW_BYTES * r + 4 * m + OUT_BYTES_PER_GROUP * g,
+                            "16 B per passing row + 4 B per dim key + 32 B per group")),
         "part_join_agg": (pf * r + pd * m, f"{pf} B per passing row + {pd} B per dim row (key, payload)"),
     }
     return table.get(kernel, (None, None))
@@ -786,12 +809,13 @@ def main() -> int:
     dom_name, (dom_tot, dom_cnt) = dom
     dom_ms = dom_tot / max(dom_cnt, 1)
     r, g = st["rows_passed"], st["groups"]
-    alg_bytes, unit_desc = kernel_alg_bytes(dom_name, n, m, r, g, T.group_by)
+    positions = dense_positions(T.pk) if st.get("join_placement") == "partitioned" and T.group_by == "fk" else None
+    alg_bytes, unit_desc = kernel_alg_bytes(dom_name, n, m, r, g, T.group_by, positions)
     achieved = alg_bytes / (dom_ms / 1e3) / 1e9 if alg_bytes else None
     per_kernel = {}
     for k, (tot, c) in kt.items():
         kms = tot / max(c, 1)
-        b, _ = kernel_alg_bytes(k, n, m, r, g, T.group_by)
+        b, _ = kernel_alg_bytes(k, n, m, r, g, T.group_by, positions)
         per_kernel[k] = {"ms": kms, "alg_gbs": (b / (kms / 1e3) / 1e9) if b else None}
     ctr = counters_for(dom_name, args.workload)
     valu = None
