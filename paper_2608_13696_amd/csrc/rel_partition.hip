@@ -78,6 +78,93 @@ __device__ __forceinline__ uint32_t key_hash(uint32_t sub, uint32_t mul, uint32_
   return (((uint32_t)key - sub) * mul) << sh;
 }
 
+// ---- narrow second-level rows --------------------------------------------------------------------------------------
+//
+// In the dense order the groupjoin needs of a fact row only its slot in the
+// unit (a function of the key), whether the key lies in the dim keys' range,
+// its price and its quantity. When the passing rows' prices and quantities
+// span few enough values, the second level writes each row as one 64-bit
+// word instead of 16 bytes: bits 0-10 the slot, bit 11 in-range, then the
+// quantity minus the smallest quantity (qb bits), then the price minus a
+// lower bound of the prices (the rest). Sums stay exact: price = bound +
+// field, added mod 2^64 like the 64-bit sums themselves. The bounds come from
+// 32-bit minima and maxima (cheap to reduce across a wave): of the
+// quantities, and of the prices' high words (price >> 32), so the price field
+// takes 32 bits plus those of the high words' spread. They are the
+// first-level scatter's per-wave values, combined by the second-level scan;
+// signed values are kept order-encoded (sign bit flipped) so that unsigned
+// atomics order them.
+constexpr uint32_t kSignFlip = 0x80000000u;
+constexpr int kRngWaves = 8;  // waves of a first-level scatter workgroup
+static_assert(kRngWaves == kSBlk / kWave, "one range entry per wave of a first-level scatter workgroup");
+constexpr uint32_t kNarrowSlotBits = 11;  // >= kJSlotBits
+constexpr uint32_t kNarrowFieldBits = 64 - kNarrowSlotBits - 1;
+__device__ __forceinline__ uint32_t order_enc(int32_t v) { return (uint32_t)v ^ kSignFlip; }
+__device__ __forceinline__ int32_t order_dec(uint32_t u) { return (int32_t)(u ^ kSignFlip); }
+__device__ __forceinline__ uint32_t bits_of(uint64_t x) { return x ? 64u - (uint32_t)__clzll((long long)x) : 0u; }
+
+struct Narrow {
+  uint32_t on;      // rows are 64-bit words
+  uint32_t qb;      // quantity field bits
+  int64_t pmin, qmin;
+};
+// rng: {min, max} of the order-encoded price high words, then of the
+// quantities. Prices lie in [hmin * 2^32, (hmax + 1) * 2^32), a span below
+// 2^(32 + bits(hmax - hmin)).
+__device__ __forceinline__ Narrow narrow_of(const KeyMap* km, const uint32_t* rng, uint32_t enabled) {
+  Narrow n{0u, 0u, 0, 0};
+  if (!enabled || !km->dense || rng[0] > rng[1]) return n;
+  const int32_t hmin = order_dec(rng[0]), hmax = order_dec(rng[1]);
+  n.pmin = (int64_t)hmin * 4294967296ll;
+  n.qmin = order_dec(rng[2]);
+  const uint32_t pb = 32u + bits_of((uint64_t)((int64_t)hmax - hmin));
+  n.qb = bits_of((uint64_t)((int64_t)order_dec(rng[3]) - n.qmin));
+  n.on = pb + n.qb <= kNarrowFieldBits;
+  return n;
+}
+
+// What the second-level scatter needs to write narrow rows.
+struct NarrowPack {
+  Narrow n;
+  uint32_t sub, mul, range, smask;
+};
+__device__ __forceinline__ NarrowPack narrow_pack(const KeyMap* km, const uint32_t* rng, uint32_t enabled) {
+  NarrowPack np{narrow_of(km, rng, enabled), 0u, 0u, 0u, 0u};
+  if (np.n.on) {
+    np.sub = km->sub;
+    np.mul = km->mul;
+    np.range = km->range;
+    np.smask = (1u << (km->slot_bits + km->merge)) - 1u;
+  }
+  return np;
+}
+
+// Minima (even entries) and maxima (odd entries) of four values over the wave
+// (every lane gets them) or over the workgroup (thread 0 gets them); every
+// lane or thread must call it.
+__device__ __forceinline__ void wave_minmax4(uint32_t (&v)[4]) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t u = (uint32_t)__shfl_xor((int)v[i], o, kWave);
+      v[i] = (i & 1) ? max(u, v[i]) : min(u, v[i]);
+    }
+  }
+}
+template <int NT>
+__device__ __forceinline__ void block_minmax4(uint32_t (&v)[4], uint32_t (*sm)[NT / kWave]) {
+  wave_minmax4(v);
+  if (lane_id() == 0)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sm[i][threadIdx.x / kWave] = v[i];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int w = 1; w < NT / kWave; ++w)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = (i & 1) ? max(sm[i][w], v[i]) : min(sm[i][w], v[i]);
+}
+
 // Bin of a key at a level: `shift` drops the low bits of the key's position
 // in the key order, `mask` keeps the level's bits.
 struct BinOf {
@@ -153,6 +240,9 @@ struct PartSide {
   uint32_t* hist1;   // [ntiles1][nb1]
   uint32_t* tot1;    // [nb1]
   uint32_t* pass1;   // fact only: bit r of word r / 32 set when row r passes the filter (the histogram writes it)
+  uint32_t* rng_part;  // fact only, nullable: per wave of a first-level tile, the passing rows' encoded ranges (narrow_of)
+  uint32_t* rng;       // fact only: those ranges over all tiles
+  uint32_t narrow;     // fact only: the second level may write narrow rows (GROUP BY fk)
   uint32_t* hist2;   // [max tiles2][nb2]
   uint32_t* pstart;  // [nb1 * nb2]
   uint32_t* pcount;  // [nb1 * nb2]
@@ -255,6 +345,7 @@ __global__ __launch_bounds__(kBlk) void k_p1_hist(PartSide s) {
     s.zero2[0] = 0;
     s.zero2[1] = 0;
   }
+  if (FACT && s.rng_part && blockIdx.x == 0 && threadIdx.x < 4) s.rng[threadIdx.x] = (threadIdx.x & 1) ? 0u : ~0u;
   for (uint32_t b = threadIdx.x; b < nb1; b += kBlk) h[b] = 0;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t r0 = tile * kTile1;
@@ -406,7 +497,7 @@ struct TileRows {
 template <bool FACT, bool PASS, int NT, int TILE>
 __device__ __forceinline__ void stage_and_write(Stage<FACT, TILE>& st, TileRows<FACT, PASS, TILE / NT>& r,
                                                 BinOf bin_of, uint32_t nb, bool with_val, int32_t* dkey,
-                                                int64_t* dprice, int32_t* dval, int8_t* dflag) {
+                                                int64_t* dprice, int32_t* dval, int8_t* dflag, const NarrowPack& np) {
   constexpr int R = TILE / NT;
   if (PASS) {
 #pragma unroll
@@ -461,6 +552,14 @@ __device__ __forceinline__ void stage_and_write(Stage<FACT, TILE>& st, TileRows<
   for (uint32_t j = threadIdx.x; j < total; j += NT) {
     const int2 kv = st.kv[j];
     const uint32_t pos = st.delta[bin_of(kv.x)] + j;
+    if (FACT && np.n.on) {  // one 64-bit word per row, in the price column's place
+      const uint32_t off = (uint32_t)kv.x - np.sub;
+      const uint64_t w = (uint64_t)((off * np.mul) & np.smask) | ((uint64_t)(off < np.range) << kNarrowSlotBits) |
+                         ((uint64_t)((int64_t)kv.y - np.n.qmin) << (kNarrowSlotBits + 1)) |
+                         (((uint64_t)(st.price[j] - np.n.pmin) << (kNarrowSlotBits + 1)) << np.n.qb);
+      reinterpret_cast<uint64_t*>(dprice)[pos] = w;
+      continue;
+    }
     dkey[pos] = kv.x;
     if (FACT) {
       dprice[pos] = st.price[j];
@@ -533,9 +632,34 @@ __global__ __launch_bounds__(kSBlk) void k_p1_scatter(PartSide s) {
   const uint32_t pbase = block_excl_scan<kSBlk>(threadIdx.x < nb1 ? s.tot1[threadIdx.x] : 0u, st.scr, &tot);
   if (threadIdx.x < kMaxBins) st.lcnt[threadIdx.x] = 0;
   if (threadIdx.x < nb1) st.gbase[threadIdx.x] = pbase + h;
+  // the tile's passing rows: ranges of price and quantity (narrow second-level
+  // rows), per thread here, per wave after the write-out
+  int32_t pmn = INT32_MAX, pmx = INT32_MIN, qmn = INT32_MAX, qmx = INT32_MIN;  // price high words, quantities
+  if constexpr (FACT) {
+    if (s.rng_part) {
+#pragma unroll
+      for (int k = 0; k < kR1; ++k)
+        if (((r.valid >> k) & 1u) && ((r.pass[k] >> (threadIdx.x & 31)) & 1u)) {
+          const int32_t ph = (int32_t)(r.price[k] >> 32);
+          pmn = min(pmn, ph);
+          pmx = max(pmx, ph);
+          qmn = min(qmn, r.val[k]);
+          qmx = max(qmx, r.val[k]);
+        }
+    }
+  }
   __syncthreads();
   stage_and_write<FACT, FACT, kSBlk, (int)kTile1>(st, r, bin_of, nb1, s.pkind != relh::PAY_NONE, s.key1,
-                                                  s.price1, FACT ? s.qty1 : s.pay1, FACT ? s.flag1 : nullptr);
+                                                  s.price1, FACT ? s.qty1 : s.pay1, FACT ? s.flag1 : nullptr,
+                                                  NarrowPack{});
+  if constexpr (FACT) {
+    if (s.rng_part) {
+      uint32_t v[4] = {order_enc(pmn), order_enc(pmx), order_enc(qmn), order_enc(qmx)};
+      wave_minmax4(v);
+      if (lane_id() == 0)
+        reinterpret_cast<uint4*>(s.rng_part)[(size_t)tile * kRngWaves + threadIdx.x / kWave] = make_uint4(v[0], v[1], v[2], v[3]);
+    }
+  }
 }
 
 // ---- second level ------------------------------------------------------------------------------------------------------
@@ -697,6 +821,26 @@ __global__ __launch_bounds__(kBlk) void k_p2_scan(PartSide s) {
     s.tdesc2[tb + k] = make_uint4(p, lo, lo + (uint32_t)kTile < end ? lo + (uint32_t)kTile : end, 0u);
   }
   if (p == 0 && threadIdx.x == 0) *s.ntiles2 = mp.ntiles;
+  if (s.rng_part) {
+    // the first-level tiles' ranges, workgroup p taking a 1 / gridDim share
+    __shared__ uint32_t s_rng[4][kBlk / kWave];
+    const int64_t T = (s.n + kTile1 - 1) / kTile1 * kRngWaves;  // one entry per wave of each first-level tile
+    uint32_t v[4] = {~0u, 0u, ~0u, 0u};
+    for (int64_t t = T * p / gridDim.x + threadIdx.x; t < T * (p + 1) / gridDim.x; t += kBlk) {
+      const uint4 u = reinterpret_cast<const uint4*>(s.rng_part)[t];
+      v[0] = min(v[0], u.x);
+      v[1] = max(v[1], u.y);
+      v[2] = min(v[2], u.z);
+      v[3] = max(v[3], u.w);
+    }
+    block_minmax4<kBlk>(v, s_rng);
+    if (threadIdx.x == 0 && v[0] <= v[1]) {
+      atomicMin(&s.rng[0], v[0]);
+      atomicMax(&s.rng[1], v[1]);
+      atomicMin(&s.rng[2], v[2]);
+      atomicMax(&s.rng[3], v[3]);
+    }
+  }
 }
 
 constexpr int kR2 = (int)(kTile / kSBlk);  // rows per thread at the second level
@@ -755,8 +899,9 @@ __global__ __launch_bounds__(kSBlk) void k_p2_scatter(PartSide s) {
   if (threadIdx.x < kMaxBins) st.lcnt[threadIdx.x] = 0;
   if (threadIdx.x < nb2) st.gbase[threadIdx.x] = s.pstart[x.p * nb2 + threadIdx.x] + s.hist2[(size_t)t * nb2 + threadIdx.x];
   __syncthreads();
+  const NarrowPack np = FACT ? narrow_pack(s.km, s.rng, s.narrow) : NarrowPack{};
   stage_and_write<FACT, false, kSBlk, (int)kTile>(st, r, bin_of, nb2, pay, s.key2, s.price2, FACT ? s.qty2 : s.pay2,
-                                                  FACT ? s.flag2 : nullptr);
+                                                  FACT ? s.flag2 : nullptr, np);
 }
 
 // ---- dense order: the dim side's presence bitmap ---------------------------------------------------------------------
@@ -1053,6 +1198,9 @@ struct JoinArgs {
   const KeyMap* km;
   const uint32_t* bitmap;  // dense order: the dim keys' presence bits over all key positions
   uint32_t zero;  // 0 at run time; see take_ticket
+  const uint32_t* rng;    // the fact rows' price and quantity ranges (narrow_of)
+  uint32_t narrow;        // narrow rows allowed
+  const uint64_t* fpack;  // narrow rows (in the second-level price column's place)
 };
 
 constexpr uint64_t kLdsEmpty = ~0ull;
@@ -1106,6 +1254,15 @@ __device__ __forceinline__ void load_keys(const JoinArgs& a, uint32_t i0, uint32
   for (int k = 0; k < kGR; ++k) {
     const uint32_t i = i0 + k * kJBlock;
     r.key[k] = a.fkey[i < fhi ? i : fhi - 1];
+  }
+}
+
+// Narrow rows: one 64-bit word per row (in r.sp).
+__device__ __forceinline__ void load_packed(const JoinArgs& a, uint32_t i0, uint32_t fhi, PayRegs& r) {
+#pragma unroll
+  for (int k = 0; k < kGR; ++k) {
+    const uint32_t i = i0 + k * kJBlock;
+    r.sp[k] = a.fpack[i < fhi ? i : fhi - 1];
   }
 }
 
@@ -1523,6 +1680,8 @@ __device__ __forceinline__ void groupjoin_dense(const JoinArgs& a, GroupjoinLds&
   const uint32_t lmask = L >= 32 ? ~0u : (1u << L) - 1u;
   const uint32_t nslots = 1u << ubits, smask = nslots - 1u;
   const uint32_t nw = ubits >= 5 ? nslots >> 5 : 1u;  // bitmap words of a unit
+  const Narrow nar = narrow_of(a.km, a.rng, a.narrow);
+  const uint64_t qmask = (1ull << nar.qb) - 1ull;  // qb <= kNarrowFieldBits < 64
   uint32_t* const cnt = sh.t.d.cnt;
   uint32_t* const own = sh.t.d.own;
   uint64_t* const tsp = sh.tsp;
@@ -1561,10 +1720,17 @@ __device__ __forceinline__ void groupjoin_dense(const JoinArgs& a, GroupjoinLds&
   KeyRegs ck, nk;
   PayRegs pay, npay;
   // a unit's bitmap words and its first step of fact rows (d.x is the unit's index)
+  auto load_rows = [&](uint32_t i0, uint32_t hi) {
+    if (nar.on) {
+      load_packed(a, i0, hi, npay);
+    } else {
+      load_keys(a, i0, hi, nk);
+      load_payload(a, i0, hi, npay);
+    }
+  };
   auto prefetch = [&](uint4 x) {
     if (tid < nw) own_w = a.bitmap[((x.x << ubits) >> 5) + tid];
-    load_keys(a, x.z + tid, x.w, nk);
-    load_payload(a, x.z + tid, x.w, npay);
+    load_rows(x.z + tid, x.w);
   };
   if (u < n_units) prefetch(d);
   while (u < n_units) {
@@ -1590,15 +1756,25 @@ __device__ __forceinline__ void groupjoin_dense(const JoinArgs& a, GroupjoinLds&
       const uint32_t i0 = flo + it * (kGR * kJBlock) + tid;
       ck = nk;
       pay = npay;
-      if (it + 1 < iters) {  // the next step's rows travel during this step's updates
-        load_keys(a, i0 + kGR * kJBlock, fhi, nk);
-        load_payload(a, i0 + kGR * kJBlock, fhi, npay);
-      }
+      if (it + 1 < iters) load_rows(i0 + kGR * kJBlock, fhi);  // the next step's rows travel during this step's updates
 #pragma unroll
       for (int k = 0; k < kGR; ++k) {
-        const uint32_t off = (uint32_t)ck.key[k] - sub;
-        bool found = i0 + k * kJBlock < fhi && off < range;
-        const int slot = (int)((off * mul) & smask);
+        bool found;
+        int slot;
+        uint64_t pv, qv;  // price and quantity (as 64-bit two's complement)
+        if (nar.on) {
+          const uint64_t w = pay.sp[k], f = w >> (kNarrowSlotBits + 1);
+          found = i0 + k * kJBlock < fhi && ((w >> kNarrowSlotBits) & 1u) != 0;
+          slot = (int)(w & smask);
+          pv = (uint64_t)nar.pmin + (f >> nar.qb);
+          qv = (uint64_t)nar.qmin + (f & qmask);
+        } else {
+          const uint32_t off = (uint32_t)ck.key[k] - sub;
+          found = i0 + k * kJBlock < fhi && off < range;
+          slot = (int)((off * mul) & smask);
+          pv = pay.sp[k];
+          qv = (uint64_t)(int64_t)pay.qty[k];
+        }
         // hot keys (split sub-units): lanes of the wave on one slot are summed first
         if (combine) {
           const uint64_t act = wave_ballot(found);
@@ -1608,8 +1784,8 @@ __device__ __forceinline__ void groupjoin_dense(const JoinArgs& a, GroupjoinLds&
           const uint64_t same = wave_ballot(found && slot == s0);
           if (__popcll(same) >= kCombineMin) {
             const bool mine = found && slot == s0;
-            const uint64_t tsum_p = wave_sum_u64(mine ? pay.sp[k] : 0);
-            const uint64_t tsum_q = wave_sum_u64(mine ? (uint64_t)(int64_t)pay.qty[k] : 0);
+            const uint64_t tsum_p = wave_sum_u64(mine ? pv : 0);
+            const uint64_t tsum_q = wave_sum_u64(mine ? qv : 0);
             if ((int)lane == first) {
               atomicAdd((unsigned long long*)&tsp[s0], (unsigned long long)tsum_p);
               atomicAdd((unsigned long long*)&tsq[s0], (unsigned long long)tsum_q);
@@ -1619,8 +1795,8 @@ __device__ __forceinline__ void groupjoin_dense(const JoinArgs& a, GroupjoinLds&
           }
         }
         if (found) {
-          atomicAdd((unsigned long long*)&tsp[slot], (unsigned long long)pay.sp[k]);
-          atomicAdd((unsigned long long*)&tsq[slot], (unsigned long long)(int64_t)pay.qty[k]);
+          atomicAdd((unsigned long long*)&tsp[slot], (unsigned long long)pv);
+          atomicAdd((unsigned long long*)&tsq[slot], (unsigned long long)qv);
           atomicAdd(&cnt[slot], 1u);
         }
       }
@@ -2302,7 +2478,8 @@ rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim
   const size_t book = ((size_t)fnt1 * nb1 + (size_t)dnt1 * nb1 + (size_t)fnt2 * nb2 + (size_t)dnt2 * nb2 + 2 * nb1 +
                        5 * (size_t)nparts + ((size_t)nparts / kUBlk + 1) * kClasses) * 4 +
                       (size_t)max_units * (sizeof(uint4) + sizeof(uint2)) + (size_t)(fnt2 + dnt2) * sizeof(uint4) +
-                      sizeof(KeyMap) + 8 * (size_t)kKeyMinMaxParts + ((size_t)n / 64 + 1) * 8 + 64 * 256;
+                      sizeof(KeyMap) + 8 * (size_t)kKeyMinMaxParts + ((size_t)n / 64 + 1) * 8 + ((size_t)fnt1 * kRngWaves + 1) * 16 +
+                      64 * 256;
   TRY(scratch(ctx, SCR_PART_D, book, &pd));
   // split-chunk accumulators and their done counters: zero when allocated, and
   // left zero by every call (the last sub-unit of a chunk clears what it emits)
@@ -2335,6 +2512,10 @@ rel_status partition_both(rel_ctx* ctx, const rel_fact* fact, const rel_dim* dim
   F.flag2 = with_flag ? cb.take<int8_t>(n) : nullptr;
   F.hist1 = cd.take<uint32_t>((size_t)fnt1 * nb1);
   F.pass1 = cd.take<uint32_t>(((size_t)n / 64 + 1) * 2);
+  // GROUP BY fk: the passing rows' price and quantity ranges, for narrow second-level rows
+  F.rng_part = dense_ok ? cd.take<uint32_t>((size_t)fnt1 * kRngWaves * 4) : nullptr;
+  F.rng = dense_ok ? cd.take<uint32_t>(4) : nullptr;
+  F.narrow = dense_ok ? 1u : 0u;
   F.tot1 = cd.take<uint32_t>(nb1);
   F.hist2 = cd.take<uint32_t>((size_t)fnt2 * nb2);
   F.pstart = cd.take<uint32_t>(nparts);
@@ -2475,6 +2656,9 @@ rel_status partitioned_groupjoin(rel_ctx* ctx, const rel_fact* fact, const rel_d
   a.d_n = out->d_n_groups;
   a.km = P.F.km;
   a.bitmap = P.bitmap;
+  a.rng = P.F.rng;
+  a.narrow = P.F.narrow;
+  a.fpack = reinterpret_cast<const uint64_t*>(P.F.price2);
   const unsigned grid = (unsigned)ctx->num_cus * 3;  // 48 KB of LDS each: three per CU
   hipLaunchKernelGGL(k_part_groupjoin, dim3(grid), dim3(kJBlock), 0, ctx->stream, a);
   REL_LAUNCH_CHECK(ctx, "part_groupjoin");

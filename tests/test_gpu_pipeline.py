@@ -328,6 +328,33 @@ def test_partitioned_extreme_quantities(ctx, n, m, zipf):
     assert st["join_placement"] == "partitioned"
 
 
+@pytest.mark.parametrize("case", ["signed_small", "high_words", "one_value", "wide_price", "wide_qty"])
+def test_partitioned_narrow_row_ranges(ctx, case):
+    # In the dense key order the second level writes each fact row as one
+    # 64-bit word (slot, in-range bit, quantity and price offsets) when the
+    # passing rows' quantities and prices span few enough values, and 16 bytes
+    # otherwise: ranges around zero, far from it, a single value, and prices
+    # or quantities too wide for the word (the 16-byte rows).
+    n, m = 1_500_000, 200_000
+    T = datagen.make_tables(n, m, 93, day_lt=1500, group_by="fk", fk_zipf=0.9)
+    rng = np.random.default_rng(94)
+    if case == "signed_small":
+        T.price_cents = rng.integers(-5_000_000, 5_000_000, size=n, dtype=np.int64)
+        T.qty = rng.integers(-100, 101, size=n).astype(np.int32)
+    elif case == "high_words":
+        T.price_cents = rng.integers(2 ** 40 - 10 ** 6, 2 ** 40 + 10 ** 6, size=n, dtype=np.int64)
+        T.qty = rng.integers(-(2 ** 31), -(2 ** 31) + 1000, size=n).astype(np.int32)
+    elif case == "one_value":
+        T.price_cents = np.full(n, -123456789, np.int64)
+        T.qty = np.full(n, 7, np.int32)
+    elif case == "wide_price":
+        T.price_cents = rng.integers(-(2 ** 62), 2 ** 62, size=n, dtype=np.int64)
+    else:
+        T.qty = rng.integers(-(2 ** 31), 2 ** 31, size=n, dtype=np.int64).astype(np.int32)
+    st = run_both(ctx, T, plan=_partitioned(), repeats=2)
+    assert st["join_placement"] == "partitioned"
+
+
 @pytest.mark.parametrize("layout", ["from_int32_min", "to_int32_max", "stride3", "stride40"])
 def test_partitioned_key_layouts(ctx, layout):
     # The partitions follow the dense key order when the dim keys span at most
