@@ -58,12 +58,31 @@ def dense_positions(pk) -> int | None:
     return 1 << lb if lb - pb <= 11 else None
 
 
-def kernel_alg_bytes(kernel: str, n: int, m: int, r: int, g: int, group_by: str, positions: int | None = None):
+def narrow_rows(T, positions: int | None) -> bool:
+    """Whether the partitioned groupjoin's second level writes each passing
+    fact row as one 64-bit word: in the dense key order, when the bits of the
+    passing rows' quantity range plus 32 plus those of their prices' high-word
+    range fit in 52 (the library's rule, from the same bounds)."""
+    if not positions:
+        return False
+    keep = T.day < T.day_lt
+    if not keep.any():
+        return False
+    hi = T.price_cents[keep] >> 32
+    q = T.qty[keep].astype("int64")
+    pb = 32 + int(hi.max() - hi.min()).bit_length()
+    qb = int(q.max() - q.min()).bit_length()
+    return pb + qb <= 52
+
+
+def kernel_alg_bytes(kernel: str, n: int, m: int, r: int, g: int, group_by: str, positions: int | None = None,
+                     narrow: bool = False):
     """Algorithmic bytes of one launch of `kernel`: each input byte the kernel
     must read once plus each output byte it must write once (no table or
     re-read traffic). n fact rows, m dim rows, r rows passing the predicate,
     g groups; positions: the dense key order's key positions (None: hash
-    order). Returns (bytes, description) or (None, None)."""
+    order); narrow: second-level fact rows of 8 B. Returns (bytes,
+    description) or (None, None)."""
     fb, db = FACT_BYTES[group_by], DIM_BYTES[group_by]
     # partitioned rows: fact 16 B (+1 flag byte when the key needs it); dim key
     # 4 B (+4 B payload when the group key comes from the dim side)
@@ -79,13 +98,15 @@ def kernel_alg_bytes(kernel: str, n: int, m: int, r: int, g: int, group_by: str,
         "fact_p1_scatter": ((fb - 4) * n + n / 8 + pf * r,
                             f"{fb - 4} B per fact row read (all but day) + its pass bit + {pf} B per passing row written"),
         "fact_p2_hist": (4 * r, "4 B per passing row (fk)"),
-        "fact_p2_scatter": (2 * pf * r, f"{pf} B per passing row read + {pf} B written"),
+        "fact_p2_scatter": ((pf + 8) * r, f"{pf} B per passing row read + 8 B written (one word per row)") if narrow
+                           else (2 * pf * r, f"{pf} B per passing row read + {pf} B written"),
         "dim_p1_hist": (4 * m, "4 B per dim row"),
         "dim_p1_scatter": ((db + pd) * m, f"{db} B per dim row read + {pd} B written"),
         "dim_p2_hist": (4 * m, "4 B per dim row"),
         "dim_p2_scatter": (2 * pd * m, f"{pd} B per dim row read + {pd} B written"),
-        "part_groupjoin": ((PART_ROW_BYTES * r + positions / 8 + OUT_BYTES_PER_GROUP * g,
-                            "16 B per passing row + 1 bit per key position (presence bitmap) + 32 B per group")
+        "part_groupjoin": (((8 if narrow else PART_ROW_BYTES) * r + positions / 8 + OUT_BYTES_PER_GROUP * g,
+                            f"{8 if narrow else PART_ROW_BYTES} B per passing row + 1 bit per key position "
+                            "(presence bitmap) + 32 B per group")
                            if positions else
                            (PART_ROW_BYTES * r + 4 * m + OUT_BYTES_PER_GROUP * g,
                             "16 B per passing row + 4 B per dim key + 32 B per group")),
@@ -810,12 +831,13 @@ def main() -> int:
     dom_ms = dom_tot / max(dom_cnt, 1)
     r, g = st["rows_passed"], st["groups"]
     positions = dense_positions(T.pk) if st.get("join_placement") == "partitioned" and T.group_by == "fk" else None
-    alg_bytes, unit_desc = kernel_alg_bytes(dom_name, n, m, r, g, T.group_by, positions)
+    narrow = narrow_rows(T, positions)
+    alg_bytes, unit_desc = kernel_alg_bytes(dom_name, n, m, r, g, T.group_by, positions, narrow)
     achieved = alg_bytes / (dom_ms / 1e3) / 1e9 if alg_bytes else None
     per_kernel = {}
     for k, (tot, c) in kt.items():
         kms = tot / max(c, 1)
-        b, _ = kernel_alg_bytes(k, n, m, r, g, T.group_by, positions)
+        b, _ = kernel_alg_bytes(k, n, m, r, g, T.group_by, positions, narrow)
         per_kernel[k] = {"ms": kms, "alg_gbs": (b / (kms / 1e3) / 1e9) if b else None}
     ctr = counters_for(dom_name, args.workload)
     valu = None
